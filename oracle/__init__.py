@@ -1,0 +1,207 @@
+"""FP64 CPU oracle for the wide reduction-reuse row operators.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``; never by the product package.  It
+shares no code with the HIP path.  The arithmetic lives in ``credit_oracle.c``
+(plain double-precision definitions, compiled with gcc); this module only
+marshals numpy arrays and decodes the low-precision I/O formats exactly.
+
+Operators (each is the plain definition; the method of the CREDIT paper reaches
+it exactly up to rounding order, Sec. III-B, Eq. (1)):
+
+* ``softmax_fwd``   y = exp(x - max x) / sum exp(x - max x)
+* ``softmax_bwd``   dx = y * (dy - sum dy*y)
+* ``layernorm_fwd`` y = (x - mean) * rstd * gamma + beta, biased variance
+* ``layernorm_bwd`` dx, dgamma, dbeta with statistics recomputed in FP64
+* ``rmsnorm_fwd`` / ``rmsnorm_bwd``
+* codecs: bfloat16 and OCP FP8 e4m3fn, decode and round-to-nearest-even encode
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "credit_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.c_int64
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2 -fopenmp).  Returns the library path."""
+    if force or not os.path.exists(_LIB_PATH) or (
+        os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)
+    ):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    sig = {
+        "oracle_num_threads": ([], ctypes.c_int),
+        "oracle_set_num_threads": ([ctypes.c_int], None),
+        "oracle_sum": ([P, _I64], ctypes.c_double),
+        "oracle_decode_bf16": ([P, P, _I64], None),
+        "oracle_encode_bf16": ([P, P, _I64], None),
+        "oracle_decode_e4m3": ([P, P, _I64], None),
+        "oracle_encode_e4m3": ([P, P, _I64], None),
+        "oracle_e4m3_step": ([ctypes.c_double], ctypes.c_double),
+        "oracle_softmax_fwd": ([_I64, _I64, P, P], None),
+        "oracle_softmax_bwd": ([_I64, _I64, P, P, P], None),
+        "oracle_layernorm_fwd": ([_I64, _I64, P, P, P, ctypes.c_double, P, P, P], None),
+        "oracle_layernorm_bwd": ([_I64, _I64, P, P, P, ctypes.c_double, P, P, P, P], None),
+        "oracle_rmsnorm_fwd": ([_I64, _I64, P, P, ctypes.c_double, P, P], None),
+        "oracle_rmsnorm_bwd": ([_I64, _I64, P, P, P, ctypes.c_double, P, P, P], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    _load().oracle_set_num_threads(int(n))
+
+
+def fsum(v) -> float:
+    """Neumaier-compensated sum of a 1-D array."""
+    v = _f64(v).ravel()
+    return _load().oracle_sum(_p(v), v.size)
+
+
+# ------------------------------------------------------------------ codecs
+def decode_bf16(bits) -> np.ndarray:
+    b = np.ascontiguousarray(bits, dtype=np.uint16)
+    out = np.empty(b.shape, np.float64)
+    _load().oracle_decode_bf16(_p(b), _p(out), b.size)
+    return out
+
+
+def encode_bf16(v) -> np.ndarray:
+    v = _f64(v)
+    out = np.empty(v.shape, np.uint16)
+    _load().oracle_encode_bf16(_p(v), _p(out), v.size)
+    return out
+
+
+def decode_e4m3(codes) -> np.ndarray:
+    c = np.ascontiguousarray(codes, dtype=np.uint8)
+    out = np.empty(c.shape, np.float64)
+    _load().oracle_decode_e4m3(_p(c), _p(out), c.size)
+    return out
+
+
+def encode_e4m3(v) -> np.ndarray:
+    v = _f64(v)
+    out = np.empty(v.shape, np.uint8)
+    _load().oracle_encode_e4m3(_p(v), _p(out), v.size)
+    return out
+
+
+def e4m3_step(v: float) -> float:
+    return _load().oracle_e4m3_step(float(v))
+
+
+def decode(raw, dtype: str, row_scale=None) -> np.ndarray:
+    """Exact FP64 values of an I/O tensor.  dtype in {"f32", "bf16", "fp8"};
+    FP8 codes are multiplied by their per-row FP32 scale (exact in FP64)."""
+    if dtype == "f32":
+        return np.asarray(raw, dtype=np.float32).astype(np.float64)
+    if dtype == "bf16":
+        return decode_bf16(np.asarray(raw).view(np.uint16))
+    if dtype == "fp8":
+        v = decode_e4m3(np.asarray(raw).view(np.uint8))
+        s = np.asarray(row_scale, dtype=np.float32).astype(np.float64)
+        return v * s.reshape(-1, 1)
+    raise ValueError(dtype)
+
+
+# ---------------------------------------------------------------- operators
+def softmax_fwd(x) -> np.ndarray:
+    x = _f64(x)
+    M, N = x.shape
+    y = np.empty_like(x)
+    _load().oracle_softmax_fwd(M, N, _p(x), _p(y))
+    return y
+
+
+def softmax_bwd(y, dy) -> np.ndarray:
+    y, dy = _f64(y), _f64(dy)
+    M, N = y.shape
+    dx = np.empty_like(y)
+    _load().oracle_softmax_bwd(M, N, _p(y), _p(dy), _p(dx))
+    return dx
+
+
+def layernorm_fwd(x, gamma, beta, eps: float):
+    """Returns (y, mean, rstd)."""
+    x, g, b = _f64(x), _f64(gamma), _f64(beta)
+    M, N = x.shape
+    y = np.empty_like(x)
+    mu = np.empty(M)
+    rs = np.empty(M)
+    _load().oracle_layernorm_fwd(M, N, _p(x), _p(g), _p(b), float(eps), _p(y), _p(mu), _p(rs))
+    return y, mu, rs
+
+
+def layernorm_bwd(x, dy, gamma, eps: float):
+    """Returns (dx, dgamma, dbeta); statistics recomputed from x in FP64."""
+    x, dy, g = _f64(x), _f64(dy), _f64(gamma)
+    M, N = x.shape
+    dx = np.empty_like(x)
+    dg = np.empty(N)
+    db = np.empty(N)
+    ws = np.empty_like(x)
+    _load().oracle_layernorm_bwd(M, N, _p(x), _p(dy), _p(g), float(eps), _p(dx), _p(dg), _p(db), _p(ws))
+    return dx, dg, db
+
+
+def rmsnorm_fwd(x, gamma, eps: float):
+    """Returns (y, rstd)."""
+    x, g = _f64(x), _f64(gamma)
+    M, N = x.shape
+    y = np.empty_like(x)
+    rs = np.empty(M)
+    _load().oracle_rmsnorm_fwd(M, N, _p(x), _p(g), float(eps), _p(y), _p(rs))
+    return y, rs
+
+
+def rmsnorm_bwd(x, dy, gamma, eps: float):
+    """Returns (dx, dgamma); statistics recomputed from x in FP64."""
+    x, dy, g = _f64(x), _f64(dy), _f64(gamma)
+    M, N = x.shape
+    dx = np.empty_like(x)
+    dg = np.empty(N)
+    ws = np.empty_like(x)
+    _load().oracle_rmsnorm_bwd(M, N, _p(x), _p(dy), _p(g), float(eps), _p(dx), _p(dg), _p(ws))
+    return dx, dg

@@ -1,0 +1,324 @@
+/*
+ * credit_oracle.c -- FP64 CPU oracle for the wide reduction-reuse row operators.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file.  It is used by tests/, by the smoke check and by the
+ * benchmark's CPU-baseline leg, and by nothing else.  It shares no code,
+ * header, table or constant with the GPU path.
+ *
+ * Every operator is written as its plain definition in double precision.  The
+ * method under test (the reduction-reuse class of the CREDIT paper, Sec. III-B,
+ * Eq. (1)) reaches these definitions exactly up to rounding order: each row is
+ * reduced to a few scalar statistics r, then every element is reused to
+ * produce y_i = h(x_i, r).  The oracle does no slicing, no blocking and no
+ * fusion: it reduces a whole row with a compensated (Neumaier) sum and then
+ * applies h.  Rows are independent, so rows are spread over OpenMP threads;
+ * that changes nothing in any row's arithmetic.
+ *
+ * Inputs are already-decoded double arrays (row-major, contiguous, M x N).
+ * The low-precision codecs below (bfloat16, OCP FP8 e4m3fn) are provided so
+ * the tests can decode exactly what the GPU consumed and can locate the
+ * rounding grid of a reference value.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------------------------------------------------------- helpers */
+
+/* Neumaier-compensated sum of n doubles spaced by `stride`. */
+static double csum(const double *v, int64_t n, int64_t stride)
+{
+    double s = 0.0, c = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double a = v[i * stride];
+        double t = s + a;
+        if (fabs(s) >= fabs(a))
+            c += (s - t) + a;
+        else
+            c += (a - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+/* Compensated accumulator used where the summand is formed on the fly. */
+typedef struct { double s, c; } acc_t;
+static inline void acc_add(acc_t *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+static inline double acc_get(const acc_t *a) { return a->s + a->c; }
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+double oracle_sum(const double *v, int64_t n) { return csum(v, n, 1); }
+
+/* ------------------------------------------------------------- the codecs */
+
+/* bfloat16: 1 sign, 8 exponent, 7 fraction bits; the upper half of an IEEE
+ * binary32.  Decoding is exact. */
+void oracle_decode_bf16(const uint16_t *in, double *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t u = (uint32_t)in[i] << 16;
+        float f;
+        memcpy(&f, &u, 4);
+        out[i] = (double)f;
+    }
+}
+
+/* Round a double to the nearest bfloat16, ties to even, directly from the
+ * double value (no intermediate binary32 rounding).  Overflow gives +-inf,
+ * NaN gives the canonical quiet NaN 0x7FC0. */
+static uint16_t bf16_from_double(double d)
+{
+    if (isnan(d)) return 0x7FC0;
+    uint16_t sign = signbit(d) ? 0x8000 : 0;
+    double a = fabs(d);
+    if (a == 0.0) return sign;
+    if (isinf(a)) return sign | 0x7F80;
+    int e;
+    frexp(a, &e);           /* a = f * 2^e, f in [0.5, 1)  => floor(log2 a) = e-1 */
+    int lg = e - 1;
+    if (lg < -126) lg = -126;               /* subnormal range keeps a fixed spacing */
+    double ulp = ldexp(1.0, lg - 7);        /* 8 significant bits */
+    double r = rint(a / ulp);               /* default mode: nearest, ties to even */
+    double v = r * ulp;
+    if (v >= ldexp(1.0, 128)) return sign | 0x7F80;
+    float f = (float)v;                     /* exact: v lies on the bfloat16 grid */
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return sign | (uint16_t)(u >> 16);
+}
+
+void oracle_encode_bf16(const double *in, uint16_t *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = bf16_from_double(in[i]);
+}
+
+/* OCP FP8 e4m3fn: 1 sign, 4 exponent (bias 7), 3 fraction bits; no infinity;
+ * S.1111.111 is NaN; largest finite 448; smallest subnormal 2^-9. */
+static double e4m3_value(uint8_t b)
+{
+    int s = b >> 7, E = (b >> 3) & 0xF, F = b & 7;
+    double v;
+    if (E == 15 && F == 7) return NAN;
+    if (E == 0)
+        v = ldexp((double)F, -9);
+    else
+        v = ldexp(1.0 + F / 8.0, E - 7);
+    return s ? -v : v;
+}
+
+void oracle_decode_e4m3(const uint8_t *in, double *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = e4m3_value(in[i]);
+}
+
+/* Round a double to e4m3fn, ties to even, saturating to +-448 (values whose
+ * rounded magnitude would exceed 448 become 448).  NaN maps to 0x7F. */
+static uint8_t e4m3_from_double(double d)
+{
+    if (isnan(d)) return 0x7F;
+    uint8_t sign = signbit(d) ? 0x80 : 0;
+    double a = fabs(d);
+    if (a == 0.0) return sign;
+    if (a >= 448.0) return sign | 0x7E;
+    int e;
+    frexp(a, &e);
+    int lg = e - 1;
+    if (lg < -6) lg = -6;                   /* below 2^-6 the spacing is 2^-9 */
+    double ulp = ldexp(1.0, lg - 3);        /* 4 significant bits */
+    double v = rint(a / ulp) * ulp;
+    if (v > 448.0) v = 448.0;
+    if (v == 0.0) return sign;
+    if (v < ldexp(1.0, -6))                 /* subnormal: v = F * 2^-9 */
+        return sign | (uint8_t)(v * 512.0);
+    frexp(v, &e);
+    int E = (e - 1) + 7;
+    int F = (int)(ldexp(v, -(e - 1)) * 8.0 - 8.0);
+    return sign | (uint8_t)((E << 3) | F);
+}
+
+void oracle_encode_e4m3(const double *in, uint8_t *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = e4m3_from_double(in[i]);
+}
+
+/* Spacing of the e4m3 grid at magnitude v (the size of one step). */
+double oracle_e4m3_step(double v)
+{
+    double a = fabs(v);
+    if (a < ldexp(1.0, -6)) return ldexp(1.0, -9);
+    int e;
+    frexp(a, &e);
+    return ldexp(1.0, (e - 1) - 3);
+}
+
+/* ---------------------------------------------------------------- softmax */
+
+/* y_i = exp(x_i - max_j x_j) / sum_j exp(x_j - max_j x_j), per row.
+ * Statistics: r = (max, sum of shifted exponentials); h = exp(x - max) / sum. */
+void oracle_softmax_fwd(int64_t M, int64_t N, const double *x, double *y)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m) {
+        const double *xr = x + m * N;
+        double *yr = y + m * N;
+        double mx = -INFINITY;
+        for (int64_t i = 0; i < N; ++i)
+            if (xr[i] > mx) mx = xr[i];
+        acc_t s = {0, 0};
+        for (int64_t i = 0; i < N; ++i) acc_add(&s, exp(xr[i] - mx));
+        double sum = acc_get(&s);
+        for (int64_t i = 0; i < N; ++i) yr[i] = exp(xr[i] - mx) / sum;
+    }
+}
+
+/* dx_i = y_i * (dy_i - sum_j dy_j y_j), per row, for the given y. */
+void oracle_softmax_bwd(int64_t M, int64_t N, const double *y, const double *dy, double *dx)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m) {
+        const double *yr = y + m * N, *gr = dy + m * N;
+        double *dr = dx + m * N;
+        acc_t c = {0, 0};
+        for (int64_t i = 0; i < N; ++i) acc_add(&c, gr[i] * yr[i]);
+        double cs = acc_get(&c);
+        for (int64_t i = 0; i < N; ++i) dr[i] = yr[i] * (gr[i] - cs);
+    }
+}
+
+/* --------------------------------------------------------------- LayerNorm */
+
+/* mu = mean(x); var = mean((x - mu)^2) (biased); rstd = 1/sqrt(var + eps);
+ * y = (x - mu) * rstd * gamma + beta.  mean/rstd outputs may be NULL. */
+void oracle_layernorm_fwd(int64_t M, int64_t N, const double *x, const double *gamma,
+                          const double *beta, double eps, double *y, double *mean, double *rstd)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m) {
+        const double *xr = x + m * N;
+        double *yr = y + m * N;
+        double mu = csum(xr, N, 1) / (double)N;
+        acc_t v = {0, 0};
+        for (int64_t i = 0; i < N; ++i) acc_add(&v, (xr[i] - mu) * (xr[i] - mu));
+        double var = acc_get(&v) / (double)N;
+        double rs = 1.0 / sqrt(var + eps);
+        for (int64_t i = 0; i < N; ++i) yr[i] = (xr[i] - mu) * rs * gamma[i] + beta[i];
+        if (mean) mean[m] = mu;
+        if (rstd) rstd[m] = rs;
+    }
+}
+
+/* Column sums dgamma_j = sum_m a[m, j] * b[m, j] (b == NULL: sum_m a[m, j]),
+ * where a and b are M x N; compensated per column. */
+static void column_sums(int64_t M, int64_t N, const double *a, const double *b, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < N; ++j) {
+        acc_t s = {0, 0};
+        for (int64_t m = 0; m < M; ++m)
+            acc_add(&s, b ? a[m * N + j] * b[m * N + j] : a[m * N + j]);
+        out[j] = acc_get(&s);
+    }
+}
+
+/* LayerNorm backward with statistics recomputed from x in FP64:
+ * xhat = (x - mu) * rstd; g = dy * gamma;
+ * dx = rstd * (g - mean(g) - xhat * mean(g * xhat));
+ * dgamma_j = sum_m dy * xhat; dbeta_j = sum_m dy.  `xhat_ws` is M x N scratch. */
+void oracle_layernorm_bwd(int64_t M, int64_t N, const double *x, const double *dy,
+                          const double *gamma, double eps, double *dx, double *dgamma,
+                          double *dbeta, double *xhat_ws)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m) {
+        const double *xr = x + m * N, *gr = dy + m * N;
+        double *dr = dx + m * N, *hr = xhat_ws + m * N;
+        double mu = csum(xr, N, 1) / (double)N;
+        acc_t v = {0, 0};
+        for (int64_t i = 0; i < N; ++i) acc_add(&v, (xr[i] - mu) * (xr[i] - mu));
+        double rs = 1.0 / sqrt(acc_get(&v) / (double)N + eps);
+        acc_t c1 = {0, 0}, c2 = {0, 0};
+        for (int64_t i = 0; i < N; ++i) {
+            hr[i] = (xr[i] - mu) * rs;
+            double g = gr[i] * gamma[i];
+            acc_add(&c1, g);
+            acc_add(&c2, g * hr[i]);
+        }
+        double m1 = acc_get(&c1) / (double)N, m2 = acc_get(&c2) / (double)N;
+        for (int64_t i = 0; i < N; ++i) dr[i] = rs * (gr[i] * gamma[i] - m1 - hr[i] * m2);
+    }
+    if (dgamma) column_sums(M, N, dy, xhat_ws, dgamma);
+    if (dbeta) column_sums(M, N, dy, NULL, dbeta);
+}
+
+/* ----------------------------------------------------------------- RMSNorm */
+
+/* rstd = 1/sqrt(mean(x^2) + eps); y = x * rstd * gamma.  rstd may be NULL. */
+void oracle_rmsnorm_fwd(int64_t M, int64_t N, const double *x, const double *gamma,
+                        double eps, double *y, double *rstd)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m) {
+        const double *xr = x + m * N;
+        double *yr = y + m * N;
+        acc_t s = {0, 0};
+        for (int64_t i = 0; i < N; ++i) acc_add(&s, xr[i] * xr[i]);
+        double rs = 1.0 / sqrt(acc_get(&s) / (double)N + eps);
+        for (int64_t i = 0; i < N; ++i) yr[i] = xr[i] * rs * gamma[i];
+        if (rstd) rstd[m] = rs;
+    }
+}
+
+/* RMSNorm backward, statistics recomputed in FP64:
+ * xhat = x * rstd; g = dy * gamma; dx = rstd * (g - xhat * mean(g * xhat));
+ * dgamma_j = sum_m dy * xhat.  `xhat_ws` is M x N scratch. */
+void oracle_rmsnorm_bwd(int64_t M, int64_t N, const double *x, const double *dy,
+                        const double *gamma, double eps, double *dx, double *dgamma,
+                        double *xhat_ws)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m) {
+        const double *xr = x + m * N, *gr = dy + m * N;
+        double *dr = dx + m * N, *hr = xhat_ws + m * N;
+        acc_t s = {0, 0};
+        for (int64_t i = 0; i < N; ++i) acc_add(&s, xr[i] * xr[i]);
+        double rs = 1.0 / sqrt(acc_get(&s) / (double)N + eps);
+        acc_t c = {0, 0};
+        for (int64_t i = 0; i < N; ++i) {
+            hr[i] = xr[i] * rs;
+            acc_add(&c, gr[i] * gamma[i] * hr[i]);
+        }
+        double mc = acc_get(&c) / (double)N;
+        for (int64_t i = 0; i < N; ++i) dr[i] = rs * (gr[i] * gamma[i] - hr[i] * mc);
+    }
+    if (dgamma) column_sums(M, N, dy, xhat_ws, dgamma);
+}

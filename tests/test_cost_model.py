@@ -1,0 +1,145 @@
+"""Pins of the cost-model oracle (oracle/cost_model.py) against numbers the
+paper prints and against hand-computed cases, and host-logic checks of the
+library's own model (libcredit, no GPU) against that oracle.  CPU only."""
+import json
+import math
+import os
+
+import pytest
+
+from oracle import cost_model as cm
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def test_byte_accounting_reproduces_printed_traffic():
+    # Sec. IV-D: baseline -> clustered bytes per element
+    gold = _load("paper_traffic.json")["bytes_per_element"]
+    wl = cm.paper_workloads()
+    for name, (base, staged) in gold.items():
+        w = wl[name]
+        assert w.b_B() == base, name
+        assert w.b_cluster() == staged, name
+        D_base, D_cl = cm.hbm_traffic(w, 65536)
+        assert D_base / 65536 == base and D_cl / 65536 == staged
+    # the 33-60% reduction range quoted with them
+    for name, (base, staged) in gold.items():
+        red = 1 - staged / base
+        assert 0.33 <= red + 1e-9 and red <= 0.60 + 1e-9
+
+
+def test_primitive_ratios_stated_in_text():
+    # Sec. III-A: remote load ~6.4x the local latency; 4.4-5.4x lower read rate
+    t = _load("paper_primitives.json")
+    for gpu in ("RTX5090", "H100"):
+        r = t[gpu]["remote_load"] / t[gpu]["local_load"]
+        assert abs(r - 6.4) < 0.05
+        rr = t[gpu]["local_read"] / t[gpu]["remote_read"]
+        assert 4.35 <= rr <= 5.45
+
+
+def test_capacity_rule_eq3():
+    # ceil(N/P) * b_keep + S_scratch <= S_max
+    assert cm.capacity_legal(65536, 2, 8.0, 1024, 232448) is False   # 262144 + 1024 > 227 KB
+    assert cm.capacity_legal(65536, 4, 8.0, 1024, 232448) is True    # 131072 + 1024
+    assert cm.capacity_legal(10, 3, 4.0, 0, 16) is True              # ceil(10/3) = 4 -> 16 bytes
+    assert cm.capacity_legal(10, 3, 4.0, 1, 16) is False
+
+
+def test_protocol_cost_eq6():
+    w, r, K = cm.protocol_cost(4, [2, 1], 4)
+    assert (w, r, K) == (4 * 4 * 3 * 3, 0.0, 4)
+    w, r, K = cm.protocol_cost(2, [1], 4)
+    assert (w, r, K) == (8, 0.0, 2)
+
+
+def test_eq7_identity_and_waves():
+    M, N, bB, br, TB = 4096, 65536, 24.0, 12.0, 1234.5
+    Beff = cm.effective_bandwidth(M, N, bB, TB)
+    assert math.isclose(cm.t_save(M, N, br, Beff), TB * br / bB, rel_tol=1e-15)
+    assert cm.waves(4096, 170, 8) == math.ceil(4096 / 21)
+    assert cm.waves(2048, 132, 2) == math.ceil(2048 / 66)
+
+
+def test_eq8_times_are_not_multiplied_by_P():
+    # T_DSM counts (P - 1) peers per source, and no factor P for the sources
+    t2 = cm.t_dsm(1024, 2, 128, [2], 4, 2.0e9, 2.0)
+    t4 = cm.t_dsm(1024, 4, 128, [2], 4, 2.0e9, 2.0)
+    W2, W4 = cm.waves(1024, 128, 2), cm.waves(1024, 128, 4)
+    assert math.isclose(t4 / t2, (W4 * 3) / (W2 * 1))
+    tr = cm.t_replay(1024, 65536, 4, 128, 4.0, 2.0e9, 20.89)
+    assert math.isclose(tr, W4 * 16384 * 4.0 / (2.0e9 * 20.89))
+
+
+def test_delta_t_and_crossover():
+    assert cm.delta_t(10.0, 1.0, 2.0, 0.5, 0.25) == 6.25
+    assert cm.t_deposit(3.0, 5.0) == 0.0 and cm.t_deposit(5.0, 3.0) == 2.0
+    prof = {4096: False, 8192: False, 16384: True, 32768: True}
+    assert cm.crossover_width(sorted(prof), lambda n: prof[n]) == 16384
+    assert cm.crossover_width([1, 2], lambda n: False) is None
+
+
+def test_credit_operator_workloads():
+    # two-pass: one statistics pass + one output pass => 3e forward, 5e backward;
+    # staged: 2e forward, 3e backward (Eq. (4) ceilings 1.5x and 1.67x)
+    for e in (4.0, 2.0, 1.0):
+        wl = cm.credit_workloads(e)
+        for name in ("softmax_fwd", "layernorm_fwd", "rmsnorm_fwd"):
+            assert wl[name].b_B() == 3 * e and wl[name].b_cluster() == 2 * e
+        for name in ("softmax_bwd", "layernorm_bwd", "rmsnorm_bwd"):
+            assert wl[name].b_B() == 5 * e and wl[name].b_cluster() == 3 * e
+
+
+# ------------------------------------------------ library (host only) vs oracle
+OPS = [("softmax_fwd", 0, 0), ("layernorm_fwd", 1, 0), ("rmsnorm_fwd", 2, 0),
+       ("softmax_bwd", 0, 1), ("layernorm_bwd", 1, 1), ("rmsnorm_bwd", 2, 1)]
+
+
+@pytest.mark.parametrize("name,op,d", OPS)
+@pytest.mark.parametrize("dt,e", [(0, 4.0), (1, 2.0)])
+def test_library_workload_info_matches_oracle(lib_built, name, op, d, dt, e):
+    from paper_2609_01864_amd import credit as C
+
+    w = C.workload_info(op, d, dt)
+    ref = cm.credit_workloads(e)[name]
+    assert w.b_base == ref.b_B() and w.b_staged == ref.b_cluster()
+    assert w.b_reread == ref.b_reread() and w.b_keep == ref.b_keep()
+    assert w.stages == ref.L and list(w.q)[: w.stages] == ref.q
+
+
+def test_library_workload_recompute_matches_paper_layernorm(lib_built):
+    # LayerNorm backward with recomputed statistics is the paper's 24 -> 12
+    from paper_2609_01864_amd import credit as C
+
+    w = C.workload_info(C.LAYERNORM, C.BWD, C.F32, recompute=True)
+    gold = _load("paper_traffic.json")["bytes_per_element"]["layernorm_bwd"]
+    assert (w.b_base, w.b_staged) == tuple(gold)
+
+
+@pytest.mark.parametrize("op,d", [(0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (2, 1)])
+@pytest.mark.parametrize("M,N", [(1024, 131072), (64, 32768), (4096, 262144), (2048, 131072), (3, 5000)])
+def test_library_model_delta_matches_oracle(lib_built, op, d, M, N):
+    from paper_2609_01864_amd import credit as C
+
+    dt = C.F32
+    tb = 321.0
+    ctrl = [3.0, 5.0, 9.0, 17.0, 33.0]
+    got = C.model_delta(None, op, d, dt, M, N, tb, ctrl)
+    w = C.workload_info(op, d, dt)
+    for i, k in enumerate((2, 4, 8, 16, 32)):
+        geo = C.plan_geometry(None, op, d, dt, M, N, C.plan("split", k))
+        if geo is None:
+            assert got[i] == -math.inf
+            continue
+        groups = geo["grid"] // k
+        # the library's groups come from the occupancy bound and XCD rounding;
+        # the model itself is Eq. (9) with W = ceil(M / groups)
+        W = math.ceil(M / groups)
+        ref = cm.delta_t(tb * w.b_reread / w.b_base, ctrl[i], 0.0, 0.0,
+                         8.0 * W * (k - 1) * sum(list(w.q)[: w.stages]) / (2.4e9 * 64.0) * 1e6)
+        assert math.isclose(got[i], ref, rel_tol=1e-5, abs_tol=1e-4), (k, got[i], ref)
