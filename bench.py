@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Benchmark of the reduction-reuse row kernels on one MI355X.
+
+Workload (one "step"): FP32 LayerNorm and RMSNorm forward, eps = 1e-5, M = 1024
+rows, N in {8192, 32768, 131072, 524288}; x ~ N(10, 1), gamma ~ U(0.5, 1.5),
+beta ~ N(0, 0.1).  Every (op, N) call runs the plan the library's selector
+picks for the shape (learned model if one is installed, else the profile-guided
+analytic model); each call reads its own input buffers, so no input is served
+from a cache warmed by the previous call.
+
+Prints one JSON line: aggregate algorithmic GB/s over the timed steps, the
+roofline of the dominant kernel (HIP events on the launch stream), the CPU
+oracle timed on a bounded sample, and per-shape plan regret against
+exhaustive timing.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+M_ROWS = 1024
+WIDTHS = (8192, 32768, 131072, 524288)
+EPS = 1e-5
+PEAK_GBPS = 8000.0
+OPS = ("layernorm_fwd", "rmsnorm_fwd")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2609_01864_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(op: str, M: int, N: int) -> int:
+    # x read + y written once, gamma (and beta) once, mean/rstd per row
+    vec = 2 if op == "layernorm_fwd" else 1
+    return M * N * 4 * 2 + vec * N * 4 + vec * M * 4
+
+
+def cpu_baseline(rows: int = 64):
+    """The FP64 oracle (as it stands) on the first `rows` rows of every
+    (op, N) of the workload, all host threads."""
+    import numpy as np
+
+    import oracle
+    from paper_2609_01864_amd import inputs as I
+
+    total_bytes = 0
+    total_s = 0.0
+    for N in WIDTHS:
+        x = I.norm_rows(M_ROWS, N, seed=1, tensor=0, rows=np.arange(rows)).astype(np.float32).astype(np.float64)
+        g, b = I.norm_params(N, seed=1)
+        g = g.astype(np.float64)
+        b = b.astype(np.float64)
+        t0 = time.perf_counter()
+        oracle.layernorm_fwd(x, g, b, EPS)
+        t1 = time.perf_counter()
+        oracle.rmsnorm_fwd(x, g, EPS)
+        t2 = time.perf_counter()
+        total_s += t2 - t0
+        total_bytes += algorithmic_bytes("layernorm_fwd", rows, N) + algorithmic_bytes("rmsnorm_fwd", rows, N)
+    return {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {rows} of {M_ROWS} rows of each (op, N) of the workload, FP64 C oracle, "
+                      f"{total_s:.1f} s"}
+
+
+def traffic_for(kernel_key: str):
+    """Counter-measured HBM bytes per launch for the dominant kernel, if the
+    committed profile was taken from the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        ent = d.get("kernels", {}).get(kernel_key)
+        if ent and ent.get("source_hash") == source_hash():
+            return ent.get("bytes_per_launch")
+    except Exception:
+        return None
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-regret", action="store_true", help="skip exhaustive timing of all plans")
+    ap.add_argument("--selector", default="auto", choices=["auto", "learned", "analytic", "fixed", "exhaustive"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the row kernels shard over rows with no communication, "
+              "so a multi-GPU figure is not measured here", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2609_01864_amd import credit as C
+
+    dev = torch.device("cuda:0")
+    h = C.Handle(0)
+    sel_name = args.selector
+    if sel_name == "auto":
+        sel_name = "learned" if h.model_loaded else "analytic"
+    sel = {"learned": C.SEL_LEARNED, "analytic": C.SEL_ANALYTIC, "fixed": C.SEL_FIXED,
+           "exhaustive": C.SEL_EXHAUSTIVE}[sel_name]
+    h.set_selector(sel)
+    log(f"selector={sel_name} model_loaded={h.model_loaded}")
+
+    # ---------------------------------------------------------------- inputs
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1)
+    bufs = {}
+    for op in OPS:
+        for N in WIDTHS:
+            x = torch.randn((M_ROWS, N), generator=gen, device=dev, dtype=torch.float32) + 10.0
+            gamma = torch.rand((N,), generator=gen, device=dev) + 0.5
+            beta = 0.1 * torch.randn((N,), generator=gen, device=dev)
+            y = torch.empty_like(x)
+            mean = torch.empty(M_ROWS, device=dev)
+            rstd = torch.empty(M_ROWS, device=dev)
+            bufs[(op, N)] = (x, gamma, beta, y, mean, rstd)
+    torch.cuda.synchronize()
+    log("inputs ready")
+
+    # ------------------------------------------------------ plan selection
+    opnum = {"layernorm_fwd": C.LAYERNORM, "rmsnorm_fwd": C.RMSNORM}
+    picks = {}
+    t0 = time.time()
+    for op in OPS:
+        for N in WIDTHS:
+            p, pred = h.select(opnum[op], C.FWD, C.F32, M_ROWS, N)
+            picks[(op, N)] = (p, pred)
+            log(f"pick {op} N={N}: {p} (predicted {pred:.1f} us)")
+    sel_s = time.time() - t0
+
+    stream = torch.cuda.current_stream(dev)
+
+    def call(op, N):
+        x, g, b, y, mean, rstd = bufs[(op, N)]
+        p = picks[(op, N)][0]
+        if op == "layernorm_fwd":
+            C.layernorm_fwd(x, g, b, EPS, p=p, out=y, h=h)
+        else:
+            C.rmsnorm_fwd(x, g, EPS, p=p, out=y, h=h)
+
+    # workspaces are sized on first use, outside the timed region
+    for op in OPS:
+        for N in WIDTHS:
+            call(op, N)
+    torch.cuda.synchronize()
+    assert h.check_errors() == C.OK
+
+    for _ in range(args.warmup):
+        for op in OPS:
+            for N in WIDTHS:
+                call(op, N)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    # ------------------------------------------------------------ timed
+    events = {(op, N): [] for op in OPS for N in WIDTHS}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        for op in OPS:
+            for N in WIDTHS:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                call(op, N)
+                e1.record(stream)
+                events[(op, N)].append((e0, e1))
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    assert h.check_errors() == C.OK
+    wall_ms = (t_end - t_start) * 1e3
+    ms_per_step = wall_ms / args.steps
+    step_bytes = sum(algorithmic_bytes(op, M_ROWS, N) for op in OPS for N in WIDTHS)
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.1f} GB/s")
+
+    per_shape = []
+    for op in OPS:
+        for N in WIDTHS:
+            us = 1e3 * sum(a.elapsed_time(b) for a, b in events[(op, N)]) / len(events[(op, N)])
+            gb = algorithmic_bytes(op, M_ROWS, N) / (us * 1e-6) / 1e9
+            p = picks[(op, N)][0]
+            per_shape.append({"op": op, "N": N, "plan": [int(p.variant), int(p.k)], "us": round(us, 2),
+                              "gbps": round(gb, 1), "frac": round(gb / PEAK_GBPS, 4)})
+    dom = max(per_shape, key=lambda r: r["us"])
+    dom_key = f"{dom['op']}:N={dom['N']}:plan={dom['plan'][0]},{dom['plan'][1]}"
+    roofline = {"bound": "hbm", "achieved": dom["gbps"], "peak": PEAK_GBPS, "unit": "GB/s",
+                "frac": round(dom["gbps"] / PEAK_GBPS, 4), "traffic": traffic_for(dom_key),
+                "kernel": dom_key, "avg_launch_us": dom["us"],
+                "algorithmic_bytes_per_launch": algorithmic_bytes(dom["op"], M_ROWS, dom["N"])}
+
+    # --------------------------------------------- regret vs exhaustive
+    regrets = []
+    if not args.no_regret:
+        for r in per_shape:
+            o = opnum[r["op"]]
+            best = None
+            times = {}
+            for c in range(C.NUM_PLANS):
+                p = C.plan_of_class(c)
+                if not h.plan_legal(o, C.FWD, C.F32, M_ROWS, r["N"], p):
+                    continue
+                t = h.time_plan(o, C.FWD, C.F32, M_ROWS, r["N"], p, reps=15, flush=True)
+                times[f"{p.variant},{p.k}"] = round(t, 2)
+                if best is None or t < best[1]:
+                    best = (p, t)
+            pk = picks[(r["op"], r["N"])][0]
+            tp = times[f"{pk.variant},{pk.k}"]
+            r["plan_times_us"] = times
+            r["best_plan"] = [int(best[0].variant), int(best[0].k)]
+            r["regret"] = round(tp / best[1] - 1.0, 4)
+            regrets.append(tp / best[1])
+            log(f"{r['op']} N={r['N']}: times {times} pick {r['plan']} regret {r['regret']:+.3f}")
+    copy_gbps = h.copy_bandwidth(1 << 30, 15)
+    log(f"copy kernel: {copy_gbps:.1f} GB/s")
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle sample")
+        cpu = cpu_baseline()
+
+    out = {
+        "metric": "HBM GB/s and % of 8 TB/s peak per op/shape; cost-model pick regret vs best",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "FP32 LayerNorm + RMSNorm forward, eps 1e-5, M=1024, N in {8192, 32768, 131072, "
+                               "524288}, x~N(10,1), gamma~U(0.5,1.5), beta~N(0,0.1)",
+                   "M": M_ROWS, "N": list(WIDTHS), "selector": sel_name,
+                   "selection_s": round(sel_s, 2)},
+        "frac_of_peak": round(value / PEAK_GBPS, 4),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "regret_geomean": round(math.exp(sum(math.log(x) for x in regrets) / len(regrets)) - 1.0, 4)
+        if regrets else None,
+        "copy_kernel_gbps": round(copy_gbps, 1),
+        "per_shape": per_shape,
+        "source_hash": source_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,320 @@
+/*
+ * credit.h -- C ABI of the MI355X (gfx950) wide reduction-reuse row-kernel library.
+ *
+ * The operators are members of the reduction-reuse class of the CREDIT paper
+ * (Sec. III-B, Eq. (1)): each row of width N is reduced to a few scalar
+ * statistics r, then every element is reused to write a full-size output
+ * y_i = h(x_i, r).  Three kernel variants exist for every operator:
+ *
+ *   CREDIT_TWO_PASS      the global-reread baseline (Sec. IV-A): one workgroup
+ *                        streams the row once for the statistics and again to
+ *                        write the output.
+ *   CREDIT_ROW_RESIDENT  one workgroup keeps its whole row in registers (the
+ *                        one-CTA staged baseline of Sec. IV-A) and writes the
+ *                        output without a second global read.
+ *   CREDIT_SPLIT_ROW     the row is split into k slices held by k co-resident
+ *                        workgroups (Eq. (2)); each reduces its slice, the k
+ *                        partial statistics are exchanged through device memory
+ *                        (the L2 / Infinity Cache stands in for the cluster's
+ *                        distributed shared memory of Sec. III-C, Eq. (5)), and
+ *                        every workgroup applies h to its own retained slice.
+ *
+ * A plan (variant, k) is chosen per shape by the profitability model of
+ * Sec. III-D (Eq. (7)-(9), with MI355X terms), by a learned selector, by
+ * exhaustive timing, or given by the caller.
+ *
+ * Conventions shared by every entry point:
+ *   - Device pointers are plain HIP device addresses; the caller owns all
+ *     tensors and the workspace.  Nothing in an operator call allocates.
+ *   - Matrices are row-major [M, ld] with unit inner stride; ld >= N is given
+ *     in ELEMENTS.  Rows whose start is not 16-byte aligned take a scalar path.
+ *   - I/O dtypes: CREDIT_F32 (float), CREDIT_BF16 (raw 16-bit bfloat16),
+ *     CREDIT_FP8_E4M3 (raw uint8 OCP e4m3fn).  FP8 tensors carry one FP32
+ *     scale per row: value = decode(code) * scale[row].  FP8 inputs read their
+ *     scales; FP8 outputs write theirs (scale = row amax / 448, or 1 for an
+ *     all-zero row) and the codes are rounded to nearest even and saturated to
+ *     +-448.  All arithmetic is FP32.  gamma, beta, dgamma, dbeta, mean and
+ *     rstd are FP32 vectors in every dtype.
+ *   - Calls are asynchronous on `stream`.  M == 0 is a no-op.  N == 0, ld < N,
+ *     a NULL required pointer, or a workspace smaller than
+ *     credit_workspace_size() returns CREDIT_ERR_INVALID_ARG /
+ *     CREDIT_ERR_WORKSPACE.  An explicit plan that is illegal for the shape
+ *     returns CREDIT_ERR_UNSUPPORTED; plans are never silently changed.
+ *   - The workspace must be zero-filled before its first use; the library
+ *     keeps it valid across calls.  Two calls that may run concurrently must
+ *     not share a workspace.
+ *   - No C++ exception crosses this interface and nothing aborts.
+ */
+#ifndef CREDIT_H
+#define CREDIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CREDIT_OK = 0,
+    CREDIT_ERR_INVALID_ARG = 1,
+    CREDIT_ERR_UNSUPPORTED = 2, /* plan illegal for this shape / dtype        */
+    CREDIT_ERR_WORKSPACE = 3,   /* workspace missing or too small              */
+    CREDIT_ERR_HIP = 4,         /* a HIP runtime call failed                   */
+    CREDIT_ERR_TIMEOUT = 5,     /* a split-row exchange wait hit its bound     */
+    CREDIT_ERR_MODEL = 6        /* selector model missing, corrupt or foreign  */
+} credit_status_t;
+
+typedef enum { CREDIT_F32 = 0, CREDIT_BF16 = 1, CREDIT_FP8_E4M3 = 2 } credit_dtype_t;
+typedef enum { CREDIT_SOFTMAX = 0, CREDIT_LAYERNORM = 1, CREDIT_RMSNORM = 2 } credit_op_t;
+typedef enum { CREDIT_FWD = 0, CREDIT_BWD = 1 } credit_dir_t;
+typedef enum { CREDIT_TWO_PASS = 0, CREDIT_ROW_RESIDENT = 1, CREDIT_SPLIT_ROW = 2 } credit_variant_t;
+typedef enum {
+    CREDIT_SEL_LEARNED = 0,    /* MLP over shape features; falls back to ANALYTIC   */
+    CREDIT_SEL_ANALYTIC = 1,   /* Eq. (9) with one timing of the baseline (Eq. (7)) */
+    CREDIT_SEL_EXHAUSTIVE = 2, /* time every legal plan, keep the fastest           */
+    CREDIT_SEL_FIXED = 3,      /* resident if it fits, else smallest legal k, else two-pass */
+    CREDIT_SEL_PEAK = 4        /* Eq. (9) with the baseline priced at calibrated copy bandwidth */
+} credit_selector_t;
+
+/* variant and split factor; k == 1 for CREDIT_TWO_PASS and CREDIT_ROW_RESIDENT,
+ * k in {2, 4, 8, 16, 32} for CREDIT_SPLIT_ROW. */
+typedef struct {
+    int32_t variant;
+    int32_t k;
+} credit_plan_t;
+
+typedef struct credit_handle_s *credit_handle_t;
+
+/* Human-readable name of a status code (static storage). */
+const char *credit_status_string(credit_status_t s);
+
+/* Library version string (static storage). */
+const char *credit_version(void);
+
+/* Creates a handle bound to HIP device `device`: reads its properties, sizes
+ * the persistent grids, allocates the handle's small device-side error flag.
+ * The handle owns the plan cache, the selector model and timing buffers. */
+credit_status_t credit_create(int device, credit_handle_t *h);
+credit_status_t credit_destroy(credit_handle_t h);
+
+/* Selector used when an operator is called with plan == NULL. */
+credit_status_t credit_set_selector(credit_handle_t h, credit_selector_t s);
+
+/* Bytes of workspace an operator call needs for (op, dir, dtype, M, N) under
+ * `plan` (NULL: the plan the current selector picks; this may time kernels on
+ * first use of a shape, Sec. III-D).  The size covers split-row exchange slots
+ * (M * stages * k * q * 8 bytes) and, for normalisation backward, per-row-group
+ * dgamma/dbeta column partials. */
+credit_status_t credit_workspace_size(credit_handle_t h, credit_op_t op, credit_dir_t dir,
+                                      credit_dtype_t dt, int64_t M, int64_t N,
+                                      const credit_plan_t *plan, size_t *bytes);
+
+/* Whether `plan` is legal for the shape: the slice of ceil(N/k) elements must
+ * fit the kernel's register capacity (the capacity rule of Eq. (3)) and, for
+ * k > 1, the k workgroups of a row must be co-resident.  Returns CREDIT_OK or
+ * CREDIT_ERR_UNSUPPORTED. */
+credit_status_t credit_plan_legal(credit_handle_t h, credit_op_t op, credit_dir_t dir,
+                                  credit_dtype_t dt, int64_t M, int64_t N,
+                                  const credit_plan_t *plan);
+
+/* Picks a plan for the shape with the handle's selector (Sec. III-D).
+ * predicted_us (nullable) receives the model's predicted time where the
+ * selector has one, else -1. */
+credit_status_t credit_select(credit_handle_t h, credit_op_t op, credit_dir_t dir,
+                              credit_dtype_t dt, int64_t M, int64_t N, credit_plan_t *out,
+                              float *predicted_us);
+
+/* ---------------------------------------------------------------- operators */
+
+/* Row softmax: y = exp(x - max x) / sum exp(x - max x). */
+credit_status_t credit_softmax_fwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                                   const void *x, int64_t ldx, const float *x_scale, void *y,
+                                   int64_t ldy, float *y_scale, const credit_plan_t *plan,
+                                   void *ws, size_t ws_bytes, void *stream);
+
+/* Softmax backward from the forward output: dx = y * (dy - sum(dy * y)). */
+credit_status_t credit_softmax_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                                   const void *y, int64_t ldy, const float *y_scale,
+                                   const void *dy, int64_t lddy, const float *dy_scale, void *dx,
+                                   int64_t lddx, float *dx_scale, const credit_plan_t *plan,
+                                   void *ws, size_t ws_bytes, void *stream);
+
+/* LayerNorm: mean and biased variance per row, rstd = 1/sqrt(var + eps),
+ * y = (x - mean) * rstd * gamma + beta.  mean / rstd outputs are nullable. */
+credit_status_t credit_layernorm_fwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                                     const void *x, int64_t ldx, const float *x_scale,
+                                     const float *gamma, const float *beta, float eps, void *y,
+                                     int64_t ldy, float *y_scale, float *mean, float *rstd,
+                                     const credit_plan_t *plan, void *ws, size_t ws_bytes,
+                                     void *stream);
+
+/* LayerNorm backward: xhat = (x - mean) * rstd, g = dy * gamma,
+ * dx = rstd * (g - mean(g) - xhat * mean(g * xhat)),
+ * dgamma = sum over rows of dy * xhat, dbeta = sum over rows of dy.
+ * mean and rstd are the forward's saved statistics; pass both NULL to have
+ * them recomputed from x in the same pass (one more reduction stage).
+ * dgamma / dbeta are overwritten (not accumulated); either may be NULL. */
+credit_status_t credit_layernorm_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                                     const void *x, int64_t ldx, const float *x_scale,
+                                     const void *dy, int64_t lddy, const float *dy_scale,
+                                     const float *gamma, const float *mean, const float *rstd,
+                                     float eps, void *dx, int64_t lddx, float *dx_scale,
+                                     float *dgamma, float *dbeta, const credit_plan_t *plan,
+                                     void *ws, size_t ws_bytes, void *stream);
+
+/* RMSNorm: rstd = 1/sqrt(mean(x^2) + eps), y = x * rstd * gamma.  rstd nullable. */
+credit_status_t credit_rmsnorm_fwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                                   const void *x, int64_t ldx, const float *x_scale,
+                                   const float *gamma, float eps, void *y, int64_t ldy,
+                                   float *y_scale, float *rstd, const credit_plan_t *plan,
+                                   void *ws, size_t ws_bytes, void *stream);
+
+/* RMSNorm backward: xhat = x * rstd, g = dy * gamma,
+ * dx = rstd * (g - xhat * mean(g * xhat)), dgamma = sum over rows of dy * xhat.
+ * rstd NULL: recomputed from x.  dgamma nullable. */
+credit_status_t credit_rmsnorm_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                                   const void *x, int64_t ldx, const float *x_scale,
+                                   const void *dy, int64_t lddy, const float *dy_scale,
+                                   const float *gamma, const float *rstd, float eps, void *dx,
+                                   int64_t lddx, float *dx_scale, float *dgamma,
+                                   const credit_plan_t *plan, void *ws, size_t ws_bytes,
+                                   void *stream);
+
+/* Elementwise FP32 -> dtype encode of an [M, N] matrix with optional per-row
+ * output scale (FP8: code = RNE_sat(x / scale[row])); and the inverse decode.
+ * Contiguous rows (ld == N). */
+credit_status_t credit_encode(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                              const float *x, const float *row_scale, void *out, void *stream);
+credit_status_t credit_decode(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                              const void *in, const float *row_scale, float *out, void *stream);
+
+/* Status of work already issued: synchronises `stream`, reports a sticky HIP
+ * error or a split-row exchange timeout (then clears the timeout flag). */
+credit_status_t credit_check_errors(credit_handle_t h, void *stream);
+
+/* ------------------------------------------------------- timing and models */
+
+/* Times `plan` on (op, dir, dtype, M, N) with library-owned buffers:
+ * `reps` runs (0: 15), each preceded by a 512 MiB cache flush when `flush` is
+ * nonzero, bracketed by HIP events; writes the median in microseconds.
+ * Follows the median-of-15 protocol of Sec. III-A. */
+credit_status_t credit_time_plan(credit_handle_t h, credit_op_t op, credit_dir_t dir,
+                                 credit_dtype_t dt, int64_t M, int64_t N,
+                                 const credit_plan_t *plan, int reps, int flush,
+                                 float *median_us);
+
+/* Times the work-free control kernel of Sec. III-D for a split factor k at
+ * (op, dir, dtype, M, N): the same persistent grid, split factor, occupancy
+ * and exchange waits as the split-row kernel, no row data.  k == 1 gives the
+ * one-workgroup control.  Median of `reps` runs in microseconds. */
+credit_status_t credit_time_control(credit_handle_t h, credit_op_t op, credit_dir_t dir,
+                                    credit_dtype_t dt, int64_t M, int64_t N, int32_t k,
+                                    int reps, float *median_us);
+
+/* Times a plain device copy of `bytes` bytes (read + write) and returns the
+ * achieved GB/s (median of `reps`); the practical HBM ceiling used to price
+ * traffic in the CREDIT_SEL_PEAK model. */
+credit_status_t credit_copy_bandwidth(credit_handle_t h, size_t bytes, int reps, float *gbps);
+
+/* Evaluates the analytic model of Sec. III-D for every plan of the shape with
+ * caller-supplied measurements (no GPU work):
+ *   t_base_us    the measured baseline time T_B (Eq. (7))
+ *   t_ctrl_us    control-kernel excess T_ctrl for k = 2,4,8,16,32 (5 entries)
+ * out_delta_us receives Delta T for k = 2,4,8,16,32 (Eq. (9)); illegal plans
+ * get -INFINITY.  Host-only: callable without a GPU for a handle created on
+ * a device, and with h == NULL using MI355X defaults. */
+credit_status_t credit_model_delta(credit_handle_t h, credit_op_t op, credit_dir_t dir,
+                                   credit_dtype_t dt, int64_t M, int64_t N, float t_base_us,
+                                   const float *t_ctrl_us, float *out_delta_us);
+
+/* Byte accounting of an operator per element (static analysis of Eq. (4)):
+ * baseline (two-pass) bytes b_B, staged bytes, eliminated reread b_reread,
+ * retained bytes b_keep, stages L and statistics per stage q (up to 4). */
+typedef struct {
+    float b_base;
+    float b_staged;
+    float b_reread;
+    float b_keep;
+    int32_t stages;
+    int32_t q[4];
+} credit_workload_t;
+credit_status_t credit_workload_info(credit_op_t op, credit_dir_t dir, credit_dtype_t dt,
+                                     int recompute_stats, credit_workload_t *out);
+
+/* ------------------------------------------------------------ learned model
+ * A 12 -> 64 -> 64 -> CREDIT_NUM_PLANS ReLU network over standardized shape
+ * features predicts the fastest plan; trained on the GPU by the library's
+ * own kernels from timings it collects. */
+#define CREDIT_NUM_FEATURES 12
+#define CREDIT_NUM_PLANS 7 /* two-pass, resident, split k = 2, 4, 8, 16, 32 */
+#define CREDIT_MLP_HIDDEN 64
+
+/* Plan of class c in [0, CREDIT_NUM_PLANS). */
+credit_status_t credit_plan_of_class(int32_t c, credit_plan_t *out);
+
+/* The 12 raw (unstandardized) features of a shape. */
+credit_status_t credit_features(credit_op_t op, credit_dir_t dir, credit_dtype_t dt, int64_t M,
+                                int64_t N, float *feat12);
+
+/* Number of FP32 parameters of the network (W1, b1, W2, b2, W3, b3 in that
+ * order, weights row-major [out][in]). */
+int64_t credit_mlp_num_params(void);
+
+/* Sets / gets the parameters and the feature standardization (mu, sd: 12 each). */
+credit_status_t credit_mlp_set(credit_handle_t h, const float *params, const float *mu,
+                               const float *sd);
+credit_status_t credit_mlp_get(credit_handle_t h, float *params, float *mu, float *sd);
+
+/* Loss and gradient at the current parameters on the GPU, without updating:
+ * masked soft-target cross-entropy averaged over n samples.  feats are raw;
+ * targets [n][C] sum to 1 over legal plans; mask [n][C] is 1 for legal. */
+credit_status_t credit_mlp_grad(credit_handle_t h, const float *feats, const float *targets,
+                                const uint8_t *mask, int64_t n, float *loss, float *grad);
+
+/* Full-batch Adam training on the GPU (beta1 0.9, beta2 0.999, eps 1e-8) for
+ * `epochs` steps from a seeded He initialisation (seed != 0) or from the
+ * current parameters (seed == 0).  The standardization is computed from the
+ * given features when seed != 0. */
+credit_status_t credit_mlp_train(credit_handle_t h, const float *feats, const float *targets,
+                                 const uint8_t *mask, int64_t n, int epochs, float lr,
+                                 uint64_t seed, float *final_loss);
+
+/* Logits [n][C] for raw features, computed on the GPU. */
+credit_status_t credit_mlp_predict(credit_handle_t h, const float *feats, int64_t n,
+                                   float *logits);
+
+/* Saves / loads the network with a header (format, arch, CU count, feature
+ * schema); a foreign or corrupt file returns CREDIT_ERR_MODEL and leaves the
+ * handle without a model. */
+credit_status_t credit_save_model(credit_handle_t h, const char *path);
+credit_status_t credit_load_model(credit_handle_t h, const char *path);
+
+/* ------------------------------------------------------------- diagnostics */
+
+/* Handle options. */
+typedef enum {
+    CREDIT_OPT_SPIN_LIMIT = 0,  /* poll iterations before an exchange wait gives up */
+    CREDIT_OPT_TEST_DROP_PUBLISH = 1, /* test only: member 1 of each row group skips
+                                         publishing its partials (forces the timeout
+                                         path of CREDIT_ERR_TIMEOUT) */
+    CREDIT_OPT_MAX_GROUPS = 2   /* cap on concurrent row groups (0: occupancy bound) */
+} credit_option_t;
+credit_status_t credit_set_option(credit_handle_t h, credit_option_t opt, int64_t value);
+
+/* Sets the next exchange epoch (process-wide); epochs are 32-bit and never 0.
+ * Used to exercise epoch wrap-around. */
+credit_status_t credit_set_epoch(uint32_t next_epoch);
+
+/* Launch geometry the library would use for a plan: grid size (workgroups),
+ * threads per workgroup, per-thread vector count, co-resident workgroups per
+ * CU.  Host-only. */
+credit_status_t credit_plan_geometry(credit_handle_t h, credit_op_t op, credit_dir_t dir,
+                                     credit_dtype_t dt, int64_t M, int64_t N,
+                                     const credit_plan_t *plan, int32_t *grid, int32_t *block,
+                                     int32_t *vpt, int32_t *per_cu);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CREDIT_H */

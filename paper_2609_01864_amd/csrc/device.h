@@ -1,0 +1,306 @@
+// device.h -- gfx950 device building blocks shared by the row kernels:
+// I/O codecs, 128-bit row-slice loads and stores, wave64 / workgroup
+// reductions, and the split-row partial exchange.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kargs.h"
+
+namespace credit {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kFp8Max = 448.0f;
+constexpr int kBlock = kBlockThreads;  // one wave per SIMD
+
+template <int DT> struct Io;
+template <> struct Io<DT_F32> { static constexpr int EPV = 4, BYTES = 4; };
+template <> struct Io<DT_BF16> { static constexpr int EPV = 8, BYTES = 2; };
+template <> struct Io<DT_FP8> { static constexpr int EPV = 16, BYTES = 1; };
+
+__device__ __forceinline__ float fast_exp2(float v) { return __builtin_amdgcn_exp2f(v); }
+
+// ------------------------------------------------------------------ codecs
+// Decode one 16-byte vector into EPV floats; FP8 codes are multiplied by the
+// row scale (OCP e4m3fn through the gfx950 hardware conversion).
+template <int DT> __device__ __forceinline__ void decode(const u32x4 v, float *f, float scale);
+
+template <> __device__ __forceinline__ void decode<DT_F32>(const u32x4 v, float *f, float) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f[i] = __uint_as_float(v[i]);
+}
+template <> __device__ __forceinline__ void decode<DT_BF16>(const u32x4 v, float *f, float) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[2 * i] = __uint_as_float(v[i] << 16);
+        f[2 * i + 1] = __uint_as_float(v[i] & 0xffff0000u);
+    }
+}
+template <> __device__ __forceinline__ void decode<DT_FP8>(const u32x4 v, float *f, float scale) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)v[i], false);
+        f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)v[i], true);
+        f[4 * i + 0] = lo.x * scale;
+        f[4 * i + 1] = lo.y * scale;
+        f[4 * i + 2] = hi.x * scale;
+        f[4 * i + 3] = hi.y * scale;
+    }
+}
+
+__device__ __forceinline__ unsigned bf16_bits(float x) {
+    __bf16 b = (__bf16)x;  // v_cvt_pk_bf16_f32: round to nearest even
+    return (unsigned)__builtin_bit_cast(unsigned short, b);
+}
+
+// Encode EPV floats into one 16-byte vector.  FP8: code = RNE(f * inv_scale),
+// clamped to the finite range first so it saturates at +-448.
+template <int DT> __device__ __forceinline__ u32x4 encode(const float *f, float inv_scale);
+
+template <> __device__ __forceinline__ u32x4 encode<DT_F32>(const float *f, float) {
+    u32x4 v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = __float_as_uint(f[i]);
+    return v;
+}
+template <> __device__ __forceinline__ u32x4 encode<DT_BF16>(const float *f, float) {
+    u32x4 v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = bf16_bits(f[2 * i]) | (bf16_bits(f[2 * i + 1]) << 16);
+    return v;
+}
+__device__ __forceinline__ float sat448(float x) { return fminf(fmaxf(x, -kFp8Max), kFp8Max); }
+template <> __device__ __forceinline__ u32x4 encode<DT_FP8>(const float *f, float inv_scale) {
+    u32x4 v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(f[4 * i] * inv_scale),
+                                                sat448(f[4 * i + 1] * inv_scale), 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(f[4 * i + 2] * inv_scale),
+                                            sat448(f[4 * i + 3] * inv_scale), w, true);
+        v[i] = (unsigned)w;
+    }
+    return v;
+}
+
+// ------------------------------------------------------------ loads/stores
+// Vector at element e of a row starting at byte pointer `row`; nv in [0, EPV]
+// elements are valid.  Full vectors of aligned rows use one 128-bit access;
+// partial vectors and misaligned rows go element by element.  Invalid
+// elements read as code 0 (value 0).
+template <int DT, bool NT>
+__device__ __forceinline__ u32x4 load_vec(const char *row, int64_t e, int nv, bool aligned) {
+    constexpr int EPV = Io<DT>::EPV, B = Io<DT>::BYTES;
+    const char *p = row + e * B;
+    if (nv == EPV && aligned) {
+        if constexpr (NT)
+            return __builtin_nontemporal_load((const u32x4 *)p);
+        else
+            return *(const u32x4 *)p;
+    }
+    u32x4 v = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < EPV; ++i) {
+        if (i < nv) {
+            unsigned bits;
+            if constexpr (B == 4)
+                bits = *(const unsigned *)(p + 4 * i);
+            else if constexpr (B == 2)
+                bits = *(const unsigned short *)(p + 2 * i);
+            else
+                bits = *(const unsigned char *)(p + i);
+            constexpr int PER = 4 / B;  // elements per 32-bit word
+            v[i / PER] |= bits << (8 * B * (i % PER));
+        }
+    }
+    return v;
+}
+
+template <int DT>
+__device__ __forceinline__ void store_vec(char *row, int64_t e, int nv, bool aligned, u32x4 v) {
+    constexpr int EPV = Io<DT>::EPV, B = Io<DT>::BYTES;
+    char *p = row + e * B;
+    if (nv == EPV && aligned) {
+        __builtin_nontemporal_store(v, (u32x4 *)p);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < EPV; ++i) {
+        if (i < nv) {
+            constexpr int PER = 4 / B;
+            unsigned bits = v[i / PER] >> (8 * B * (i % PER));
+            if constexpr (B == 4)
+                *(unsigned *)(p + 4 * i) = bits;
+            else if constexpr (B == 2)
+                *(unsigned short *)(p + 2 * i) = (unsigned short)bits;
+            else
+                *(unsigned char *)(p + i) = (unsigned char)bits;
+        }
+    }
+}
+
+// Hides the contents of retained data registers from the optimiser between
+// passes over them, so each pass decodes the packed data again instead of the
+// compiler keeping every decoded FP32 value of the first pass alive.  Emits no
+// instruction.
+template <int V> __device__ __forceinline__ void opaque(u32x4 (&d)[V]) {
+#pragma unroll
+    for (int j = 0; j < V; ++j) asm volatile("" : "+v"(d[j]));
+}
+
+// -------------------------------------------------------- wave64 reduction
+// Partner value across lanes (lane ^ m) inside each 32-lane half: DPP quad
+// permutes for m = 1, 2 and ds_swizzle bit-mode xor for m = 4, 8, 16.
+template <int MASK> __device__ __forceinline__ float xor_lane(float v) {
+    int i = __float_as_int(v);
+    if constexpr (MASK == 1)
+        return __int_as_float(__builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
+    else if constexpr (MASK == 2)
+        return __int_as_float(__builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
+    else
+        return __int_as_float(__builtin_amdgcn_ds_swizzle(i, 0x1F | (MASK << 10)));
+}
+
+// Butterfly over the 32 lanes of each half, then lanes 0 and 32 merged in
+// that order; every lane returns the same (wave-uniform) tuple.
+template <int NV, class Merge>
+__device__ __forceinline__ void wave_reduce(float (&v)[NV], Merge merge) {
+    float o[NV];
+#define CREDIT_XSTEP(M)                                  \
+    _Pragma("unroll") for (int i = 0; i < NV; ++i) o[i] = xor_lane<M>(v[i]); \
+    merge(v, o);
+    CREDIT_XSTEP(1)
+    CREDIT_XSTEP(2)
+    CREDIT_XSTEP(4)
+    CREDIT_XSTEP(8)
+    CREDIT_XSTEP(16)
+#undef CREDIT_XSTEP
+    float hi[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        hi[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 32));
+        v[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 0));
+    }
+    merge(v, hi);
+}
+
+// Workgroup reduction over NW waves.  `red` is LDS scratch of [2][NW][NV]
+// floats used alternately (parity flips each call), so one barrier per call
+// suffices.  Waves are merged in order 0..NW-1: the result is uniform.
+template <int NW, int NV, class Merge>
+__device__ __forceinline__ void block_reduce(float (&v)[NV], Merge merge, float *red, int &parity) {
+    wave_reduce<NV>(v, merge);
+    const int wave = threadIdx.x >> 6;
+    float *buf = red + parity * (NW * NV);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) buf[wave * NV + i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = buf[i];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+        float t[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) t[i] = buf[w * NV + i];
+        merge(v, t);
+    }
+    parity ^= 1;
+}
+
+// ------------------------------------------------------------- merges
+struct MergeSum {
+    template <int NV> __device__ __forceinline__ void operator()(float (&a)[NV], const float (&b)[NV]) const {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) a[i] += b[i];
+    }
+};
+struct MergeMax {
+    __device__ __forceinline__ void operator()(float (&a)[1], const float (&b)[1]) const { a[0] = fmaxf(a[0], b[0]); }
+};
+// Online softmax statistics in the base-2 domain: (c, s) with c = max of
+// x*log2(e) and s = sum of 2^(x*log2(e) - c).  Empty partials have c = -inf.
+struct MergeSoftmax {
+    __device__ __forceinline__ void operator()(float (&a)[2], const float (&b)[2]) const {
+        float c = fmaxf(a[0], b[0]);
+        float sa = a[0] == -INFINITY ? 0.f : a[1] * fast_exp2(a[0] - c);
+        float sb = b[0] == -INFINITY ? 0.f : b[1] * fast_exp2(b[0] - c);
+        a[0] = c;
+        a[1] = sa + sb;
+    }
+};
+// Chan et al. pairwise combination of (count, mean, M2).
+__device__ __forceinline__ void chan_merge(float &n, float &mean, float &m2, float nb, float meanb, float m2b) {
+    float nn = n + nb;
+    if (nb == 0.f) return;
+    if (n == 0.f) { n = nb; mean = meanb; m2 = m2b; return; }
+    float d = meanb - mean;
+    float wb = nb / nn;
+    mean = mean + d * wb;
+    m2 = m2 + m2b + d * d * n * wb;
+    n = nn;
+}
+struct MergeChan {
+    __device__ __forceinline__ void operator()(float (&a)[3], const float (&b)[3]) const {
+        chan_merge(a[0], a[1], a[2], b[0], b[1], b[2]);
+    }
+};
+
+// --------------------------------------------------- split-row exchange
+// Slot word: high 32 bits = launch epoch, low 32 bits = FP32 partial.  Each
+// word is written with one agent-scope atomic store and polled with
+// agent-scope atomic loads, so a reader that sees the current epoch also sees
+// the value that came with it; no fence and no counter reset are needed.
+__device__ __forceinline__ unsigned long long *slot_ptr(const RowArgs &a, int64_t row, int stage, int c, int j) {
+    return a.slots + (((row * kMaxStages + stage) * (int64_t)a.k + c) * kMaxQ + j);
+}
+
+// Publishes this workgroup's q partials for (row, stage) and gathers all k*q
+// partials of the row group into LDS `xb` (member-major).  Returns after a
+// barrier, with xb valid for every thread.  A bounded wait: after
+// a.spin_limit polls (or once another workgroup of this launch has reported a
+// timeout) the wait gives up, raises the error flag and proceeds.
+template <int Q>
+__device__ __forceinline__ void exchange(const RowArgs &a, int64_t row, int stage, int c,
+                                         const float (&mine)[Q], float *xb) {
+    const int tid = threadIdx.x;
+    const int kq = a.k * Q;
+    if (tid < Q) {
+        bool drop = (a.flags & F_TEST_DROP_PUBLISH) && c == 1;
+        if (!drop) {
+            unsigned long long w = ((unsigned long long)a.epoch << 32) | __float_as_uint(mine[tid]);
+            __hip_atomic_store(slot_ptr(a, row, stage, c, tid), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if (tid < 64) {
+        const int lane = tid;
+        bool ok = lane >= kq;
+        unsigned long long w = 0;
+        unsigned long long *p = ok ? nullptr : slot_ptr(a, row, stage, lane / Q, lane % Q);
+        unsigned spins = 0;
+        while (true) {
+            if (!ok) {
+                w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = (unsigned)(w >> 32) == a.epoch;
+            }
+            if (__all(ok)) break;
+            // The flag holds the epoch of the launch that timed out, so a stale
+            // flag from an earlier launch never cuts this launch's waits short.
+            if (++spins > a.spin_limit ||
+                __hip_atomic_load(a.errflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == a.epoch) {
+                if (lane == 0)
+                    __hip_atomic_store(a.errflag, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (lane < kq) xb[lane] = ok ? __uint_as_float((unsigned)w) : 0.f;
+    }
+    __syncthreads();
+}
+
+}  // namespace credit

@@ -1,0 +1,1402 @@
+// host.cpp -- the C ABI of libcredit: validation, plan resolution (legality,
+// persistent-grid geometry, workspace layout), launches, timing, the plan
+// selectors of Sec. III-D and the learned selector's training driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/credit.h"
+#include "kargs.h"
+
+namespace credit {
+const void *resident_kernel_softmax_fwd(int, int);
+const void *resident_kernel_ln_fwd(int, int);
+const void *resident_kernel_rms_fwd(int, int);
+const void *resident_kernel_softmax_bwd(int, int);
+const void *resident_kernel_ln_bwd(int, int);
+const void *resident_kernel_rms_bwd(int, int);
+const void *twopass_kernel_softmax_fwd(int, int);
+const void *twopass_kernel_ln_fwd(int, int);
+const void *twopass_kernel_rms_fwd(int, int);
+const void *twopass_kernel_softmax_bwd(int, int);
+const void *twopass_kernel_ln_bwd(int, int);
+const void *twopass_kernel_rms_bwd(int, int);
+const void *colreduce_kernel();
+const void *colstats_kernel(int, bool);
+const void *control_kernel();
+const void *zero_kernel();
+const void *fill_kernel();
+const void *copy_kernel();
+const void *encode_kernel(int);
+const void *decode_kernel(int);
+const void *mlp_kernel(int);
+}  // namespace credit
+
+using namespace credit;
+
+namespace {
+
+constexpr int kSplitKs[5] = {2, 4, 8, 16, 32};
+constexpr size_t kFlushBytes = (size_t)512 << 20;
+constexpr double kClockHz = 2.4e9;      // MI355X peak engine clock
+constexpr double kSlotBytes = 8.0;      // one exchange slot word
+constexpr double kSlotRate = 64.0;      // slot-store issue rate, bytes per cycle per CU
+constexpr int kDefaultCUs = 256;
+constexpr int kLdsBytes = 163840;
+constexpr int kMlpParams = CREDIT_NUM_FEATURES * CREDIT_MLP_HIDDEN + CREDIT_MLP_HIDDEN +
+                           CREDIT_MLP_HIDDEN * CREDIT_MLP_HIDDEN + CREDIT_MLP_HIDDEN +
+                           CREDIT_NUM_PLANS * CREDIT_MLP_HIDDEN + CREDIT_NUM_PLANS;
+
+std::atomic<uint32_t> g_epoch{1};
+uint32_t next_epoch() {
+    uint32_t e = g_epoch.fetch_add(1);
+    while (e == 0) e = g_epoch.fetch_add(1);
+    return e;
+}
+
+int kop(int op, int dir) { return op + 3 * dir; }
+int dt_bytes(int dt) { return dt == CREDIT_F32 ? 4 : dt == CREDIT_BF16 ? 2 : 1; }
+int dt_epv(int dt) { return 16 / dt_bytes(dt); }
+int ncp_of(int k_op) { return k_op == OP_LN_BWD ? 2 : k_op == OP_RMS_BWD ? 1 : 0; }
+bool two_inputs(int k_op) { return k_op >= OP_SOFTMAX_BWD; }
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+const void *resident_fn(int k_op, int dt, int vpt) {
+    switch (k_op) {
+    case OP_SOFTMAX_FWD: return resident_kernel_softmax_fwd(dt, vpt);
+    case OP_LN_FWD: return resident_kernel_ln_fwd(dt, vpt);
+    case OP_RMS_FWD: return resident_kernel_rms_fwd(dt, vpt);
+    case OP_SOFTMAX_BWD: return resident_kernel_softmax_bwd(dt, vpt);
+    case OP_LN_BWD: return resident_kernel_ln_bwd(dt, vpt);
+    case OP_RMS_BWD: return resident_kernel_rms_bwd(dt, vpt);
+    }
+    return nullptr;
+}
+const void *twopass_fn(int k_op, int dt, int block) {
+    switch (k_op) {
+    case OP_SOFTMAX_FWD: return twopass_kernel_softmax_fwd(dt, block);
+    case OP_LN_FWD: return twopass_kernel_ln_fwd(dt, block);
+    case OP_RMS_FWD: return twopass_kernel_rms_fwd(dt, block);
+    case OP_SOFTMAX_BWD: return twopass_kernel_softmax_bwd(dt, block);
+    case OP_LN_BWD: return twopass_kernel_ln_bwd(dt, block);
+    case OP_RMS_BWD: return twopass_kernel_rms_bwd(dt, block);
+    }
+    return nullptr;
+}
+
+// Host copy of the kernels' register model: waves per SIMD a resident kernel
+// is compiled for (used when no device is available to ask).
+int model_waves(int k_op, int dt, int vpt) {
+    int data = vpt * 4 * (two_inputs(k_op) ? 2 : 1) + ncp_of(k_op) * vpt * dt_epv(dt);
+    int work = 64 + (dt == CREDIT_FP8_E4M3 ? 32 : 0) + (k_op == OP_SOFTMAX_FWD || k_op == OP_SOFTMAX_BWD ? 0 : 16);
+    int w = 512 / (data + work);
+    return std::max(1, std::min(8, w));
+}
+
+// Number of exchange stages of a row (for the control kernel and the model).
+int stages_of(int k_op, int dt, bool recompute) {
+    int L = 1;
+    if (dt == CREDIT_FP8_E4M3 && k_op != OP_SOFTMAX_FWD) L += 1;
+    if (recompute && (k_op == OP_LN_BWD || k_op == OP_RMS_BWD)) L += 1;
+    return L;
+}
+
+struct Launch {
+    int variant = 0, k = 1;
+    const void *fn = nullptr;
+    int grid = 0, block = 0, vpt = 0, groups = 0, per_cu = 0;
+    size_t shmem = 0;
+    int64_t chunk = 0;
+    bool xcd = false;
+    int parts = 0, rowblocks = 0;  // dgamma/dbeta partial rows
+    size_t off_slots = 0, off_colpart = 0, off_stats = 0, ws_bytes = 0;
+};
+
+}  // namespace
+
+struct credit_handle_s {
+    int device = 0;
+    int cus = kDefaultCUs;
+    std::string arch;
+    hipStream_t stream = nullptr;  // timing stream
+    unsigned *errflag = nullptr;
+    credit_selector_t selector = CREDIT_SEL_FIXED;
+    bool selector_set = false;
+    int64_t spin_limit = 1 << 22;
+    bool drop_publish = false;
+    int64_t max_groups = 0;
+    std::recursive_mutex lock;
+    std::map<const void *, int> occ_cache;
+    std::map<std::tuple<int, int, int, int64_t, int64_t, int>, credit_plan_t> plan_cache;
+    // timing arena
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    char *flushbuf = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    float copy_gbps = 0.f;
+    // learned selector
+    bool has_model = false;
+    std::vector<float> params = std::vector<float>(kMlpParams, 0.f);
+    float mu[CREDIT_NUM_FEATURES] = {0};
+    float sd[CREDIT_NUM_FEATURES] = {0};
+};
+
+namespace {
+
+int occupancy(credit_handle_t h, const void *fn, int block, size_t shmem) {
+    if (!h) return -1;
+    auto it = h->occ_cache.find(fn);
+    if (it != h->occ_cache.end() && shmem == 0) return it->second;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, shmem) != hipSuccess) return 0;
+    if (shmem == 0) h->occ_cache[fn] = n;
+    return n;
+}
+
+// Resolves a plan into launch geometry and workspace layout.  Returns
+// CREDIT_ERR_UNSUPPORTED when the plan is illegal for the shape.
+credit_status_t resolve(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t plan,
+                        bool recompute, Launch &L) {
+    L = Launch();
+    L.variant = plan.variant;
+    const int epv = dt_epv(dt);
+    const int64_t nvec = (N + epv - 1) / epv;
+    const int cus = h ? h->cus : kDefaultCUs;
+    const int ncp = ncp_of(k_op);
+    if (plan.variant == CREDIT_TWO_PASS) {
+        if (plan.k != 1) return CREDIT_ERR_UNSUPPORTED;
+        L.k = 1;
+        L.block = nvec >= 4096 ? 1024 : 256;
+        L.fn = twopass_fn(k_op, dt, L.block);
+        if (!L.fn) return CREDIT_ERR_UNSUPPORTED;
+        int occ = h ? occupancy(h, L.fn, L.block, 0) : std::max(1, 2048 / L.block);
+        if (occ <= 0) return CREDIT_ERR_HIP;
+        L.per_cu = occ;
+        L.grid = (int)std::min<int64_t>(M, (int64_t)occ * cus);
+        L.groups = L.grid;
+        size_t off = 256;  // error/reserved header
+        if (ncp) {
+            int64_t colblocks = (nvec + 255) / 256;
+            L.rowblocks = (int)std::max<int64_t>(1, std::min<int64_t>(M, (2048 + colblocks - 1) / colblocks));
+            L.parts = L.rowblocks;
+            L.off_colpart = off;
+            off = align256(off + (size_t)L.rowblocks * ncp * N * 4);
+            L.off_stats = off;
+            off = align256(off + (size_t)2 * M * 4);
+        }
+        L.ws_bytes = off;
+        return CREDIT_OK;
+    }
+    int k = plan.k;
+    if (plan.variant == CREDIT_ROW_RESIDENT) {
+        if (k != 1) return CREDIT_ERR_UNSUPPORTED;
+    } else if (plan.variant == CREDIT_SPLIT_ROW) {
+        bool ok = false;
+        for (int kk : kSplitKs) ok |= kk == k;
+        if (!ok) return CREDIT_ERR_UNSUPPORTED;
+    } else {
+        return CREDIT_ERR_INVALID_ARG;
+    }
+    L.k = k;
+    const int64_t cvec = (nvec + k - 1) / k;
+    const int64_t need = (cvec + kBlockThreads - 1) / kBlockThreads;
+    int vpt = 0;
+    for (int v : kVpts)
+        if (v >= need && v <= max_vpt(k_op, dt)) { vpt = v; break; }
+    if (!vpt) return CREDIT_ERR_UNSUPPORTED;  // slice exceeds register capacity (Eq. (3))
+    L.vpt = vpt;
+    L.chunk = cvec * epv;
+    L.block = kBlockThreads;
+    L.fn = resident_fn(k_op, dt, vpt);
+    if (!L.fn) return CREDIT_ERR_UNSUPPORTED;
+    int occ = h ? occupancy(h, L.fn, L.block, 0) : model_waves(k_op, dt, vpt);
+    if (occ <= 0) return h ? CREDIT_ERR_HIP : CREDIT_ERR_UNSUPPORTED;
+    L.per_cu = occ;
+    int64_t cap = (int64_t)occ * cus;
+    int64_t gmax = cap / k;
+    if (h && h->max_groups > 0) gmax = std::min<int64_t>(gmax, h->max_groups);
+    if (gmax < 1) return CREDIT_ERR_UNSUPPORTED;  // k members cannot be co-resident
+    int64_t groups = std::min<int64_t>(std::max<int64_t>(M, 1), gmax);
+    if (k > 1 && groups >= 8) {
+        groups = groups / 8 * 8;
+        L.xcd = true;
+    }
+    L.groups = (int)groups;
+    L.grid = (int)(groups * k);
+    size_t off = 256;
+    if (k > 1) {
+        L.off_slots = off;
+        off = align256(off + (size_t)M * kMaxStages * k * kMaxQ * 8);
+    }
+    if (ncp) {
+        L.parts = L.groups;
+        L.off_colpart = off;
+        off = align256(off + (size_t)L.groups * ncp * N * 4);
+    }
+    L.ws_bytes = off;
+    (void)recompute;
+    return CREDIT_OK;
+}
+
+hipError_t launch(const void *fn, int grid, int block, size_t shmem, hipStream_t s, void **args) {
+    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, shmem, s);
+}
+
+hipError_t zero_words(void *p, int64_t nwords, hipStream_t s) {
+    if (nwords <= 0) return hipSuccess;
+    int grid = (int)std::min<int64_t>(4096, (nwords + 255) / 256);
+    void *args[] = {&p, &nwords};
+    return launch(zero_kernel(), grid, 256, 0, s, args);
+}
+
+bool al16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+struct OpCall {
+    int k_op, dt;
+    int64_t M, N;
+    const void *in0, *in1;
+    int64_t ld0, ld1;
+    void *out;
+    int64_t ldo;
+    const float *s0, *s1;
+    float *so;
+    const float *gamma, *beta, *mean_in, *rstd_in;
+    float *mean_out, *rstd_out;
+    float *dgamma, *dbeta;
+    float eps;
+};
+
+credit_status_t pick_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t *out, float *pred);
+
+// Issues an operator with a resolved launch on `stream`.
+credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void *ws, hipStream_t stream,
+                      bool recompute) {
+    const int B = dt_bytes(c.dt);
+    RowArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.in0 = c.in0; a.in1 = c.in1; a.out = c.out;
+    a.ld0 = c.ld0; a.ld1 = c.ld1; a.ldo = c.ldo;
+    a.s0 = c.s0; a.s1 = c.s1; a.so = c.so;
+    a.gamma = c.gamma; a.beta = c.beta;
+    a.mean_in = c.mean_in; a.rstd_in = c.rstd_in;
+    a.mean_out = c.mean_out; a.rstd_out = c.rstd_out;
+    a.M = c.M; a.N = c.N;
+    a.eps = c.eps;
+    a.errflag = h->errflag;
+    a.safe = (const char *)h->errflag + 256;  // 256 zero bytes, never written
+    a.spin_limit = (unsigned)std::min<int64_t>(h->spin_limit, 0xffffffffLL);
+    int flags = 0;
+    if (al16(c.in0) && (c.ld0 * B) % 16 == 0) flags |= F_ALIGN0;
+    if (c.in1 && al16(c.in1) && (c.ld1 * B) % 16 == 0) flags |= F_ALIGN1;
+    if (al16(c.out) && (c.ldo * B) % 16 == 0) flags |= F_ALIGNO;
+    if ((!c.gamma || al16(c.gamma)) && (!c.beta || al16(c.beta))) flags |= F_ALIGNP;
+    if (recompute) flags |= F_RECOMPUTE;
+    if (h->drop_publish) flags |= F_TEST_DROP_PUBLISH;
+    char *w = (char *)ws;
+    const int ncp = ncp_of(c.k_op);
+    hipError_t e = hipSuccess;
+    if (L.variant == CREDIT_TWO_PASS) {
+        a.k = 1;
+        a.groups = L.grid;
+        a.chunk = c.N;
+        if (ncp && recompute) {
+            a.mean_out = (float *)(w + L.off_stats);
+            a.rstd_out = a.mean_out + c.M;
+        }
+        a.flags = flags;
+        void *args[] = {&a};
+        e = launch(L.fn, L.grid, L.block, 0, stream, args);
+        if (e != hipSuccess) return CREDIT_ERR_HIP;
+        if (ncp && (c.dgamma || c.dbeta)) {
+            RowArgs b = a;
+            if (recompute) {
+                b.mean_in = a.mean_out;
+                b.rstd_in = a.rstd_out;
+            }
+            b.colpart = (float *)(w + L.off_colpart);
+            int epv = dt_epv(c.dt);
+            int64_t nvec = (c.N + epv - 1) / epv;
+            int rb = L.rowblocks;
+            void *args2[] = {&b, &rb};
+            e = hipLaunchKernel(colstats_kernel(c.dt, c.k_op == OP_LN_BWD), dim3((unsigned)((nvec + 255) / 256), rb),
+                                dim3(256), args2, 0, stream);
+            if (e != hipSuccess) return CREDIT_ERR_HIP;
+        }
+    } else {
+        a.k = L.k;
+        a.groups = L.groups;
+        a.chunk = L.chunk;
+        if (L.k > 1) {
+            a.slots = (unsigned long long *)(w + L.off_slots);
+            a.epoch = next_epoch();
+            if (L.xcd) flags |= F_XCD;
+        }
+        if (ncp) a.colpart = (float *)(w + L.off_colpart);
+        a.flags = flags;
+        void *args[] = {&a};
+        e = launch(L.fn, L.grid, L.block, 0, stream, args);
+        if (e != hipSuccess) return CREDIT_ERR_HIP;
+    }
+    if (ncp && (c.dgamma || c.dbeta)) {
+        const float *part = (const float *)(w + L.off_colpart);
+        int parts = L.parts;
+        int n_cp = ncp;
+        int64_t N = c.N;
+        float *o0 = c.dgamma, *o1 = c.dbeta;
+        void *args[] = {&part, &parts, &n_cp, &N, &o0, &o1};
+        e = launch(colreduce_kernel(), (int)((N + 255) / 256), 256, 0, stream, args);
+        if (e != hipSuccess) return CREDIT_ERR_HIP;
+    }
+    return CREDIT_OK;
+}
+
+credit_status_t run_op(credit_handle_t h, const OpCall &c, const credit_plan_t *plan, void *ws, size_t ws_bytes,
+                       void *stream, bool recompute) {
+    if (!h) return CREDIT_ERR_INVALID_ARG;
+    if (c.M < 0 || c.N <= 0) return CREDIT_ERR_INVALID_ARG;
+    if (c.dt < 0 || c.dt > 2) return CREDIT_ERR_INVALID_ARG;
+    if (c.ld0 < c.N || c.ldo < c.N || (two_inputs(c.k_op) && c.ld1 < c.N)) return CREDIT_ERR_INVALID_ARG;
+    if (c.M == 0) {
+        hipStream_t s = (hipStream_t)stream;
+        if (c.dgamma && zero_words(c.dgamma, c.N, s) != hipSuccess) return CREDIT_ERR_HIP;
+        if (c.dbeta && zero_words(c.dbeta, c.N, s) != hipSuccess) return CREDIT_ERR_HIP;
+        return CREDIT_OK;
+    }
+    if (!c.in0 || !c.out || (two_inputs(c.k_op) && !c.in1)) return CREDIT_ERR_INVALID_ARG;
+    if (c.dt == CREDIT_FP8_E4M3) {
+        if (!c.s0 || !c.so || (two_inputs(c.k_op) && !c.s1)) return CREDIT_ERR_INVALID_ARG;
+    }
+    const bool norm = c.k_op == OP_LN_FWD || c.k_op == OP_RMS_FWD || c.k_op == OP_LN_BWD || c.k_op == OP_RMS_BWD;
+    if (norm && !c.gamma) return CREDIT_ERR_INVALID_ARG;
+    if (c.k_op == OP_LN_FWD && !c.beta) return CREDIT_ERR_INVALID_ARG;
+    if ((c.k_op == OP_LN_BWD || c.k_op == OP_RMS_BWD) && !recompute && !c.rstd_in) return CREDIT_ERR_INVALID_ARG;
+    if (c.k_op == OP_LN_BWD && !recompute && !c.mean_in) return CREDIT_ERR_INVALID_ARG;
+    credit_plan_t p;
+    if (plan) {
+        p = *plan;
+    } else {
+        credit_status_t st = pick_plan(h, c.k_op, c.dt, c.M, c.N, &p, nullptr);
+        if (st != CREDIT_OK) return st;
+    }
+    Launch L;
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    credit_status_t st = resolve(h, c.k_op, c.dt, c.M, c.N, p, recompute, L);
+    if (st != CREDIT_OK) return st;
+    if (!ws || ws_bytes < L.ws_bytes) return CREDIT_ERR_WORKSPACE;
+    return issue(h, c, L, ws, (hipStream_t)stream, recompute);
+}
+
+// ------------------------------------------------------------ static analysis
+// Byte accounting of Eq. (4) for the two-pass schedule: each statistics stage
+// streams the resident inputs; the output pass streams them again and writes.
+credit_workload_t workload(int k_op, int dt, bool recompute) {
+    credit_workload_t w;
+    std::memset(&w, 0, sizeof(w));
+    const float e = (float)dt_bytes(dt);
+    const int nin = two_inputs(k_op) ? 2 : 1;
+    int L = 0;
+    float stage_bytes = 0.f;
+    if (recompute && (k_op == OP_LN_BWD || k_op == OP_RMS_BWD)) {
+        w.q[L++] = k_op == OP_LN_BWD ? 2 : 1;
+        stage_bytes += e;  // reads x only
+    }
+    w.q[L++] = (k_op == OP_SOFTMAX_FWD || k_op == OP_LN_FWD || k_op == OP_LN_BWD) ? 2 : 1;
+    stage_bytes += nin * e;
+    if (dt == CREDIT_FP8_E4M3 && k_op != OP_SOFTMAX_FWD) {
+        w.q[L++] = 1;  // amax of the output before it can be scaled
+        stage_bytes += nin * e;
+    }
+    w.stages = L;
+    w.b_staged = nin * e + e;
+    w.b_base = stage_bytes + nin * e + e;
+    w.b_reread = w.b_base - w.b_staged;
+    w.b_keep = nin * e;
+    return w;
+}
+
+// Eq. (9) with MI355X terms for every split factor.  t_ctrl_us[i] is the
+// control-kernel excess for kSplitKs[i].
+void model_delta(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, double t_base_us, const float *t_ctrl_us,
+                 float *out) {
+    credit_workload_t w = workload(k_op, dt, false);
+    const double t_save = t_base_us * w.b_reread / w.b_base;  // Eq. (7)
+    int sumq = 0;
+    for (int l = 0; l < w.stages; ++l) sumq += w.q[l];
+    for (int i = 0; i < 5; ++i) {
+        Launch L;
+        credit_plan_t p = {CREDIT_SPLIT_ROW, kSplitKs[i]};
+        if (resolve(h, k_op, dt, M, N, p, false, L) != CREDIT_OK) {
+            out[i] = -INFINITY;
+            continue;
+        }
+        const int64_t W = (M + L.groups - 1) / L.groups;  // waves of row groups (Eq. (8))
+        const double t_replay = 0.0;                      // slices replay from registers
+        const double t_deposit = 0.0;                     // the deposit is the load itself
+        const double t_x = kSlotBytes * W * (L.k - 1) * sumq / (kClockHz * kSlotRate) * 1e6;
+        out[i] = (float)(t_save - t_ctrl_us[i] - t_replay - t_deposit - t_x);
+    }
+}
+
+// ---------------------------------------------------------------- timing
+struct Bufs {
+    char *in0, *in1, *out, *ws;
+    float *s0, *s1, *so, *gamma, *beta, *mean, *rstd, *dgamma, *dbeta;
+    size_t ws_bytes;
+};
+
+credit_status_t ensure_arena(credit_handle_t h, size_t bytes) {
+    if (h->arena_bytes >= bytes && h->flushbuf) return CREDIT_OK;
+    if (h->arena) hipFree(h->arena);
+    h->arena = nullptr;
+    h->arena_bytes = 0;
+    size_t want = std::max(bytes, (size_t)64 << 20);
+    if (hipMalloc(&h->arena, want) != hipSuccess) {
+        h->arena = nullptr;
+        hipGetLastError();
+        return CREDIT_ERR_HIP;
+    }
+    h->arena_bytes = want;
+    if (!h->flushbuf && hipMalloc(&h->flushbuf, kFlushBytes) != hipSuccess) {
+        h->flushbuf = nullptr;
+        hipGetLastError();
+        return CREDIT_ERR_HIP;
+    }
+    // deterministic contents: inputs valid for every dtype, workspace zero
+    int64_t nwords = (int64_t)(want / 4);
+    unsigned seed = 12345u;
+    int dt = CREDIT_F32;
+    void *p = h->arena;
+    void *args[] = {&p, &nwords, &seed, &dt};
+    if (launch(fill_kernel(), 4096, 256, 0, h->stream, args) != hipSuccess) return CREDIT_ERR_HIP;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+    return CREDIT_OK;
+}
+
+// Lays out the buffers of one operator call in the arena and fills them.
+credit_status_t prepare(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, size_t ws_bytes, Bufs &b) {
+    const size_t mat = align256((size_t)M * N * dt_bytes(dt));
+    const size_t vecM = align256((size_t)M * 4), vecN = align256((size_t)N * 4);
+    size_t total = mat * 3 + vecM * 5 + vecN * 4 + align256(ws_bytes);
+    credit_status_t st = ensure_arena(h, total);
+    if (st != CREDIT_OK) return st;
+    char *p = h->arena;
+    b.in0 = p; p += mat;
+    b.in1 = p; p += mat;
+    b.out = p; p += mat;
+    b.s0 = (float *)p; p += vecM;
+    b.s1 = (float *)p; p += vecM;
+    b.so = (float *)p; p += vecM;
+    b.mean = (float *)p; p += vecM;
+    b.rstd = (float *)p; p += vecM;
+    b.gamma = (float *)p; p += vecN;
+    b.beta = (float *)p; p += vecN;
+    b.dgamma = (float *)p; p += vecN;
+    b.dbeta = (float *)p; p += vecN;
+    b.ws = p;
+    b.ws_bytes = ws_bytes;
+    // inputs in the dtype's format; scales / statistics as plain FP32
+    int64_t wmat = (int64_t)(2 * mat / 4);
+    unsigned seed = 7u;
+    void *pin = b.in0;
+    void *a1[] = {&pin, &wmat, &seed, &dt};
+    if (launch(fill_kernel(), 4096, 256, 0, h->stream, a1) != hipSuccess) return CREDIT_ERR_HIP;
+    if (zero_words(b.ws, (int64_t)(align256(ws_bytes) / 4), h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+    (void)k_op;
+    return CREDIT_OK;
+}
+
+OpCall call_for(int k_op, int dt, int64_t M, int64_t N, const Bufs &b) {
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = k_op; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = b.in0; c.in1 = two_inputs(k_op) ? b.in1 : nullptr;
+    c.ld0 = c.ld1 = c.ldo = N;
+    c.out = b.out;
+    c.s0 = b.s0; c.s1 = b.s1; c.so = b.so;
+    c.gamma = b.gamma; c.beta = b.beta;
+    c.mean_in = b.mean; c.rstd_in = b.rstd;
+    c.dgamma = b.dgamma; c.dbeta = b.dbeta;
+    c.eps = 1e-5f;
+    return c;
+}
+
+float median(std::vector<float> v) {
+    std::sort(v.begin(), v.end());
+    size_t n = v.size();
+    return n % 2 ? v[n / 2] : 0.5f * (v[n / 2 - 1] + v[n / 2]);
+}
+
+credit_status_t flush(credit_handle_t h) {
+    return zero_words(h->flushbuf, (int64_t)(kFlushBytes / 4), h->stream) == hipSuccess ? CREDIT_OK : CREDIT_ERR_HIP;
+}
+
+template <class F> credit_status_t time_median(credit_handle_t h, int reps, int do_flush, F issue_fn, float *us) {
+    std::vector<float> t;
+    for (int r = -3; r < reps; ++r) {
+        if (do_flush && flush(h) != CREDIT_OK) return CREDIT_ERR_HIP;
+        if (hipEventRecord(h->ev0, h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+        credit_status_t st = issue_fn();
+        if (st != CREDIT_OK) return st;
+        if (hipEventRecord(h->ev1, h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+        if (hipEventSynchronize(h->ev1) != hipSuccess) return CREDIT_ERR_HIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->ev0, h->ev1) != hipSuccess) return CREDIT_ERR_HIP;
+        if (r >= 0) t.push_back(ms * 1000.f);
+    }
+    *us = median(t);
+    return CREDIT_OK;
+}
+
+credit_status_t time_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t p, int reps,
+                          int do_flush, float *us) {
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    Launch L;
+    credit_status_t st = resolve(h, k_op, dt, M, N, p, false, L);
+    if (st != CREDIT_OK) return st;
+    Bufs b;
+    st = prepare(h, k_op, dt, M, N, L.ws_bytes, b);
+    if (st != CREDIT_OK) return st;
+    OpCall c = call_for(k_op, dt, M, N, b);
+    return time_median(h, reps > 0 ? reps : 15, do_flush, [&]() { return issue(h, c, L, b.ws, h->stream, false); }, us);
+}
+
+credit_status_t time_control(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, int k, int reps, float *us) {
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    Launch L;
+    credit_plan_t p = {k == 1 ? CREDIT_ROW_RESIDENT : CREDIT_SPLIT_ROW, k};
+    credit_status_t st = resolve(h, k_op, dt, M, N, p, false, L);
+    if (st != CREDIT_OK && k == 1) {
+        p = {CREDIT_TWO_PASS, 1};
+        st = resolve(h, k_op, dt, M, N, p, false, L);
+        if (st == CREDIT_OK) {  // one-workgroup control at the two-pass grid, 256 threads
+            L.block = kBlockThreads;
+            L.groups = L.grid;
+        }
+    }
+    if (st != CREDIT_OK) return st;
+    // pin the control kernel to the same workgroups per CU
+    size_t shmem = (size_t)(kLdsBytes / std::max(1, L.per_cu)) - 1024;
+    if (occupancy(h, control_kernel(), kBlockThreads, shmem) > L.per_cu) shmem += 512;
+    Bufs b;
+    st = prepare(h, k_op, dt, M, N, L.ws_bytes, b);
+    if (st != CREDIT_OK) return st;
+    RowArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.M = M; a.N = N; a.k = L.k; a.groups = L.groups;
+    a.slots = (unsigned long long *)(b.ws + L.off_slots);
+    a.errflag = h->errflag;
+    a.spin_limit = (unsigned)std::min<int64_t>(h->spin_limit, 0xffffffffLL);
+    int stages = stages_of(k_op, dt, false);
+    return time_median(h, reps > 0 ? reps : 15, 0,
+                       [&]() {
+                           a.epoch = next_epoch();
+                           a.flags = L.xcd ? F_XCD : 0;
+                           void *args[] = {&a, &stages};
+                           return launch(control_kernel(), L.grid, kBlockThreads, shmem, h->stream, args) == hipSuccess
+                                      ? CREDIT_OK
+                                      : CREDIT_ERR_HIP;
+                       },
+                       us);
+}
+
+credit_status_t copy_bw(credit_handle_t h, size_t bytes, int reps, float *gbps) {
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    bytes = bytes / 64 * 64;
+    credit_status_t st = ensure_arena(h, 2 * bytes);
+    if (st != CREDIT_OK) return st;
+    const void *src = h->arena;
+    void *dst = h->arena + bytes;
+    int64_t n = (int64_t)(bytes / 16);
+    int grid = h->cus * 8;
+    float us = 0.f;
+    st = time_median(h, reps > 0 ? reps : 15, 0,
+                     [&]() {
+                         void *args[] = {&src, &dst, &n};
+                         return launch(copy_kernel(), grid, 256, 0, h->stream, args) == hipSuccess ? CREDIT_OK
+                                                                                                  : CREDIT_ERR_HIP;
+                     },
+                     &us);
+    if (st != CREDIT_OK) return st;
+    *gbps = (float)(2.0 * bytes / (us * 1e-6) / 1e9);
+    return CREDIT_OK;
+}
+
+// -------------------------------------------------------------- selectors
+bool plan_ok(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t p) {
+    Launch L;
+    return resolve(h, k_op, dt, M, N, p, false, L) == CREDIT_OK;
+}
+
+credit_plan_t class_plan(int c) {
+    if (c == 0) return {CREDIT_TWO_PASS, 1};
+    if (c == 1) return {CREDIT_ROW_RESIDENT, 1};
+    return {CREDIT_SPLIT_ROW, kSplitKs[c - 2]};
+}
+
+credit_plan_t fixed_rule(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N) {
+    for (int c = 1; c < CREDIT_NUM_PLANS; ++c) {
+        credit_plan_t p = class_plan(c);
+        if (plan_ok(h, k_op, dt, M, N, p)) return p;
+    }
+    return class_plan(0);
+}
+
+void features(int k_op, int dt, int64_t M, int64_t N, float *f) {
+    const int op = k_op % 3, dir = k_op / 3;
+    for (int i = 0; i < CREDIT_NUM_FEATURES; ++i) f[i] = 0.f;
+    f[op] = 1.f;
+    f[3] = (float)dir;
+    f[4 + dt] = 1.f;
+    const double e = dt_bytes(dt);
+    const int nin = two_inputs(k_op) ? 2 : 1;
+    f[7] = (float)std::log2((double)std::max<int64_t>(M, 1));
+    f[8] = (float)std::log2((double)N);
+    f[9] = (float)std::log2((double)N * e * nin);
+    f[10] = (float)std::log2((double)std::max<int64_t>(M, 1) * N * e * (nin + 1));
+    f[11] = (float)std::log2(std::max(1.0, (double)M / kDefaultCUs));
+}
+
+credit_status_t mlp_predict_dev(credit_handle_t h, const float *feats, int64_t n, float *logits);
+
+credit_status_t analytic_pick(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, bool peak,
+                              credit_plan_t *out, float *pred) {
+    credit_plan_t base = {CREDIT_ROW_RESIDENT, 1};
+    if (!plan_ok(h, k_op, dt, M, N, base)) base = {CREDIT_TWO_PASS, 1};
+    float tb = 0.f;
+    credit_status_t st;
+    credit_workload_t w = workload(k_op, dt, false);
+    if (peak) {
+        if (h->copy_gbps <= 0.f) {
+            st = copy_bw(h, (size_t)1 << 30, 7, &h->copy_gbps);
+            if (st != CREDIT_OK) return st;
+        }
+        // Table-V row-1 analogue: the baseline priced at copy bandwidth
+        tb = (float)((double)M * N * w.b_base / (h->copy_gbps * 1e9) * 1e6);
+    } else {
+        st = time_plan(h, k_op, dt, M, N, base, 15, 1, &tb);
+        if (st != CREDIT_OK) return st;
+    }
+    float c1 = 0.f;
+    st = time_control(h, k_op, dt, M, N, 1, 7, &c1);
+    if (st != CREDIT_OK) return st;
+    float ctrl[5];
+    for (int i = 0; i < 5; ++i) {
+        credit_plan_t p = {CREDIT_SPLIT_ROW, kSplitKs[i]};
+        ctrl[i] = 0.f;
+        if (!plan_ok(h, k_op, dt, M, N, p)) continue;
+        float ck = 0.f;
+        st = time_control(h, k_op, dt, M, N, kSplitKs[i], 7, &ck);
+        if (st != CREDIT_OK) return st;
+        ctrl[i] = std::max(0.f, ck - c1);
+    }
+    float delta[5];
+    model_delta(h, k_op, dt, M, N, tb, ctrl, delta);
+    if (peak) {
+        // serialized staging: the deposit is charged in full
+        const double dep = (double)M * N * w.b_keep / (h->copy_gbps * 1e9) * 1e6;
+        for (float &d : delta) d = (float)(d - dep);
+    }
+    int best = -1;
+    for (int i = 0; i < 5; ++i)
+        if (delta[i] > 0.f && (best < 0 || delta[i] > delta[best])) best = i;
+    if (best >= 0) {
+        *out = {CREDIT_SPLIT_ROW, kSplitKs[best]};
+        if (pred) *pred = tb - delta[best];
+    } else {
+        *out = base;
+        if (pred) *pred = tb;
+    }
+    return CREDIT_OK;
+}
+
+credit_status_t exhaustive_pick(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t *out,
+                                float *pred) {
+    float best = INFINITY;
+    for (int c = 0; c < CREDIT_NUM_PLANS; ++c) {
+        credit_plan_t p = class_plan(c);
+        if (!plan_ok(h, k_op, dt, M, N, p)) continue;
+        float t = 0.f;
+        credit_status_t st = time_plan(h, k_op, dt, M, N, p, 15, 1, &t);
+        if (st != CREDIT_OK) return st;
+        if (t < best) {
+            best = t;
+            *out = p;
+        }
+    }
+    if (pred) *pred = best;
+    return std::isfinite(best) ? CREDIT_OK : CREDIT_ERR_UNSUPPORTED;
+}
+
+credit_status_t learned_pick(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t *out) {
+    float f[CREDIT_NUM_FEATURES], logits[CREDIT_NUM_PLANS];
+    features(k_op, dt, M, N, f);
+    credit_status_t st = mlp_predict_dev(h, f, 1, logits);
+    if (st != CREDIT_OK) return st;
+    int best = -1;
+    for (int c = 0; c < CREDIT_NUM_PLANS; ++c) {
+        if (!plan_ok(h, k_op, dt, M, N, class_plan(c))) continue;
+        if (best < 0 || logits[c] > logits[best]) best = c;
+    }
+    if (best < 0) return CREDIT_ERR_UNSUPPORTED;
+    *out = class_plan(best);
+    return CREDIT_OK;
+}
+
+credit_status_t pick_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t *out,
+                          float *pred) {
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    credit_selector_t sel = h->selector;
+    if (!h->selector_set) sel = h->has_model ? CREDIT_SEL_LEARNED : CREDIT_SEL_FIXED;
+    auto key = std::make_tuple(k_op, dt, (int)sel, M, N, 0);
+    if (!pred) {
+        auto it = h->plan_cache.find(key);
+        if (it != h->plan_cache.end()) {
+            *out = it->second;
+            return CREDIT_OK;
+        }
+    }
+    if (pred) *pred = -1.f;
+    credit_status_t st = CREDIT_OK;
+    switch (sel) {
+    case CREDIT_SEL_LEARNED:
+        if (h->has_model) {
+            st = learned_pick(h, k_op, dt, M, N, out);
+            if (st == CREDIT_OK) break;
+        }
+        st = analytic_pick(h, k_op, dt, M, N, false, out, pred);
+        break;
+    case CREDIT_SEL_ANALYTIC: st = analytic_pick(h, k_op, dt, M, N, false, out, pred); break;
+    case CREDIT_SEL_PEAK: st = analytic_pick(h, k_op, dt, M, N, true, out, pred); break;
+    case CREDIT_SEL_EXHAUSTIVE: st = exhaustive_pick(h, k_op, dt, M, N, out, pred); break;
+    default: *out = fixed_rule(h, k_op, dt, M, N); break;
+    }
+    if (st == CREDIT_OK) h->plan_cache[key] = *out;
+    return st;
+}
+
+// ------------------------------------------------------------------- MLP
+const int kH = CREDIT_MLP_HIDDEN, kF = CREDIT_NUM_FEATURES, kC = CREDIT_NUM_PLANS;
+const size_t oW1 = 0, ob1 = oW1 + kH * kF, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH, ob3 = oW3 + kC * kH;
+
+struct MlpDev {
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    float *raw = nullptr, *z = nullptr, *h1 = nullptr, *h2 = nullptr, *lg = nullptr, *tg = nullptr;
+    float *dl = nullptr, *dh2 = nullptr, *dh1 = nullptr, *loss = nullptr, *lmean = nullptr, *mu = nullptr,
+          *sd = nullptr, *dz = nullptr;
+    uint8_t *mask = nullptr;
+    int64_t n = 0;
+    std::vector<void *> owned;
+    ~MlpDev() {
+        for (void *q : owned) hipFree(q);
+    }
+    template <class T> bool alloc(T *&q, size_t count) {
+        if (hipMalloc((void **)&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return false;
+        owned.push_back(q);
+        return true;
+    }
+    bool init(int64_t n_) {
+        n = n_;
+        return alloc(p, kMlpParams) && alloc(g, kMlpParams) && alloc(m, kMlpParams) && alloc(v, kMlpParams) &&
+               alloc(raw, n * kF) && alloc(z, n * kF) && alloc(h1, n * kH) && alloc(h2, n * kH) &&
+               alloc(lg, n * kC) && alloc(tg, n * kC) && alloc(dl, n * kC) && alloc(dh2, n * kH) &&
+               alloc(dh1, n * kH) && alloc(loss, n) && alloc(lmean, 1) && alloc(mu, kF) && alloc(sd, kF) &&
+               alloc(dz, n * kF) && alloc(mask, n * kC);
+    }
+};
+
+int blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + 255) / 256); }
+
+hipError_t mlp_forward(MlpDev &d, hipStream_t s) {
+    int64_t n = d.n;
+    int nf = kF;
+    hipError_t e;
+    {
+        void *a[] = {&d.raw, &d.mu, &d.sd, &d.z, &n, &nf};
+        if ((e = launch(mlp_kernel(0), blocks(n * kF), 256, 0, s, a)) != hipSuccess) return e;
+    }
+    auto dense = [&](float *in, size_t ow, size_t ob, float *out, int I, int O, int relu) {
+        float *W = d.p + ow, *b = d.p + ob;
+        void *a[] = {&in, &W, &b, &out, &n, &I, &O, &relu};
+        return launch(mlp_kernel(1), blocks(n * O), 256, 0, s, a);
+    };
+    if ((e = dense(d.z, oW1, ob1, d.h1, kF, kH, 1)) != hipSuccess) return e;
+    if ((e = dense(d.h1, oW2, ob2, d.h2, kH, kH, 1)) != hipSuccess) return e;
+    return dense(d.h2, oW3, ob3, d.lg, kH, kC, 0);
+}
+
+hipError_t mlp_backward(MlpDev &d, hipStream_t s) {
+    int64_t n = d.n;
+    int C = kC;
+    hipError_t e;
+    {
+        void *a[] = {&d.lg, &d.tg, &d.mask, &d.dl, &d.loss, &n, &C};
+        if ((e = launch(mlp_kernel(2), blocks(n), 256, 0, s, a)) != hipSuccess) return e;
+    }
+    {
+        void *a[] = {&d.loss, &n, &d.lmean};
+        if ((e = launch(mlp_kernel(3), 1, 256, 0, s, a)) != hipSuccess) return e;
+    }
+    auto bw = [&](float *dout, float *in, size_t ow, size_t ob, int I, int O) {
+        float *dW = d.g + ow, *db = d.g + ob;
+        void *a[] = {&dout, &in, &dW, &db, &n, &I, &O};
+        return launch(mlp_kernel(4), blocks((int64_t)O * (I + 1)), 256, 0, s, a);
+    };
+    auto bi = [&](float *dout, size_t ow, float *act, float *din, int I, int O) {
+        float *W = d.p + ow;
+        void *a[] = {&dout, &W, &act, &din, &n, &I, &O};
+        return launch(mlp_kernel(5), blocks(n * I), 256, 0, s, a);
+    };
+    if ((e = bw(d.dl, d.h2, oW3, ob3, kH, kC)) != hipSuccess) return e;
+    if ((e = bi(d.dl, oW3, d.h2, d.dh2, kH, kC)) != hipSuccess) return e;
+    if ((e = bw(d.dh2, d.h1, oW2, ob2, kH, kH)) != hipSuccess) return e;
+    if ((e = bi(d.dh2, oW2, d.h1, d.dh1, kH, kH)) != hipSuccess) return e;
+    return bw(d.dh1, d.z, oW1, ob1, kF, kH);
+}
+
+bool mlp_upload(credit_handle_t h, MlpDev &d, const float *feats, const float *targets, const uint8_t *mask) {
+    int64_t n = d.n;
+    bool ok = hipMemcpy(d.p, h->params.data(), kMlpParams * 4, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(d.raw, feats, n * kF * 4, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(d.mu, h->mu, kF * 4, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(d.sd, h->sd, kF * 4, hipMemcpyHostToDevice) == hipSuccess;
+    if (ok && targets) ok = hipMemcpy(d.tg, targets, n * kC * 4, hipMemcpyHostToDevice) == hipSuccess;
+    if (ok && mask) ok = hipMemcpy(d.mask, mask, n * kC, hipMemcpyHostToDevice) == hipSuccess;
+    return ok;
+}
+
+credit_status_t mlp_predict_dev(credit_handle_t h, const float *feats, int64_t n, float *logits) {
+    MlpDev d;
+    if (!d.init(n)) return CREDIT_ERR_HIP;
+    if (!mlp_upload(h, d, feats, nullptr, nullptr)) return CREDIT_ERR_HIP;
+    if (mlp_forward(d, h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+    if (hipMemcpy(logits, d.lg, n * kC * 4, hipMemcpyDeviceToHost) != hipSuccess) return CREDIT_ERR_HIP;
+    return CREDIT_OK;
+}
+
+// splitmix64 + Box-Muller: a portable seeded normal generator for He init.
+struct Rng {
+    uint64_t s;
+    uint64_t next() {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+    double normal() { return std::sqrt(-2.0 * std::log(uniform())) * std::cos(6.283185307179586 * uniform()); }
+};
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char *credit_status_string(credit_status_t s) {
+    switch (s) {
+    case CREDIT_OK: return "CREDIT_OK";
+    case CREDIT_ERR_INVALID_ARG: return "CREDIT_ERR_INVALID_ARG";
+    case CREDIT_ERR_UNSUPPORTED: return "CREDIT_ERR_UNSUPPORTED";
+    case CREDIT_ERR_WORKSPACE: return "CREDIT_ERR_WORKSPACE";
+    case CREDIT_ERR_HIP: return "CREDIT_ERR_HIP";
+    case CREDIT_ERR_TIMEOUT: return "CREDIT_ERR_TIMEOUT";
+    case CREDIT_ERR_MODEL: return "CREDIT_ERR_MODEL";
+    }
+    return "CREDIT_ERR_UNKNOWN";
+}
+
+const char *credit_version(void) { return "credit-mi355x 0.1.0 (gfx950)"; }
+
+credit_status_t credit_create(int device, credit_handle_t *out) {
+    if (!out) return CREDIT_ERR_INVALID_ARG;
+    *out = nullptr;
+    try {
+        hipDeviceProp_t prop;
+        if (hipSetDevice(device) != hipSuccess) return CREDIT_ERR_HIP;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess) return CREDIT_ERR_HIP;
+        credit_handle_t h = new credit_handle_s();
+        h->device = device;
+        h->cus = prop.multiProcessorCount;
+        h->arch = prop.gcnArchName;
+        if (hipStreamCreate(&h->stream) != hipSuccess || hipMalloc(&h->errflag, 512) != hipSuccess ||
+            hipMemset(h->errflag, 0, 512) != hipSuccess || hipEventCreate(&h->ev0) != hipSuccess ||
+            hipEventCreate(&h->ev1) != hipSuccess) {
+            credit_destroy(h);
+            return CREDIT_ERR_HIP;
+        }
+        *out = h;
+        return CREDIT_OK;
+    } catch (...) {
+        return CREDIT_ERR_HIP;
+    }
+}
+
+credit_status_t credit_destroy(credit_handle_t h) {
+    if (!h) return CREDIT_ERR_INVALID_ARG;
+    if (h->stream) hipStreamSynchronize(h->stream);
+    if (h->arena) hipFree(h->arena);
+    if (h->flushbuf) hipFree(h->flushbuf);
+    if (h->errflag) hipFree(h->errflag);
+    if (h->ev0) hipEventDestroy(h->ev0);
+    if (h->ev1) hipEventDestroy(h->ev1);
+    if (h->stream) hipStreamDestroy(h->stream);
+    delete h;
+    return CREDIT_OK;
+}
+
+credit_status_t credit_set_selector(credit_handle_t h, credit_selector_t s) {
+    if (!h || (int)s < 0 || (int)s > 4) return CREDIT_ERR_INVALID_ARG;
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    h->selector = s;
+    h->selector_set = true;
+    return CREDIT_OK;
+}
+
+static bool valid_enum(credit_op_t op, credit_dir_t dir, credit_dtype_t dt) {
+    return (int)op >= 0 && (int)op <= 2 && (int)dir >= 0 && (int)dir <= 1 && (int)dt >= 0 && (int)dt <= 2;
+}
+
+credit_status_t credit_workspace_size(credit_handle_t h, credit_op_t op, credit_dir_t dir, credit_dtype_t dt,
+                                      int64_t M, int64_t N, const credit_plan_t *plan, size_t *bytes) {
+    if (!h || !bytes || !valid_enum(op, dir, dt) || M < 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
+    try {
+        credit_plan_t p;
+        if (plan) {
+            p = *plan;
+        } else if (M == 0) {
+            p = {CREDIT_TWO_PASS, 1};
+        } else {
+            credit_status_t st = pick_plan(h, kop(op, dir), dt, M, N, &p, nullptr);
+            if (st != CREDIT_OK) return st;
+        }
+        Launch L;
+        std::lock_guard<std::recursive_mutex> g(h->lock);
+        credit_status_t st = resolve(h, kop(op, dir), dt, M, N, p, true, L);
+        if (st != CREDIT_OK) return st;
+        *bytes = L.ws_bytes;
+        return CREDIT_OK;
+    } catch (...) {
+        return CREDIT_ERR_HIP;
+    }
+}
+
+credit_status_t credit_plan_legal(credit_handle_t h, credit_op_t op, credit_dir_t dir, credit_dtype_t dt, int64_t M,
+                                  int64_t N, const credit_plan_t *plan) {
+    if (!plan || !valid_enum(op, dir, dt) || M < 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
+    Launch L;
+    if (h) {
+        std::lock_guard<std::recursive_mutex> g(h->lock);
+        return resolve(h, kop(op, dir), dt, M, N, *plan, false, L);
+    }
+    return resolve(nullptr, kop(op, dir), dt, M, N, *plan, false, L);
+}
+
+credit_status_t credit_plan_geometry(credit_handle_t h, credit_op_t op, credit_dir_t dir, credit_dtype_t dt,
+                                     int64_t M, int64_t N, const credit_plan_t *plan, int32_t *grid, int32_t *block,
+                                     int32_t *vpt, int32_t *per_cu) {
+    if (!plan || !valid_enum(op, dir, dt) || M < 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
+    Launch L;
+    credit_status_t st;
+    if (h) {
+        std::lock_guard<std::recursive_mutex> g(h->lock);
+        st = resolve(h, kop(op, dir), dt, M, N, *plan, false, L);
+    } else {
+        st = resolve(nullptr, kop(op, dir), dt, M, N, *plan, false, L);
+    }
+    if (st != CREDIT_OK) return st;
+    if (grid) *grid = L.grid;
+    if (block) *block = L.block;
+    if (vpt) *vpt = L.vpt;
+    if (per_cu) *per_cu = L.per_cu;
+    return CREDIT_OK;
+}
+
+credit_status_t credit_select(credit_handle_t h, credit_op_t op, credit_dir_t dir, credit_dtype_t dt, int64_t M,
+                              int64_t N, credit_plan_t *out, float *predicted_us) {
+    if (!h || !out || !valid_enum(op, dir, dt) || M <= 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
+    try {
+        float pred = -1.f;
+        credit_status_t st = pick_plan(h, kop(op, dir), dt, M, N, out, &pred);
+        if (predicted_us) *predicted_us = pred;
+        return st;
+    } catch (...) {
+        return CREDIT_ERR_HIP;
+    }
+}
+
+credit_status_t credit_softmax_fwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const void *x,
+                                   int64_t ldx, const float *x_scale, void *y, int64_t ldy, float *y_scale,
+                                   const credit_plan_t *plan, void *ws, size_t ws_bytes, void *stream) {
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = OP_SOFTMAX_FWD; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = x; c.ld0 = ldx; c.s0 = x_scale;
+    c.out = y; c.ldo = ldy; c.so = y_scale;
+    c.ld1 = N;
+    try { return run_op(h, c, plan, ws, ws_bytes, stream, false); } catch (...) { return CREDIT_ERR_HIP; }
+}
+
+credit_status_t credit_softmax_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const void *y,
+                                   int64_t ldy, const float *y_scale, const void *dy, int64_t lddy,
+                                   const float *dy_scale, void *dx, int64_t lddx, float *dx_scale,
+                                   const credit_plan_t *plan, void *ws, size_t ws_bytes, void *stream) {
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = OP_SOFTMAX_BWD; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = y; c.ld0 = ldy; c.s0 = y_scale;
+    c.in1 = dy; c.ld1 = lddy; c.s1 = dy_scale;
+    c.out = dx; c.ldo = lddx; c.so = dx_scale;
+    try { return run_op(h, c, plan, ws, ws_bytes, stream, false); } catch (...) { return CREDIT_ERR_HIP; }
+}
+
+credit_status_t credit_layernorm_fwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const void *x,
+                                     int64_t ldx, const float *x_scale, const float *gamma, const float *beta,
+                                     float eps, void *y, int64_t ldy, float *y_scale, float *mean, float *rstd,
+                                     const credit_plan_t *plan, void *ws, size_t ws_bytes, void *stream) {
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = OP_LN_FWD; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = x; c.ld0 = ldx; c.s0 = x_scale;
+    c.gamma = gamma; c.beta = beta; c.eps = eps;
+    c.out = y; c.ldo = ldy; c.so = y_scale;
+    c.mean_out = mean; c.rstd_out = rstd;
+    c.ld1 = N;
+    try { return run_op(h, c, plan, ws, ws_bytes, stream, false); } catch (...) { return CREDIT_ERR_HIP; }
+}
+
+credit_status_t credit_layernorm_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const void *x,
+                                     int64_t ldx, const float *x_scale, const void *dy, int64_t lddy,
+                                     const float *dy_scale, const float *gamma, const float *mean, const float *rstd,
+                                     float eps, void *dx, int64_t lddx, float *dx_scale, float *dgamma,
+                                     float *dbeta, const credit_plan_t *plan, void *ws, size_t ws_bytes,
+                                     void *stream) {
+    if ((mean == nullptr) != (rstd == nullptr)) return CREDIT_ERR_INVALID_ARG;
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = OP_LN_BWD; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = x; c.ld0 = ldx; c.s0 = x_scale;
+    c.in1 = dy; c.ld1 = lddy; c.s1 = dy_scale;
+    c.gamma = gamma; c.mean_in = mean; c.rstd_in = rstd; c.eps = eps;
+    c.out = dx; c.ldo = lddx; c.so = dx_scale;
+    c.dgamma = dgamma; c.dbeta = dbeta;
+    try { return run_op(h, c, plan, ws, ws_bytes, stream, mean == nullptr); } catch (...) { return CREDIT_ERR_HIP; }
+}
+
+credit_status_t credit_rmsnorm_fwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const void *x,
+                                   int64_t ldx, const float *x_scale, const float *gamma, float eps, void *y,
+                                   int64_t ldy, float *y_scale, float *rstd, const credit_plan_t *plan, void *ws,
+                                   size_t ws_bytes, void *stream) {
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = OP_RMS_FWD; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = x; c.ld0 = ldx; c.s0 = x_scale;
+    c.gamma = gamma; c.eps = eps;
+    c.out = y; c.ldo = ldy; c.so = y_scale;
+    c.rstd_out = rstd;
+    c.ld1 = N;
+    try { return run_op(h, c, plan, ws, ws_bytes, stream, false); } catch (...) { return CREDIT_ERR_HIP; }
+}
+
+credit_status_t credit_rmsnorm_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const void *x,
+                                   int64_t ldx, const float *x_scale, const void *dy, int64_t lddy,
+                                   const float *dy_scale, const float *gamma, const float *rstd, float eps, void *dx,
+                                   int64_t lddx, float *dx_scale, float *dgamma, const credit_plan_t *plan, void *ws,
+                                   size_t ws_bytes, void *stream) {
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = OP_RMS_BWD; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = x; c.ld0 = ldx; c.s0 = x_scale;
+    c.in1 = dy; c.ld1 = lddy; c.s1 = dy_scale;
+    c.gamma = gamma; c.rstd_in = rstd; c.eps = eps;
+    c.out = dx; c.ldo = lddx; c.so = dx_scale;
+    c.dgamma = dgamma;
+    try { return run_op(h, c, plan, ws, ws_bytes, stream, rstd == nullptr); } catch (...) { return CREDIT_ERR_HIP; }
+}
+
+credit_status_t credit_encode(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const float *x,
+                              const float *row_scale, void *out, void *stream) {
+    if (!h || M < 0 || N <= 0 || (int)dt < 0 || (int)dt > 2 || (M > 0 && (!x || !out))) return CREDIT_ERR_INVALID_ARG;
+    if (M == 0) return CREDIT_OK;
+    int64_t total = M * N;
+    int grid = (int)std::min<int64_t>(8192, (total + 255) / 256);
+    void *args[] = {&x, &row_scale, &out, &M, &N};
+    return launch(encode_kernel(dt), grid, 256, 0, (hipStream_t)stream, args) == hipSuccess ? CREDIT_OK : CREDIT_ERR_HIP;
+}
+
+credit_status_t credit_decode(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const void *in,
+                              const float *row_scale, float *out, void *stream) {
+    if (!h || M < 0 || N <= 0 || (int)dt < 0 || (int)dt > 2 || (M > 0 && (!in || !out))) return CREDIT_ERR_INVALID_ARG;
+    if (M == 0) return CREDIT_OK;
+    int64_t total = M * N;
+    int grid = (int)std::min<int64_t>(8192, (total + 255) / 256);
+    void *args[] = {&in, &row_scale, &out, &M, &N};
+    return launch(decode_kernel(dt), grid, 256, 0, (hipStream_t)stream, args) == hipSuccess ? CREDIT_OK : CREDIT_ERR_HIP;
+}
+
+credit_status_t credit_check_errors(credit_handle_t h, void *stream) {
+    if (!h) return CREDIT_ERR_INVALID_ARG;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return CREDIT_ERR_HIP;
+    if (hipGetLastError() != hipSuccess) return CREDIT_ERR_HIP;
+    unsigned flag = 0;
+    if (hipMemcpy(&flag, h->errflag, 4, hipMemcpyDeviceToHost) != hipSuccess) return CREDIT_ERR_HIP;
+    if (flag != 0) {
+        if (hipMemset(h->errflag, 0, 4) != hipSuccess) return CREDIT_ERR_HIP;
+        return CREDIT_ERR_TIMEOUT;
+    }
+    return CREDIT_OK;
+}
+
+credit_status_t credit_time_plan(credit_handle_t h, credit_op_t op, credit_dir_t dir, credit_dtype_t dt, int64_t M,
+                                 int64_t N, const credit_plan_t *plan, int reps, int do_flush, float *median_us) {
+    if (!h || !plan || !median_us || !valid_enum(op, dir, dt) || M <= 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
+    try {
+        return time_plan(h, kop(op, dir), dt, M, N, *plan, reps, do_flush, median_us);
+    } catch (...) {
+        return CREDIT_ERR_HIP;
+    }
+}
+
+credit_status_t credit_time_control(credit_handle_t h, credit_op_t op, credit_dir_t dir, credit_dtype_t dt,
+                                    int64_t M, int64_t N, int32_t k, int reps, float *median_us) {
+    if (!h || !median_us || !valid_enum(op, dir, dt) || M <= 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
+    try {
+        return time_control(h, kop(op, dir), dt, M, N, k, reps, median_us);
+    } catch (...) {
+        return CREDIT_ERR_HIP;
+    }
+}
+
+credit_status_t credit_copy_bandwidth(credit_handle_t h, size_t bytes, int reps, float *gbps) {
+    if (!h || !gbps || bytes < 4096) return CREDIT_ERR_INVALID_ARG;
+    try {
+        return copy_bw(h, bytes, reps, gbps);
+    } catch (...) {
+        return CREDIT_ERR_HIP;
+    }
+}
+
+credit_status_t credit_model_delta(credit_handle_t h, credit_op_t op, credit_dir_t dir, credit_dtype_t dt, int64_t M,
+                                   int64_t N, float t_base_us, const float *t_ctrl_us, float *out_delta_us) {
+    if (!t_ctrl_us || !out_delta_us || !valid_enum(op, dir, dt) || M <= 0 || N <= 0 || !(t_base_us >= 0.f))
+        return CREDIT_ERR_INVALID_ARG;
+    if (h) {
+        std::lock_guard<std::recursive_mutex> g(h->lock);
+        model_delta(h, kop(op, dir), dt, M, N, t_base_us, t_ctrl_us, out_delta_us);
+    } else {
+        model_delta(nullptr, kop(op, dir), dt, M, N, t_base_us, t_ctrl_us, out_delta_us);
+    }
+    return CREDIT_OK;
+}
+
+credit_status_t credit_workload_info(credit_op_t op, credit_dir_t dir, credit_dtype_t dt, int recompute_stats,
+                                     credit_workload_t *out) {
+    if (!out || !valid_enum(op, dir, dt)) return CREDIT_ERR_INVALID_ARG;
+    *out = workload(kop(op, dir), dt, recompute_stats != 0);
+    return CREDIT_OK;
+}
+
+credit_status_t credit_plan_of_class(int32_t c, credit_plan_t *out) {
+    if (!out || c < 0 || c >= CREDIT_NUM_PLANS) return CREDIT_ERR_INVALID_ARG;
+    *out = class_plan(c);
+    return CREDIT_OK;
+}
+
+credit_status_t credit_features(credit_op_t op, credit_dir_t dir, credit_dtype_t dt, int64_t M, int64_t N,
+                                float *feat12) {
+    if (!feat12 || !valid_enum(op, dir, dt) || M <= 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
+    features(kop(op, dir), dt, M, N, feat12);
+    return CREDIT_OK;
+}
+
+int64_t credit_mlp_num_params(void) { return kMlpParams; }
+
+credit_status_t credit_mlp_set(credit_handle_t h, const float *params, const float *mu, const float *sd) {
+    if (!h || !params || !mu || !sd) return CREDIT_ERR_INVALID_ARG;
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    for (int i = 0; i < kF; ++i)
+        if (!(sd[i] > 0.f)) return CREDIT_ERR_INVALID_ARG;
+    std::memcpy(h->params.data(), params, kMlpParams * 4);
+    std::memcpy(h->mu, mu, kF * 4);
+    std::memcpy(h->sd, sd, kF * 4);
+    h->has_model = true;
+    h->plan_cache.clear();
+    return CREDIT_OK;
+}
+
+credit_status_t credit_mlp_get(credit_handle_t h, float *params, float *mu, float *sd) {
+    if (!h) return CREDIT_ERR_INVALID_ARG;
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    if (params) std::memcpy(params, h->params.data(), kMlpParams * 4);
+    if (mu) std::memcpy(mu, h->mu, kF * 4);
+    if (sd) std::memcpy(sd, h->sd, kF * 4);
+    return CREDIT_OK;
+}
+
+credit_status_t credit_mlp_grad(credit_handle_t h, const float *feats, const float *targets, const uint8_t *mask,
+                                int64_t n, float *loss, float *grad) {
+    if (!h || !feats || !targets || !mask || n <= 0) return CREDIT_ERR_INVALID_ARG;
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    try {
+        MlpDev d;
+        if (!d.init(n) || !mlp_upload(h, d, feats, targets, mask)) return CREDIT_ERR_HIP;
+        if (mlp_forward(d, h->stream) != hipSuccess || mlp_backward(d, h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+        if (loss && hipMemcpy(loss, d.lmean, 4, hipMemcpyDeviceToHost) != hipSuccess) return CREDIT_ERR_HIP;
+        if (grad && hipMemcpy(grad, d.g, kMlpParams * 4, hipMemcpyDeviceToHost) != hipSuccess) return CREDIT_ERR_HIP;
+        return CREDIT_OK;
+    } catch (...) {
+        return CREDIT_ERR_HIP;
+    }
+}
+
+credit_status_t credit_mlp_train(credit_handle_t h, const float *feats, const float *targets, const uint8_t *mask,
+                                 int64_t n, int epochs, float lr, uint64_t seed, float *final_loss) {
+    if (!h || !feats || !targets || !mask || n <= 0 || epochs < 0 || !(lr > 0.f)) return CREDIT_ERR_INVALID_ARG;
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    try {
+        if (seed != 0) {
+            // feature standardization from the training set
+            for (int f = 0; f < kF; ++f) {
+                double s = 0, s2 = 0;
+                for (int64_t i = 0; i < n; ++i) s += feats[i * kF + f];
+                double m = s / n;
+                for (int64_t i = 0; i < n; ++i) s2 += (feats[i * kF + f] - m) * (feats[i * kF + f] - m);
+                double sd = std::sqrt(s2 / n);
+                h->mu[f] = (float)m;
+                h->sd[f] = sd > 1e-6 ? (float)sd : 1.f;
+            }
+            // He initialisation, zero biases
+            Rng r{seed};
+            auto he = [&](size_t off, int O, int I) {
+                double sc = std::sqrt(2.0 / I);
+                for (int i = 0; i < O * I; ++i) h->params[off + i] = (float)(r.normal() * sc);
+            };
+            std::fill(h->params.begin(), h->params.end(), 0.f);
+            he(oW1, kH, kF);
+            he(oW2, kH, kH);
+            he(oW3, kC, kH);
+        }
+        MlpDev d;
+        if (!d.init(n) || !mlp_upload(h, d, feats, targets, mask)) return CREDIT_ERR_HIP;
+        if (hipMemset(d.m, 0, kMlpParams * 4) != hipSuccess || hipMemset(d.v, 0, kMlpParams * 4) != hipSuccess)
+            return CREDIT_ERR_HIP;
+        const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+        int64_t np = kMlpParams;
+        double p1 = 1.0, p2 = 1.0;
+        for (int t = 1; t <= epochs; ++t) {
+            if (mlp_forward(d, h->stream) != hipSuccess || mlp_backward(d, h->stream) != hipSuccess)
+                return CREDIT_ERR_HIP;
+            p1 *= b1;
+            p2 *= b2;
+            float bc1 = (float)(1.0 - p1), bc2 = (float)(1.0 - p2);
+            float lr_ = lr, b1_ = b1, b2_ = b2, eps_ = eps;
+            void *a[] = {&d.p, &d.g, &d.m, &d.v, &np, &lr_, &b1_, &b2_, &eps_, &bc1, &bc2};
+            if (launch(mlp_kernel(6), blocks(np), 256, 0, h->stream, a) != hipSuccess) return CREDIT_ERR_HIP;
+        }
+        // loss at the final parameters
+        if (mlp_forward(d, h->stream) != hipSuccess || mlp_backward(d, h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+        if (hipMemcpy(h->params.data(), d.p, kMlpParams * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return CREDIT_ERR_HIP;
+        if (final_loss && hipMemcpy(final_loss, d.lmean, 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return CREDIT_ERR_HIP;
+        h->has_model = true;
+        h->plan_cache.clear();
+        return CREDIT_OK;
+    } catch (...) {
+        return CREDIT_ERR_HIP;
+    }
+}
+
+credit_status_t credit_mlp_predict(credit_handle_t h, const float *feats, int64_t n, float *logits) {
+    if (!h || !feats || !logits || n <= 0) return CREDIT_ERR_INVALID_ARG;
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    try {
+        return mlp_predict_dev(h, feats, n, logits);
+    } catch (...) {
+        return CREDIT_ERR_HIP;
+    }
+}
+
+static const char *kSchema = "f12-h64-h64-c7-v1";
+
+credit_status_t credit_save_model(credit_handle_t h, const char *path) {
+    if (!h || !path) return CREDIT_ERR_INVALID_ARG;
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    if (!h->has_model) return CREDIT_ERR_MODEL;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return CREDIT_ERR_INVALID_ARG;
+    std::string arch = h->arch.substr(0, h->arch.find(':'));
+    std::fprintf(f, "CREDIT-MLP 1\narch %s\ncus %d\nschema %s\nmu", arch.c_str(), h->cus, kSchema);
+    for (int i = 0; i < kF; ++i) std::fprintf(f, " %.9g", h->mu[i]);
+    std::fprintf(f, "\nsd");
+    for (int i = 0; i < kF; ++i) std::fprintf(f, " %.9g", h->sd[i]);
+    std::fprintf(f, "\nparams %d\n", kMlpParams);
+    for (int i = 0; i < kMlpParams; ++i) std::fprintf(f, "%.9g\n", h->params[i]);
+    std::fprintf(f, "end\n");
+    return std::fclose(f) == 0 ? CREDIT_OK : CREDIT_ERR_INVALID_ARG;
+}
+
+credit_status_t credit_load_model(credit_handle_t h, const char *path) {
+    if (!h || !path) return CREDIT_ERR_INVALID_ARG;
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    h->has_model = false;
+    h->plan_cache.clear();
+    FILE *f = std::fopen(path, "r");
+    if (!f) return CREDIT_ERR_MODEL;
+    char arch[64] = {0}, schema[64] = {0}, tag[16] = {0};
+    int ver = 0, cus = 0, np = 0;
+    bool ok = std::fscanf(f, "CREDIT-MLP %d arch %63s cus %d schema %63s mu", &ver, arch, &cus, schema) == 4;
+    std::string want = h->arch.substr(0, h->arch.find(':'));
+    ok = ok && ver == 1 && want == arch && cus == h->cus && std::strcmp(schema, kSchema) == 0;
+    float mu[kF], sd[kF];
+    for (int i = 0; ok && i < kF; ++i) ok = std::fscanf(f, "%f", &mu[i]) == 1;
+    ok = ok && std::fscanf(f, " sd") == 0;
+    for (int i = 0; ok && i < kF; ++i) ok = std::fscanf(f, "%f", &sd[i]) == 1 && sd[i] > 0.f;
+    ok = ok && std::fscanf(f, " params %d", &np) == 1 && np == kMlpParams;
+    std::vector<float> p(kMlpParams);
+    for (int i = 0; ok && i < kMlpParams; ++i) ok = std::fscanf(f, "%f", &p[i]) == 1 && std::isfinite(p[i]);
+    ok = ok && std::fscanf(f, "%15s", tag) == 1 && std::strcmp(tag, "end") == 0;
+    std::fclose(f);
+    if (!ok) return CREDIT_ERR_MODEL;
+    std::memcpy(h->params.data(), p.data(), kMlpParams * 4);
+    std::memcpy(h->mu, mu, sizeof(mu));
+    std::memcpy(h->sd, sd, sizeof(sd));
+    h->has_model = true;
+    return CREDIT_OK;
+}
+
+credit_status_t credit_set_option(credit_handle_t h, credit_option_t opt, int64_t value) {
+    if (!h) return CREDIT_ERR_INVALID_ARG;
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    switch (opt) {
+    case CREDIT_OPT_SPIN_LIMIT:
+        if (value < 0) return CREDIT_ERR_INVALID_ARG;
+        h->spin_limit = value;
+        return CREDIT_OK;
+    case CREDIT_OPT_TEST_DROP_PUBLISH: h->drop_publish = value != 0; return CREDIT_OK;
+    case CREDIT_OPT_MAX_GROUPS:
+        if (value < 0) return CREDIT_ERR_INVALID_ARG;
+        h->max_groups = value;
+        h->plan_cache.clear();
+        return CREDIT_OK;
+    }
+    return CREDIT_ERR_INVALID_ARG;
+}
+
+credit_status_t credit_set_epoch(uint32_t next) {
+    g_epoch.store(next == 0 ? 1 : next);
+    return CREDIT_OK;
+}
+
+}  // extern "C"

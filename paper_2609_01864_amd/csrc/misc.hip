@@ -1,0 +1,160 @@
+// misc.hip -- support kernels: dgamma/dbeta column reductions, the work-free
+// control kernel of the profitability model, cache flush, deterministic fill,
+// the copy-bandwidth probe and the elementwise codecs.
+#include "resident.h"
+#include "twopass.h"
+
+namespace credit {
+
+// out_p[j] = sum over g < parts of part[g][p][j], in increasing g
+// (deterministic: no atomics, fixed order).
+__global__ __launch_bounds__(256) void k_colreduce(const float *part, int parts, int ncp, int64_t N, float *out0,
+                                                   float *out1) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= N) return;
+    for (int p = 0; p < ncp; ++p) {
+        float *o = p == 0 ? out0 : out1;
+        if (!o) continue;
+        float s = 0.f;
+        for (int g = 0; g < parts; ++g) s += part[((int64_t)g * ncp + p) * N + j];
+        o[j] = s;
+    }
+}
+
+const void *colreduce_kernel() { return (const void *)&k_colreduce; }
+
+const void *colstats_kernel(int dt, bool ln) {
+    if (dt == DT_F32) return ln ? (const void *)&k_colstats<DT_F32, true> : (const void *)&k_colstats<DT_F32, false>;
+    if (dt == DT_BF16) return ln ? (const void *)&k_colstats<DT_BF16, true> : (const void *)&k_colstats<DT_BF16, false>;
+    if (dt == DT_FP8) return ln ? (const void *)&k_colstats<DT_FP8, true> : (const void *)&k_colstats<DT_FP8, false>;
+    return nullptr;
+}
+
+// The work-free control kernel (Sec. III-D): the split-row kernel's grid, row
+// groups, split factor and occupancy (pinned through the dynamic LDS size
+// chosen by the host), and per row `stages` workgroup barriers plus, for
+// k > 1, the partial exchange; no row data is read or written.
+__global__ __launch_bounds__(kBlock) void k_control(RowArgs a, int stages) {
+    extern __shared__ float pin[];
+    __shared__ float red[2 * 4 * 2];
+    __shared__ float xb[kMaxK * kMaxQ];
+    int parity = 0;
+    const int G = gridDim.x, bid = blockIdx.x;
+    const int lb = (a.flags & F_XCD) ? (bid & 7) * (G >> 3) + (bid >> 3) : bid;
+    const int c = lb % a.k, grp = lb / a.k;
+    for (int64_t row = grp; row < a.M; row += a.groups) {
+        for (int s = 0; s < stages; ++s) {
+            float v[2] = {(float)threadIdx.x, 0.f};
+            block_reduce<4, 2>(v, MergeSum(), red, parity);
+            if (a.k > 1) exchange<2>(a, row, s, c, v, xb);
+        }
+    }
+    if (a.M < 0) pin[threadIdx.x] = red[0];  // keeps the dynamic allocation
+}
+
+const void *control_kernel() { return (const void *)&k_control; }
+
+// Zero-fill of n 32-bit words (used instead of a memset node so the sequence
+// stays safe under stream capture).
+__global__ __launch_bounds__(256) void k_zero(unsigned *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+}
+const void *zero_kernel() { return (const void *)&k_zero; }
+
+// Deterministic pseudo-random fill of a timing buffer with values valid for
+// the dtype: FP32 / BF16 in [-2, 2), FP8 any finite code.
+__device__ __forceinline__ unsigned mix32(unsigned long long x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdULL;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ULL;
+    x ^= x >> 33;
+    return (unsigned)x;
+}
+__global__ __launch_bounds__(256) void k_fill(unsigned *p, int64_t nwords, unsigned seed, int dt) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * 256) {
+        unsigned h = mix32(((unsigned long long)seed << 40) ^ (unsigned long long)i);
+        unsigned w;
+        if (dt == DT_F32) {
+            w = __float_as_uint(((float)(h >> 8) * (1.f / 16777216.f)) * 4.f - 2.f);
+        } else if (dt == DT_BF16) {
+            float a = ((float)(h & 0xffff) * (1.f / 65536.f)) * 4.f - 2.f;
+            float b = ((float)(h >> 16) * (1.f / 65536.f)) * 4.f - 2.f;
+            w = (__float_as_uint(a) >> 16) | (__float_as_uint(b) & 0xffff0000u);
+        } else {
+            w = h;
+            // replace NaN codes (S.1111.111) by the largest finite code
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (((w >> (8 * b)) & 0x7fu) == 0x7fu) w ^= 1u << (8 * b);
+        }
+        p[i] = w;
+    }
+}
+const void *fill_kernel() { return (const void *)&k_fill; }
+
+// Streaming copy used to calibrate the achievable read+write bandwidth and the
+// hardware traffic counters: 4 independent 128-bit loads in flight per thread.
+__global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        u32x4 a = __builtin_nontemporal_load(src + i);
+        u32x4 b = __builtin_nontemporal_load(src + i + stride);
+        u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
+        u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+const void *copy_kernel() { return (const void *)&k_copy; }
+
+// Elementwise FP32 -> dtype: code = RNE(x / scale[row]) (FP8 saturating).
+template <int DT>
+__global__ __launch_bounds__(256) void k_encode(const float *x, const float *scale, void *out, int64_t M, int64_t N) {
+    constexpr int B = Io<DT>::BYTES;
+    const int64_t total = M * N;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        float v = x[i];
+        if (scale) v = v / scale[i / N];
+        if constexpr (DT == DT_F32) {
+            ((float *)out)[i] = v;
+        } else if constexpr (DT == DT_BF16) {
+            ((unsigned short *)out)[i] = (unsigned short)bf16_bits(v);
+        } else {
+            int w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(v), 0.f, 0, false);
+            ((unsigned char *)out)[i] = (unsigned char)(w & 0xff);
+        }
+        (void)B;
+    }
+}
+// Elementwise dtype -> FP32: decode(code) * scale[row].
+template <int DT>
+__global__ __launch_bounds__(256) void k_decode(const void *in, const float *scale, float *out, int64_t M, int64_t N) {
+    const int64_t total = M * N;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        float v;
+        if constexpr (DT == DT_F32) {
+            v = ((const float *)in)[i];
+        } else if constexpr (DT == DT_BF16) {
+            v = __uint_as_float((unsigned)((const unsigned short *)in)[i] << 16);
+        } else {
+            f32x2 t = __builtin_amdgcn_cvt_pk_f32_fp8((int)((const unsigned char *)in)[i], false);
+            v = t.x;
+        }
+        out[i] = scale ? v * scale[i / N] : v;
+    }
+}
+const void *encode_kernel(int dt) {
+    return dt == DT_F32 ? (const void *)&k_encode<DT_F32>
+         : dt == DT_BF16 ? (const void *)&k_encode<DT_BF16> : (const void *)&k_encode<DT_FP8>;
+}
+const void *decode_kernel(int dt) {
+    return dt == DT_F32 ? (const void *)&k_decode<DT_F32>
+         : dt == DT_BF16 ? (const void *)&k_decode<DT_BF16> : (const void *)&k_decode<DT_FP8>;
+}
+
+}  // namespace credit

@@ -1,0 +1,720 @@
+// resident.h -- the row-resident (k == 1) and split-row (k > 1) kernels.
+//
+// A workgroup of 256 threads (one wave per SIMD) owns a slice of `chunk`
+// elements of a row (Eq. (2): the slices I_c of the k members of a row group
+// partition the row).  It loads the slice once with 128-bit loads and keeps it
+// in registers in the packed I/O format (the staged copy of Fig. 2b, held in
+// VGPRs instead of shared memory), reduces it thread -> wave -> workgroup, and,
+// when k > 1, exchanges the q partials of every stage with the other members
+// (replicated gather: every member reads all k slots and combines them in the
+// fixed order c = 0..k-1, so all members reconstruct bit-identical statistics,
+// Eq. (5)).  It then applies h to its own retained slice and writes it.  The
+// workgroup is persistent: row group `grp` processes rows grp, grp + groups, ...
+//
+// Slot j of thread t holds vector j * 256 + t of the slice.  Three row loops
+// exist, chosen once per workgroup (the choice is uniform, and every loop
+// contains workgroup barriers):
+//   AL && FULLS   every slot of every thread is a full, 16-byte aligned vector:
+//                 straight-line 128-bit loads and stores, no masks;
+//   AL && !FULLS  aligned rows, slice not an exact multiple: slots past the
+//                 last full vector re-read the slice's first vector and are
+//                 zeroed / masked, the trailing partial vector (if any) is
+//                 handled by its owner;
+//   !AL           misaligned rows: element-wise accesses, same masking.
+#pragma once
+#include "device.h"
+
+namespace credit {
+
+template <int OP> struct OpTraits {
+    static constexpr bool TWO = OP >= OP_SOFTMAX_BWD;  // two resident input tensors
+    static constexpr int NCP = OP == OP_LN_BWD ? 2 : (OP == OP_RMS_BWD ? 1 : 0);  // column partials
+};
+
+// Waves per SIMD the register allocation must allow (each workgroup is one
+// wave per SIMD, so this is also the workgroups per CU): the retained data,
+// the FP32 column partials and the working registers within 512 / W VGPRs.
+template <int OP, int DT, int VPT> constexpr int resident_waves() {
+    constexpr int data = VPT * 4 * (OpTraits<OP>::TWO ? 2 : 1) + OpTraits<OP>::NCP * VPT * Io<DT>::EPV;
+    constexpr int work = 64 + (DT == DT_FP8 ? 32 : 0) + (OP == OP_SOFTMAX_FWD || OP == OP_SOFTMAX_BWD ? 0 : 16);
+    constexpr int w = 512 / (data + work);
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
+// Aligned accesses address a slot as (uniform base pointer, 32-bit per-thread
+// byte offset), so the compiler emits SGPR-base + VGPR-offset instructions and
+// keeps no 64-bit address per slot alive across passes.
+__device__ __forceinline__ u32x4 vload_nt(const char *base, uint32_t off) {
+    return __builtin_nontemporal_load((const u32x4 *)(base + off));
+}
+__device__ __forceinline__ void vstore_nt(char *base, uint32_t off, u32x4 v) {
+    __builtin_nontemporal_store(v, (u32x4 *)(base + off));
+}
+
+// EPV FP32 parameters (gamma / beta) of one vector slot: aligned form from a
+// uniform base and a byte offset; element-wise form for misaligned rows.
+template <int DT>
+__device__ __forceinline__ void load_params_al(const float *base, uint32_t off, float *out) {
+    constexpr int EPV = Io<DT>::EPV;
+    const char *p = (const char *)base + off;
+#pragma unroll
+    for (int i = 0; i < EPV; i += 4) {
+        float4 v = *(const float4 *)(p + 4 * i);
+        out[i] = v.x; out[i + 1] = v.y; out[i + 2] = v.z; out[i + 3] = v.w;
+    }
+}
+template <int DT>
+__device__ __forceinline__ void load_params_el(const float *p, int64_t col, bool ok, float *out) {
+#pragma unroll
+    for (int i = 0; i < Io<DT>::EPV; ++i) out[i] = ok ? p[col + i] : 0.f;
+}
+
+// Parameters of the trailing partial vector (n valid elements, n < EPV).
+template <int DT>
+__device__ __forceinline__ void load_params_tail(const float *p, int64_t col, int n, float *out) {
+#pragma unroll
+    for (int i = 0; i < Io<DT>::EPV; ++i) out[i] = i < n ? p[col + i] : 0.f;
+}
+
+// Combines the k exchanged partials of a stage in member order.
+template <int Q, class Merge>
+__device__ __forceinline__ void combine_members(float (&v)[Q], const float *xb, int k, Merge merge) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) v[j] = xb[j];
+    for (int c = 1; c < k; ++c) {
+        float t[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) t[j] = xb[c * Q + j];
+        merge(v, t);
+    }
+}
+
+// Reduces a per-thread tuple over the workgroup and, for k > 1, over the row
+// group.  Sum- and max-type statistics.
+template <int Q, class Merge>
+__device__ __forceinline__ void row_reduce(float (&v)[Q], Merge merge, const RowArgs &a, int64_t row,
+                                           int stage, int c, float *red, float *xb, int &parity) {
+    block_reduce<4, Q>(v, merge, red, parity);
+    if (a.k > 1) {
+        exchange<Q>(a, row, stage, c, v, xb);
+        combine_members<Q>(v, xb, a.k, merge);
+    }
+}
+
+// Chan statistics (n, mean, M2) over the workgroup and the row group.  The
+// exchange carries (mean, M2); each member's count follows from its slice.
+__device__ __forceinline__ void row_reduce_chan(float (&v)[3], const RowArgs &a, int64_t row, int stage,
+                                                int c, float *red, float *xb, int &parity) {
+    block_reduce<4, 3>(v, MergeChan(), red, parity);
+    if (a.k > 1) {
+        float mine[2] = {v[1], v[2]};
+        exchange<2>(a, row, stage, c, mine, xb);
+        float n = 0.f, mean = 0.f, m2 = 0.f;
+        for (int m = 0; m < a.k; ++m) {
+            int64_t lo = (int64_t)m * a.chunk;
+            int64_t cnt = a.N - lo < a.chunk ? a.N - lo : a.chunk;
+            float nm = cnt > 0 ? (float)cnt : 0.f;
+            chan_merge(n, mean, m2, nm, xb[2 * m], xb[2 * m + 1]);
+        }
+        v[0] = n; v[1] = mean; v[2] = m2;
+    }
+}
+
+// Geometry of a workgroup's slice.
+struct Slice {
+    int64_t c0;    // first column
+    int64_t nval;  // valid elements
+    int64_t nfv;   // full vectors
+    int tail_n;    // elements of the trailing partial vector (0: none)
+    int owner;     // thread that holds it
+};
+
+template <int OP, int DT, int VPT, bool AL, bool FULLS>
+__device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const Slice &sl, float *red, float *xb) {
+    using T = OpTraits<OP>;
+    constexpr int EPV = Io<DT>::EPV, B = Io<DT>::BYTES, NCP = T::NCP;
+    constexpr bool FP8 = DT == DT_FP8;
+    // slots per batch of parameter loads: 16 FP32 parameter registers in flight
+    constexpr int GBW = 16 / EPV / (OP == OP_LN_FWD ? 2 : 1);
+    constexpr int GB = GBW < 1 ? 1 : (VPT < GBW ? VPT : GBW);
+    int parity = 0;
+    const int tid = threadIdx.x;
+    const float invN = 1.f / (float)a.N;
+    auto ok_of = [&](int j) -> bool { return FULLS || (int64_t)(j * kBlock + tid) < sl.nfv; };
+    auto col_of = [&](int j) -> int64_t { return sl.c0 + (int64_t)(j * kBlock + tid) * EPV; };
+    const bool tail = !FULLS && sl.tail_n > 0 && tid == sl.owner;
+    const int tn = sl.tail_n;
+    const int64_t tcol = sl.c0 + sl.nfv * EPV;
+    // elements this thread holds (for the Chan counts)
+    float held = 0.f;
+    if (FULLS) {
+        held = (float)(VPT * EPV);
+    } else {
+        for (int j = 0; j < VPT; ++j) held += ok_of(j) ? (float)EPV : 0.f;
+        if (tail) held += (float)tn;
+    }
+
+    float cp[NCP ? NCP : 1][NCP ? VPT * EPV : 1];
+    float cpt[NCP ? NCP : 1][NCP ? EPV : 1];
+    if constexpr (NCP) {
+#pragma unroll
+        for (int p = 0; p < NCP; ++p) {
+#pragma unroll
+            for (int i = 0; i < VPT * EPV; ++i) cp[p][i] = 0.f;
+#pragma unroll
+            for (int i = 0; i < EPV; ++i) cpt[p][i] = 0.f;
+        }
+    }
+
+    for (int64_t row = grp; row < a.M; row += a.groups) {
+        const char *r0 = (const char *)a.in0 + row * a.ld0 * B;
+        const char *r1 = T::TWO ? (const char *)a.in1 + row * a.ld1 * B : nullptr;
+        char *orow = (char *)a.out + row * a.ldo * B;
+        const bool writer = c == 0 && tid == 0;
+        // Uniform bases of this row's slice and per-thread byte offsets that are
+        // made opaque each row, so slot addresses are formed next to their use
+        // instead of being hoisted out of the row loop as 64-bit registers.
+        const char *b0 = r0 + sl.c0 * B;
+        const char *b1 = T::TWO ? r1 + sl.c0 * B : nullptr;
+        char *bo = orow + sl.c0 * B;
+        uint32_t toff = (uint32_t)tid * 16u, poff = (uint32_t)tid * (EPV * 4u);
+        asm volatile("" : "+v"(toff));
+        asm volatile("" : "+v"(poff));
+        // masked slots read the slice's first vector (AL needs nfv >= 1); their
+        // data is zeroed before use and their stores are skipped
+        auto doff = [&](int j) -> uint32_t {
+            return (FULLS || ok_of(j)) ? toff + (uint32_t)j * (kBlock * 16u) : 0u;
+        };
+        auto pofs = [&](int j) -> uint32_t {
+            return (FULLS || ok_of(j)) ? poff + (uint32_t)j * (kBlock * EPV * 4u) : 0u;
+        };
+        auto LD = [&](const char *base, const char *rowp, int j) -> u32x4 {
+            if constexpr (AL)
+                return vload_nt(base, doff(j));
+            else
+                return load_vec<DT, false>(rowp, col_of(j), ok_of(j) ? EPV : 0, false);
+        };
+        auto ST = [&](int j, u32x4 v) {
+            if (FULLS || ok_of(j)) {
+                if constexpr (AL)
+                    vstore_nt(bo, toff + (uint32_t)j * (kBlock * 16u), v);
+                else
+                    store_vec<DT>(orow, col_of(j), EPV, false, v);
+            }
+        };
+        auto PAR = [&](const float *p, int j, float *out) {
+            if constexpr (AL)
+                load_params_al<DT>(p + sl.c0, pofs(j), out);
+            else
+                load_params_el<DT>(p, col_of(j), ok_of(j), out);
+        };
+        u32x4 d0[VPT];
+        u32x4 d1[T::TWO ? VPT : 1];
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) d0[j] = LD(b0, r0, j);
+        if constexpr (T::TWO) {
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) d1[j] = LD(b1, r1, j);
+        }
+        u32x4 t0 = {0u, 0u, 0u, 0u}, t1 = {0u, 0u, 0u, 0u};
+        if (tail) {
+            t0 = load_vec<DT, false>(r0, tcol, tn, false);
+            if constexpr (T::TWO) t1 = load_vec<DT, false>(r1, tcol, tn, false);
+        }
+        // Called at the start of every pass over the retained slice.
+        auto fresh = [&]() {
+            opaque<VPT>(d0);
+            if constexpr (T::TWO) opaque<VPT>(d1);
+        };
+        if constexpr (!FULLS) {
+            fresh();  // all loads are in flight; wait for them once here
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                const bool ok = ok_of(j);
+                d0[j] = ok ? d0[j] : u32x4{0u, 0u, 0u, 0u};
+                if constexpr (T::TWO) d1[j] = ok ? d1[j] : u32x4{0u, 0u, 0u, 0u};
+            }
+        }
+
+        if constexpr (OP == OP_SOFTMAX_FWD) {
+            // Base-2 statistics: K = scale * log2(e); c = max(q * K); s = sum 2^(q*K - c).
+            const float K = (FP8 ? a.s0[row] : 1.f) * kLog2e;
+            float qmax = -INFINITY;
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float q[EPV];
+                decode<DT>(d0[j], q, 1.f);
+                const bool ok = ok_of(j);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) qmax = fmaxf(qmax, ok ? q[i] : -INFINITY);
+            }
+            if (tail) {
+                float q[EPV];
+                decode<DT>(t0, q, 1.f);
+                for (int i = 0; i < tn; ++i) qmax = fmaxf(qmax, q[i]);
+            }
+            float st[2] = {qmax == -INFINITY ? -INFINITY : qmax * K, 0.f};
+            const float ct = qmax == -INFINITY ? 0.f : st[0];
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float q[EPV];
+                decode<DT>(d0[j], q, 1.f);
+                const bool ok = ok_of(j);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    float e = fast_exp2(fmaf(q[i], K, -ct));
+                    st[1] += ok ? e : 0.f;
+                }
+            }
+            if (tail) {
+                float q[EPV];
+                decode<DT>(t0, q, 1.f);
+                for (int i = 0; i < tn; ++i) st[1] += fast_exp2(fmaf(q[i], K, -ct));
+            }
+            row_reduce<2>(st, MergeSoftmax(), a, row, 0, c, red, xb, parity);
+            const float cmax = st[0];
+            const float inv_s = 1.f / st[1];
+            // FP8 output: the largest output is 2^0 * inv_s, so amax = inv_s and the
+            // code of element i is 448 * 2^(q*K - c) (no second statistics stage).
+            const float omul = FP8 ? kFp8Max : inv_s;
+            if (FP8 && writer) a.so[row] = inv_s / kFp8Max;
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float q[EPV], y[EPV];
+                decode<DT>(d0[j], q, 1.f);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, -cmax)) * omul;
+                ST(j, encode<DT>(y, 1.f));
+            }
+            if (tail) {
+                float q[EPV], y[EPV];
+                decode<DT>(t0, q, 1.f);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, -cmax)) * omul;
+                store_vec<DT>(orow, tcol, tn, false, encode<DT>(y, 1.f));
+            }
+        } else if constexpr (OP == OP_LN_FWD || OP == OP_RMS_FWD) {
+            constexpr bool LN = OP == OP_LN_FWD;
+            const float xs = FP8 ? a.s0[row] : 1.f;
+            float mean = 0.f, rstd;
+            if constexpr (LN) {
+                float sum = 0.f;
+                fresh();
+#pragma unroll
+                for (int j = 0; j < VPT; ++j) {
+                    float x[EPV];
+                    decode<DT>(d0[j], x, xs);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) sum += x[i];  // masked slots hold zeros
+                }
+                if (tail) {
+                    float x[EPV];
+                    decode<DT>(t0, x, xs);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) sum += x[i];
+                }
+                const float tm = held > 0.f ? sum / held : 0.f;
+                float m2 = 0.f;
+                fresh();
+#pragma unroll
+                for (int j = 0; j < VPT; ++j) {
+                    float x[EPV];
+                    decode<DT>(d0[j], x, xs);
+                    const bool ok = ok_of(j);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) {
+                        float d = ok ? x[i] - tm : 0.f;
+                        m2 = fmaf(d, d, m2);
+                    }
+                }
+                if (tail) {
+                    float x[EPV];
+                    decode<DT>(t0, x, xs);
+                    for (int i = 0; i < tn; ++i) {
+                        float d = x[i] - tm;
+                        m2 = fmaf(d, d, m2);
+                    }
+                }
+                float st[3] = {held, tm, m2};
+                row_reduce_chan(st, a, row, 0, c, red, xb, parity);
+                mean = st[1];
+                rstd = rsqrtf(st[2] * invN + a.eps);
+            } else {
+                float st[1] = {0.f};
+                fresh();
+#pragma unroll
+                for (int j = 0; j < VPT; ++j) {
+                    float x[EPV];
+                    decode<DT>(d0[j], x, xs);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) st[0] = fmaf(x[i], x[i], st[0]);
+                }
+                if (tail) {
+                    float x[EPV];
+                    decode<DT>(t0, x, xs);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) st[0] = fmaf(x[i], x[i], st[0]);
+                }
+                row_reduce<1>(st, MergeSum(), a, row, 0, c, red, xb, parity);
+                rstd = rsqrtf(st[0] * invN + a.eps);
+            }
+            if (writer) {
+                if (a.mean_out) a.mean_out[row] = mean;
+                if (a.rstd_out) a.rstd_out[row] = rstd;
+            }
+            auto h = [&](const float *x, const float *g, const float *bb, float *y) {
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    if constexpr (LN)
+                        y[i] = fmaf((x[i] - mean) * rstd, g[i], bb[i]);
+                    else
+                        y[i] = x[i] * rstd * g[i];
+                }
+            };
+            // output pass over the slots in batches of GB: the parameter loads of
+            // a batch are issued together; store == false only measures amax
+            auto out_pass = [&](bool store, float oinv, float &amax) {
+                fresh();
+#pragma unroll
+                for (int jb = 0; jb < VPT; jb += GB) {
+                    // keep the scheduler from hoisting every batch's parameter
+                    // loads to the top (that would hold VPT slots of gamma/beta)
+                    __builtin_amdgcn_sched_barrier(0);
+                    float g[GB][EPV], bb[GB][LN ? EPV : 1];
+#pragma unroll
+                    for (int u = 0; u < GB; ++u) {
+                        PAR(a.gamma, jb + u, g[u]);
+                        if constexpr (LN) PAR(a.beta, jb + u, bb[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < GB; ++u) {
+                        const int j = jb + u;
+                        float x[EPV], y[EPV];
+                        decode<DT>(d0[j], x, xs);
+                        h(x, g[u], LN ? bb[u] : g[u], y);
+                        if (store) {
+                            ST(j, encode<DT>(y, oinv));
+                        } else {
+                            const bool ok = ok_of(j);
+#pragma unroll
+                            for (int i = 0; i < EPV; ++i) amax = fmaxf(amax, ok ? fabsf(y[i]) : 0.f);
+                        }
+                    }
+                }
+                if (tail) {
+                    float x[EPV], y[EPV], g[EPV], bb[EPV];
+                    decode<DT>(t0, x, xs);
+                    load_params_tail<DT>(a.gamma, tcol, tn, g);
+                    if constexpr (LN) load_params_tail<DT>(a.beta, tcol, tn, bb);
+                    h(x, g, bb, y);
+                    if (store) {
+                        store_vec<DT>(orow, tcol, tn, false, encode<DT>(y, oinv));
+                    } else {
+                        for (int i = 0; i < tn; ++i) amax = fmaxf(amax, fabsf(y[i]));
+                    }
+                }
+            };
+            float oinv = 1.f;
+            if constexpr (FP8) {
+                float am[1] = {0.f};
+                out_pass(false, 1.f, am[0]);
+                row_reduce<1>(am, MergeMax(), a, row, 1, c, red, xb, parity);
+                oinv = am[0] > 0.f ? kFp8Max / am[0] : 1.f;
+                if (writer) a.so[row] = am[0] > 0.f ? am[0] / kFp8Max : 1.f;
+            }
+            float unused = 0.f;
+            out_pass(true, oinv, unused);
+        } else if constexpr (OP == OP_SOFTMAX_BWD) {
+            const float ys = FP8 ? a.s0[row] : 1.f, gs = FP8 ? a.s1[row] : 1.f;
+            float st[1] = {0.f};
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float y[EPV], g[EPV];
+                decode<DT>(d0[j], y, ys);
+                decode<DT>(d1[j], g, gs);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) st[0] = fmaf(g[i], y[i], st[0]);
+            }
+            if (tail) {
+                float y[EPV], g[EPV];
+                decode<DT>(t0, y, ys);
+                decode<DT>(t1, g, gs);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) st[0] = fmaf(g[i], y[i], st[0]);
+            }
+            row_reduce<1>(st, MergeSum(), a, row, 0, c, red, xb, parity);
+            const float cs = st[0];
+            auto h = [&](u32x4 yv, u32x4 gv, float *dx) {
+                float y[EPV], g[EPV];
+                decode<DT>(yv, y, ys);
+                decode<DT>(gv, g, gs);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) dx[i] = y[i] * (g[i] - cs);
+            };
+            float oinv = 1.f;
+            if constexpr (FP8) {
+                float am[1] = {0.f};
+                fresh();
+#pragma unroll
+                for (int j = 0; j < VPT; ++j) {
+                    float dx[EPV];
+                    h(d0[j], d1[j], dx);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) am[0] = fmaxf(am[0], fabsf(dx[i]));  // masked: y = 0
+                }
+                if (tail) {
+                    float dx[EPV];
+                    h(t0, t1, dx);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) am[0] = fmaxf(am[0], fabsf(dx[i]));
+                }
+                row_reduce<1>(am, MergeMax(), a, row, 1, c, red, xb, parity);
+                oinv = am[0] > 0.f ? kFp8Max / am[0] : 1.f;
+                if (writer) a.so[row] = am[0] > 0.f ? am[0] / kFp8Max : 1.f;
+            }
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float dx[EPV];
+                h(d0[j], d1[j], dx);
+                ST(j, encode<DT>(dx, oinv));
+            }
+            if (tail) {
+                float dx[EPV];
+                h(t0, t1, dx);
+                store_vec<DT>(orow, tcol, tn, false, encode<DT>(dx, oinv));
+            }
+        } else {  // OP_LN_BWD, OP_RMS_BWD
+            constexpr bool LN = OP == OP_LN_BWD;
+            const float xs = FP8 ? a.s0[row] : 1.f, gs = FP8 ? a.s1[row] : 1.f;
+            float mean = 0.f, rstd;
+            if (a.flags & F_RECOMPUTE) {
+                if constexpr (LN) {
+                    float sum = 0.f;
+                    fresh();
+#pragma unroll
+                    for (int j = 0; j < VPT; ++j) {
+                        float x[EPV];
+                        decode<DT>(d0[j], x, xs);
+#pragma unroll
+                        for (int i = 0; i < EPV; ++i) sum += x[i];
+                    }
+                    if (tail) {
+                        float x[EPV];
+                        decode<DT>(t0, x, xs);
+#pragma unroll
+                        for (int i = 0; i < EPV; ++i) sum += x[i];
+                    }
+                    const float tm = held > 0.f ? sum / held : 0.f;
+                    float m2 = 0.f;
+                    fresh();
+#pragma unroll
+                    for (int j = 0; j < VPT; ++j) {
+                        float x[EPV];
+                        decode<DT>(d0[j], x, xs);
+                        const bool ok = ok_of(j);
+#pragma unroll
+                        for (int i = 0; i < EPV; ++i) {
+                            float d = ok ? x[i] - tm : 0.f;
+                            m2 = fmaf(d, d, m2);
+                        }
+                    }
+                    if (tail) {
+                        float x[EPV];
+                        decode<DT>(t0, x, xs);
+                        for (int i = 0; i < tn; ++i) {
+                            float d = x[i] - tm;
+                            m2 = fmaf(d, d, m2);
+                        }
+                    }
+                    float st[3] = {held, tm, m2};
+                    row_reduce_chan(st, a, row, 2, c, red, xb, parity);
+                    mean = st[1];
+                    rstd = rsqrtf(st[2] * invN + a.eps);
+                } else {
+                    float st[1] = {0.f};
+                    fresh();
+#pragma unroll
+                    for (int j = 0; j < VPT; ++j) {
+                        float x[EPV];
+                        decode<DT>(d0[j], x, xs);
+#pragma unroll
+                        for (int i = 0; i < EPV; ++i) st[0] = fmaf(x[i], x[i], st[0]);
+                    }
+                    if (tail) {
+                        float x[EPV];
+                        decode<DT>(t0, x, xs);
+#pragma unroll
+                        for (int i = 0; i < EPV; ++i) st[0] = fmaf(x[i], x[i], st[0]);
+                    }
+                    row_reduce<1>(st, MergeSum(), a, row, 2, c, red, xb, parity);
+                    rstd = rsqrtf(st[0] * invN + a.eps);
+                }
+            } else {
+                if constexpr (LN) mean = a.mean_in[row];
+                rstd = a.rstd_in[row];
+            }
+            // stage: (sum g, sum g*xhat) for LayerNorm, (sum g*xhat) for RMSNorm;
+            // masked slots have dy = 0, hence g = 0
+            constexpr int Q = LN ? 2 : 1;
+            float st[Q];
+#pragma unroll
+            for (int t = 0; t < Q; ++t) st[t] = 0.f;
+            auto acc = [&](const float *x, const float *dy, const float *gm) {
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    float xh = (x[i] - mean) * rstd;
+                    float g = dy[i] * gm[i];
+                    if constexpr (LN) {
+                        st[0] += g;
+                        st[1] = fmaf(g, xh, st[1]);
+                    } else {
+                        st[0] = fmaf(g, xh, st[0]);
+                    }
+                }
+            };
+            fresh();
+#pragma unroll
+            for (int jb = 0; jb < VPT; jb += GB) {
+                __builtin_amdgcn_sched_barrier(0);
+                float gm[GB][EPV];
+#pragma unroll
+                for (int u = 0; u < GB; ++u) PAR(a.gamma, jb + u, gm[u]);
+#pragma unroll
+                for (int u = 0; u < GB; ++u) {
+                    float x[EPV], dy[EPV];
+                    decode<DT>(d0[jb + u], x, xs);
+                    decode<DT>(d1[jb + u], dy, gs);
+                    acc(x, dy, gm[u]);
+                }
+            }
+            if (tail) {
+                float x[EPV], dy[EPV], gm[EPV];
+                decode<DT>(t0, x, xs);
+                decode<DT>(t1, dy, gs);
+                load_params_tail<DT>(a.gamma, tcol, tn, gm);
+                acc(x, dy, gm);
+            }
+            row_reduce<Q>(st, MergeSum(), a, row, 0, c, red, xb, parity);
+            const float c1 = LN ? st[0] * invN : 0.f;
+            const float c2 = (LN ? st[1] : st[0]) * invN;
+            auto hh = [&](const float *x, const float *dy, const float *gm, float *dx) {
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    float xh = (x[i] - mean) * rstd;
+                    dx[i] = rstd * (dy[i] * gm[i] - c1 - xh * c2);
+                }
+            };
+            auto out_pass = [&](bool store, float oinv, float &amax) {
+                fresh();
+#pragma unroll
+                for (int jb = 0; jb < VPT; jb += GB) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    float gm[GB][EPV];
+#pragma unroll
+                    for (int u = 0; u < GB; ++u)
+                        PAR(a.gamma, jb + u, gm[u]);
+#pragma unroll
+                    for (int u = 0; u < GB; ++u) {
+                        const int j = jb + u;
+                        float x[EPV], dy[EPV], dx[EPV];
+                        decode<DT>(d0[j], x, xs);
+                        decode<DT>(d1[j], dy, gs);
+                        hh(x, dy, gm[u], dx);
+                        const bool ok = ok_of(j);
+                        if (store) {
+#pragma unroll
+                            for (int i = 0; i < EPV; ++i) {  // masked slots add dy = 0
+                                float xh = (x[i] - mean) * rstd;
+                                cp[0][j * EPV + i] = fmaf(dy[i], xh, cp[0][j * EPV + i]);
+                                if constexpr (LN) cp[NCP - 1][j * EPV + i] += dy[i];
+                            }
+                            ST(j, encode<DT>(dx, oinv));
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < EPV; ++i) amax = fmaxf(amax, ok ? fabsf(dx[i]) : 0.f);
+                        }
+                    }
+                }
+                if (tail) {
+                    float x[EPV], dy[EPV], gm[EPV], dx[EPV];
+                    decode<DT>(t0, x, xs);
+                    decode<DT>(t1, dy, gs);
+                    load_params_tail<DT>(a.gamma, tcol, tn, gm);
+                    hh(x, dy, gm, dx);
+                    if (store) {
+#pragma unroll
+                        for (int i = 0; i < EPV; ++i) {
+                            float xh = (x[i] - mean) * rstd;
+                            cpt[0][i] = fmaf(dy[i], xh, cpt[0][i]);
+                            if constexpr (LN) cpt[NCP - 1][i] += dy[i];
+                        }
+                        store_vec<DT>(orow, tcol, tn, false, encode<DT>(dx, oinv));
+                    } else {
+                        for (int i = 0; i < tn; ++i) amax = fmaxf(amax, fabsf(dx[i]));
+                    }
+                }
+            };
+            float oinv = 1.f;
+            if constexpr (FP8) {
+                float am[1] = {0.f};
+                out_pass(false, 1.f, am[0]);
+                row_reduce<1>(am, MergeMax(), a, row, 1, c, red, xb, parity);
+                oinv = am[0] > 0.f ? kFp8Max / am[0] : 1.f;
+                if (writer) a.so[row] = am[0] > 0.f ? am[0] / kFp8Max : 1.f;
+            }
+            float unused = 0.f;
+            out_pass(true, oinv, unused);
+        }
+    }
+
+    if constexpr (NCP) {
+        for (int p = 0; p < NCP; ++p) {
+            float *dst = a.colpart + ((int64_t)grp * NCP + p) * a.N;
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                if (!ok_of(j)) continue;
+                const int64_t col = col_of(j);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) dst[col + i] = cp[p][j * EPV + i];
+            }
+            if (tail)
+                for (int i = 0; i < tn; ++i) dst[tcol + i] = cpt[p][i];
+        }
+    }
+}
+
+template <int OP, int DT, int VPT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(resident_waves<OP, DT, VPT>())))
+void k_resident(RowArgs a) {
+    constexpr int EPV = Io<DT>::EPV;
+    __shared__ float red[2 * 4 * 3];
+    __shared__ float xb[kMaxK * kMaxQ];
+    const int G = gridDim.x, bid = blockIdx.x;
+    // XCD-aware numbering: hardware workgroup ids are dealt round-robin to the
+    // 8 XCDs, so logical ids that are consecutive within one XCD (and thus the
+    // k members of a row group) share that XCD's L2.
+    const int lb = (a.flags & F_XCD) ? (bid & 7) * (G >> 3) + (bid >> 3) : bid;
+    const int c = lb % a.k, grp = lb / a.k;
+    Slice sl;
+    sl.c0 = (int64_t)c * a.chunk;
+    const int64_t rem = a.N - sl.c0;
+    sl.nval = rem <= 0 ? 0 : (rem < a.chunk ? rem : a.chunk);
+    sl.nfv = sl.nval / EPV;
+    sl.tail_n = (int)(sl.nval - sl.nfv * EPV);
+    sl.owner = (int)(sl.nfv % kBlock);
+    constexpr int AL_ALL = F_ALIGN0 | F_ALIGNO | F_ALIGNP | (OpTraits<OP>::TWO ? F_ALIGN1 : 0);
+    const bool al = (a.flags & AL_ALL) == AL_ALL;
+    if (al && sl.nval == (int64_t)VPT * kBlock * EPV)
+        row_loop<OP, DT, VPT, true, true>(a, c, grp, sl, red, xb);
+    else if (al && sl.nfv >= 1)
+        row_loop<OP, DT, VPT, true, false>(a, c, grp, sl, red, xb);
+    else
+        row_loop<OP, DT, VPT, false, false>(a, c, grp, sl, red, xb);
+}
+
+}  // namespace credit

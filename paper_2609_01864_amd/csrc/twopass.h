@@ -1,0 +1,291 @@
+// twopass.h -- the global-reread baseline (Sec. IV-A, the multi-pass kernel
+// whose reread traffic N * b_reread appears in Eq. (4)).
+//
+// One workgroup per row (persistent over rows).  Each statistics stage
+// streams the row from global memory in batches of U 128-bit vectors per
+// thread; the output pass streams it again and writes.  Nothing is retained
+// between passes, so a reread is served by L2 / Infinity Cache when the row
+// is still there and by HBM otherwise.  Normalisation backward computes dx
+// here; dgamma / dbeta come from k_colstats + k_colreduce.
+#pragma once
+#include "device.h"
+#include "resident.h"
+
+namespace credit {
+
+// EPV FP32 parameters of the vector at column `col` with nv valid elements.
+template <int DT>
+__device__ __forceinline__ void load_params_n(const float *p, int64_t col, int nv, bool aligned, float *out) {
+    constexpr int EPV = Io<DT>::EPV;
+    if (nv == EPV && aligned) {
+#pragma unroll
+        for (int i = 0; i < EPV; i += 4) {
+            float4 v = *(const float4 *)(p + col + i);
+            out[i] = v.x; out[i + 1] = v.y; out[i + 2] = v.z; out[i + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < EPV; ++i) out[i] = i < nv ? p[col + i] : 0.f;
+    }
+}
+
+template <int DT, int BLOCK, int U, bool NT, class F>
+__device__ __forceinline__ void stream_row(const char *r0, const char *r1, int64_t N, bool al0, bool al1, F f) {
+    constexpr int EPV = Io<DT>::EPV;
+    const int64_t nvec = (N + EPV - 1) / EPV;
+    for (int64_t v0 = threadIdx.x; v0 < nvec; v0 += (int64_t)BLOCK * U) {
+        u32x4 d0[U], d1[U];
+        int nv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t v = v0 + (int64_t)u * BLOCK;
+            int64_t r = N - v * EPV;
+            nv[u] = r <= 0 ? 0 : (r >= EPV ? EPV : (int)r);
+            d0[u] = load_vec<DT, NT>(r0, v * EPV, nv[u], al0);
+            if (r1) d1[u] = load_vec<DT, NT>(r1, v * EPV, nv[u], al1);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) f(v0 + (int64_t)u * BLOCK, d0[u], r1 ? d1[u] : d0[u], nv[u]);
+    }
+}
+
+template <int OP, int DT, int BLOCK, int U>
+__global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
+    constexpr int EPV = Io<DT>::EPV, B = Io<DT>::BYTES, NW = BLOCK / 64;
+    constexpr bool FP8 = DT == DT_FP8;
+    constexpr bool TWO = OpTraits<OP>::TWO;
+    __shared__ float red[2 * NW * 3];
+    int parity = 0;
+    const int64_t N = a.N;
+    const float invN = 1.f / (float)N;
+    const bool al0 = a.flags & F_ALIGN0, al1 = a.flags & F_ALIGN1, alo = a.flags & F_ALIGNO,
+               alp = a.flags & F_ALIGNP;
+
+    for (int64_t row = blockIdx.x; row < a.M; row += gridDim.x) {
+        const char *r0 = (const char *)a.in0 + row * a.ld0 * B;
+        const char *r1 = TWO ? (const char *)a.in1 + row * a.ld1 * B : nullptr;
+        char *orow = (char *)a.out + row * a.ldo * B;
+        const bool writer = threadIdx.x == 0;
+
+        if constexpr (OP == OP_SOFTMAX_FWD) {
+            const float K = (FP8 ? a.s0[row] : 1.f) * kLog2e;
+            float st[2] = {-INFINITY, 0.f};  // online base-2 (c, s)
+            stream_row<DT, BLOCK, U, false>(r0, nullptr, N, al0, al1, [&](int64_t, u32x4 v, u32x4, int nv) {
+                float q[EPV];
+                decode<DT>(v, q, 1.f);
+                float bm = -INFINITY;
+#pragma unroll
+                for (int i = 0; i < EPV; ++i)
+                    if (i < nv) bm = fmaxf(bm, q[i]);
+                if (bm == -INFINITY) return;
+                const float cb = bm * K;
+                if (cb > st[0]) {
+                    st[1] = st[0] == -INFINITY ? 0.f : st[1] * fast_exp2(st[0] - cb);
+                    st[0] = cb;
+                }
+#pragma unroll
+                for (int i = 0; i < EPV; ++i)
+                    if (i < nv) st[1] += fast_exp2(fmaf(q[i], K, -st[0]));
+            });
+            block_reduce<NW, 2>(st, MergeSoftmax(), red, parity);
+            const float cmax = st[0], inv_s = 1.f / st[1];
+            const float omul = FP8 ? kFp8Max : inv_s;
+            if (FP8 && writer) a.so[row] = inv_s / kFp8Max;
+            stream_row<DT, BLOCK, U, true>(r0, nullptr, N, al0, al1, [&](int64_t v, u32x4 d, u32x4, int nv) {
+                if (nv == 0) return;
+                float q[EPV], y[EPV];
+                decode<DT>(d, q, 1.f);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, -cmax)) * omul;
+                store_vec<DT>(orow, v * EPV, nv, alo, encode<DT>(y, 1.f));
+            });
+        } else if constexpr (OP == OP_LN_FWD || OP == OP_RMS_FWD || OP == OP_LN_BWD || OP == OP_RMS_BWD) {
+            constexpr bool LN = OP == OP_LN_FWD || OP == OP_LN_BWD;
+            constexpr bool BWD = OP == OP_LN_BWD || OP == OP_RMS_BWD;
+            const float xs = FP8 ? a.s0[row] : 1.f;
+            const float gs = (FP8 && BWD) ? a.s1[row] : 1.f;
+            float mean = 0.f, rstd = 0.f;
+            if (!BWD || (a.flags & F_RECOMPUTE)) {
+                if constexpr (LN) {
+                    // Chan merge of exact per-vector (count, mean, M2).
+                    float st[3] = {0.f, 0.f, 0.f};
+                    stream_row<DT, BLOCK, U, false>(r0, nullptr, N, al0, al1, [&](int64_t, u32x4 v, u32x4, int nv) {
+                        if (nv == 0) return;
+                        float x[EPV];
+                        decode<DT>(v, x, xs);
+                        float s = 0.f;
+#pragma unroll
+                        for (int i = 0; i < EPV; ++i) s += x[i];
+                        const float n = (float)nv, m = s / n;
+                        float m2 = 0.f;
+#pragma unroll
+                        for (int i = 0; i < EPV; ++i) {
+                            float d = x[i] - m;
+                            if (i < nv) m2 = fmaf(d, d, m2);
+                        }
+                        chan_merge(st[0], st[1], st[2], n, m, m2);
+                    });
+                    block_reduce<NW, 3>(st, MergeChan(), red, parity);
+                    mean = st[1];
+                    rstd = rsqrtf(st[2] * invN + a.eps);
+                } else {
+                    float st[1] = {0.f};
+                    stream_row<DT, BLOCK, U, false>(r0, nullptr, N, al0, al1, [&](int64_t, u32x4 v, u32x4, int) {
+                        float x[EPV];
+                        decode<DT>(v, x, xs);
+#pragma unroll
+                        for (int i = 0; i < EPV; ++i) st[0] = fmaf(x[i], x[i], st[0]);
+                    });
+                    block_reduce<NW, 1>(st, MergeSum(), red, parity);
+                    rstd = rsqrtf(st[0] * invN + a.eps);
+                }
+                if (writer) {
+                    if (a.mean_out) a.mean_out[row] = mean;
+                    if (a.rstd_out) a.rstd_out[row] = rstd;
+                }
+            } else {
+                if constexpr (LN) mean = a.mean_in[row];
+                rstd = a.rstd_in[row];
+            }
+            float c1 = 0.f, c2 = 0.f;
+            if constexpr (BWD) {
+                float st[2] = {0.f, 0.f};
+                stream_row<DT, BLOCK, U, false>(r0, r1, N, al0, al1, [&](int64_t v, u32x4 dxv, u32x4 dyv, int nv) {
+                    float x[EPV], dy[EPV], gm[EPV];
+                    decode<DT>(dxv, x, xs);
+                    decode<DT>(dyv, dy, gs);
+                    load_params_n<DT>(a.gamma, v * EPV, nv, alp, gm);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) {
+                        float xh = (x[i] - mean) * rstd;
+                        float g = dy[i] * gm[i];
+                        st[0] += g;
+                        st[1] = fmaf(g, xh, st[1]);
+                    }
+                });
+                block_reduce<NW, 2>(st, MergeSum(), red, parity);
+                c1 = LN ? st[0] * invN : 0.f;
+                c2 = st[1] * invN;
+            }
+            auto apply = [&](int64_t v, u32x4 d0v, u32x4 d1v, int nv, float *y) {
+                float x[EPV], gm[EPV];
+                decode<DT>(d0v, x, xs);
+                load_params_n<DT>(a.gamma, v * EPV, nv, alp, gm);
+                if constexpr (BWD) {
+                    float dy[EPV];
+                    decode<DT>(d1v, dy, gs);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) {
+                        float xh = (x[i] - mean) * rstd;
+                        y[i] = rstd * (dy[i] * gm[i] - c1 - xh * c2);
+                    }
+                } else if constexpr (LN) {
+                    float bb[EPV];
+                    load_params_n<DT>(a.beta, v * EPV, nv, alp, bb);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) y[i] = fmaf((x[i] - mean) * rstd, gm[i], bb[i]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) y[i] = x[i] * rstd * gm[i];
+                }
+            };
+            float oinv = 1.f;
+            if constexpr (FP8) {
+                float am[1] = {0.f};
+                stream_row<DT, BLOCK, U, false>(r0, r1, N, al0, al1, [&](int64_t v, u32x4 d0v, u32x4 d1v, int nv) {
+                    float y[EPV];
+                    apply(v, d0v, d1v, nv, y);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i)
+                        if (i < nv) am[0] = fmaxf(am[0], fabsf(y[i]));
+                });
+                block_reduce<NW, 1>(am, MergeMax(), red, parity);
+                oinv = am[0] > 0.f ? kFp8Max / am[0] : 1.f;
+                if (writer) a.so[row] = am[0] > 0.f ? am[0] / kFp8Max : 1.f;
+            }
+            stream_row<DT, BLOCK, U, true>(r0, r1, N, al0, al1, [&](int64_t v, u32x4 d0v, u32x4 d1v, int nv) {
+                if (nv == 0) return;
+                float y[EPV];
+                apply(v, d0v, d1v, nv, y);
+                store_vec<DT>(orow, v * EPV, nv, alo, encode<DT>(y, oinv));
+            });
+        } else {  // OP_SOFTMAX_BWD
+            const float ys = FP8 ? a.s0[row] : 1.f, gs = FP8 ? a.s1[row] : 1.f;
+            float st[1] = {0.f};
+            stream_row<DT, BLOCK, U, false>(r0, r1, N, al0, al1, [&](int64_t, u32x4 yv, u32x4 gv, int) {
+                float y[EPV], g[EPV];
+                decode<DT>(yv, y, ys);
+                decode<DT>(gv, g, gs);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) st[0] = fmaf(g[i], y[i], st[0]);
+            });
+            block_reduce<NW, 1>(st, MergeSum(), red, parity);
+            const float cs = st[0];
+            float oinv = 1.f;
+            if constexpr (FP8) {
+                float am[1] = {0.f};
+                stream_row<DT, BLOCK, U, false>(r0, r1, N, al0, al1, [&](int64_t, u32x4 yv, u32x4 gv, int) {
+                    float y[EPV], g[EPV];
+                    decode<DT>(yv, y, ys);
+                    decode<DT>(gv, g, gs);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) am[0] = fmaxf(am[0], fabsf(y[i] * (g[i] - cs)));
+                });
+                block_reduce<NW, 1>(am, MergeMax(), red, parity);
+                oinv = am[0] > 0.f ? kFp8Max / am[0] : 1.f;
+                if (writer) a.so[row] = am[0] > 0.f ? am[0] / kFp8Max : 1.f;
+            }
+            stream_row<DT, BLOCK, U, true>(r0, r1, N, al0, al1, [&](int64_t v, u32x4 yv, u32x4 gv, int nv) {
+                if (nv == 0) return;
+                float y[EPV], g[EPV], dx[EPV];
+                decode<DT>(yv, y, ys);
+                decode<DT>(gv, g, gs);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) dx[i] = y[i] * (g[i] - cs);
+                store_vec<DT>(orow, v * EPV, nv, alo, encode<DT>(dx, oinv));
+            });
+        }
+    }
+}
+
+// dgamma / dbeta partials for the two-pass normalisation backward: block
+// (bx, by) covers 256 column vectors and the rows [by*M/RB, (by+1)*M/RB);
+// partial[by][p][col] = sum over those rows of dy*xhat (p = 0) and dy (p = 1).
+template <int DT, bool LN>
+__global__ __launch_bounds__(256) void k_colstats(RowArgs a, int rowblocks) {
+    constexpr int EPV = Io<DT>::EPV, B = Io<DT>::BYTES, NCP = LN ? 2 : 1;
+    constexpr bool FP8 = DT == DT_FP8;
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t col = v * EPV;
+    const int64_t r = a.N - col;
+    const int nv = r <= 0 ? 0 : (r >= EPV ? EPV : (int)r);
+    if (nv == 0) return;
+    const int64_t rb = blockIdx.y;
+    const int64_t m0 = rb * a.M / rowblocks, m1 = (rb + 1) * a.M / rowblocks;
+    const bool al0 = a.flags & F_ALIGN0, al1 = a.flags & F_ALIGN1;
+    float ag[EPV], ab[EPV];
+#pragma unroll
+    for (int i = 0; i < EPV; ++i) ag[i] = ab[i] = 0.f;
+    for (int64_t m = m0; m < m1; ++m) {
+        const float xs = FP8 ? a.s0[m] : 1.f, gs = FP8 ? a.s1[m] : 1.f;
+        const float mean = LN ? a.mean_in[m] : 0.f, rstd = a.rstd_in[m];
+        float x[EPV], dy[EPV];
+        decode<DT>(load_vec<DT, true>((const char *)a.in0 + m * a.ld0 * B, col, nv, al0), x, xs);
+        decode<DT>(load_vec<DT, true>((const char *)a.in1 + m * a.ld1 * B, col, nv, al1), dy, gs);
+#pragma unroll
+        for (int i = 0; i < EPV; ++i) {
+            ag[i] = fmaf(dy[i], (x[i] - mean) * rstd, ag[i]);
+            ab[i] += dy[i];
+        }
+    }
+    float *dst = a.colpart + rb * NCP * a.N;
+#pragma unroll
+    for (int i = 0; i < EPV; ++i) {
+        if (i < nv) {
+            dst[col + i] = ag[i];
+            if (LN) dst[a.N + col + i] = ab[i];
+        }
+    }
+}
+
+}  // namespace credit

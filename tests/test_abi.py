@@ -1,0 +1,101 @@
+"""The C-ABI library loads on a machine without a GPU and exports every entry
+point include/credit.h declares; host-only logic (plan legality, geometry,
+features, argument validation) behaves as documented.  CPU only."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "credit.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(credit_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_operator_boundary():
+    names = declared_functions()
+    for op in ("softmax", "layernorm", "rmsnorm"):
+        for d in ("fwd", "bwd"):
+            assert f"credit_{op}_{d}" in names
+    for extra in ("credit_create", "credit_destroy", "credit_select", "credit_workspace_size", "credit_time_plan",
+                  "credit_mlp_train", "credit_check_errors", "credit_status_string", "credit_load_model"):
+        assert extra in names
+
+
+def test_library_exports_every_declared_symbol(lib_built):
+    from paper_2609_01864_amd import credit
+
+    out = subprocess.run(["nm", "-D", "--defined-only", credit.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        getattr(lib_built, n)  # resolvable through ctypes as well
+
+
+def test_status_strings_and_version(lib_built):
+    from paper_2609_01864_amd import credit as C
+
+    assert C.status_string(C.OK) == "CREDIT_OK"
+    assert C.status_string(C.ERR_TIMEOUT) == "CREDIT_ERR_TIMEOUT"
+    assert "gfx950" in C.version()
+
+
+def test_plan_classes_and_features(lib_built):
+    from paper_2609_01864_amd import credit as C
+
+    plans = [C.plan_of_class(c).as_tuple() for c in range(C.NUM_PLANS)]
+    assert plans == [(0, 1), (1, 1), (2, 2), (2, 4), (2, 8), (2, 16), (2, 32)]
+    f = C.features(C.LAYERNORM, C.BWD, C.BF16, 2048, 131072)
+    assert list(f[:7]) == [0, 1, 0, 1, 0, 1, 0]
+    assert f[7] == 11 and f[8] == 17 and f[9] == np.log2(131072 * 2 * 2)
+    assert np.isclose(f[10], np.log2(2048 * 131072 * 2 * 3)) and f[11] == 3
+
+
+def test_host_legality_follows_capacity(lib_built):
+    from paper_2609_01864_amd import credit as C
+
+    L = C.lib()
+    # FP32 forward: one workgroup holds up to 256 threads x 32 vectors x 4 = 32768 elements
+    ok = lambda N, p: L.credit_plan_legal(None, C.SOFTMAX, C.FWD, C.F32, 64, N, ctypes.byref(p)) == C.OK
+    assert ok(32768, C.plan("resident"))
+    assert not ok(32769, C.plan("resident"))
+    assert ok(32769, C.plan("split", 2))
+    assert ok(1 << 20, C.plan("split", 32))
+    assert not ok((1 << 20) + 1, C.plan("split", 32))
+    assert ok(1 << 24, C.plan("two_pass"))
+    # malformed plans
+    assert L.credit_plan_legal(None, 0, 0, 0, 64, 1024, ctypes.byref(C.plan("split", 3))) == C.ERR_UNSUPPORTED
+    assert L.credit_plan_legal(None, 0, 0, 0, 64, 1024, ctypes.byref(C.plan("resident", 2))) == C.ERR_UNSUPPORTED
+    assert L.credit_plan_legal(None, 0, 0, 0, 64, 0, ctypes.byref(C.plan("resident"))) == C.ERR_INVALID_ARG
+    # backward holds two tensors and (norms) FP32 column partials: smaller slices
+    assert L.credit_plan_legal(None, C.LAYERNORM, C.BWD, C.F32, 8, 8192, ctypes.byref(C.plan("resident"))) == C.OK
+    assert L.credit_plan_legal(None, C.LAYERNORM, C.BWD, C.F32, 8, 8193,
+                               ctypes.byref(C.plan("resident"))) == C.ERR_UNSUPPORTED
+
+
+def test_geometry_is_persistent_and_xcd_rounded(lib_built):
+    from paper_2609_01864_amd import credit as C
+
+    g = C.plan_geometry(None, C.RMSNORM, C.FWD, C.F32, 1024, 524288, C.plan("split", 16))
+    assert C.plan_geometry(None, C.RMSNORM, C.FWD, C.F32, 1024, 524288, C.plan("split", 8)) is None
+    assert g["block"] == 256 and g["grid"] % 128 == 0  # multiple of 8 * k
+    assert g["grid"] // 8 <= 1024
+    g1 = C.plan_geometry(None, C.RMSNORM, C.FWD, C.F32, 5, 1000, C.plan("resident"))
+    assert g1["grid"] == 5
+
+
+def test_null_handle_rejected_by_operators(lib_built):
+    from paper_2609_01864_amd import credit as C
+
+    s = C.lib().credit_softmax_fwd(None, 4, 4, C.F32, None, 4, None, None, 4, None, None, None, 0, None)
+    assert s == C.ERR_INVALID_ARG

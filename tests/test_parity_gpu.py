@@ -1,0 +1,126 @@
+"""GPU parity: every operator x dtype x legal plan against the FP64 oracle on
+the same seeded inputs, at small shapes spanning several vectors, ragged
+tails, tiny rows, more rows than row groups, padded and misaligned rows."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2609_01864_amd import credit as C
+
+from _cases import ALL_PLANS, OPNUM, OPS, Case, check_case
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 1), (3, 7), (5, 17), (2, 33), (37, 1000), (4, 4097), (3, 20011)]
+
+
+def legal_plans(h, op, dtype, M, N):
+    o, d = OPNUM[op]
+    out = []
+    for v, k in ALL_PLANS:
+        p = C.plan(v, k)
+        if h.plan_legal(o, d, C.DTYPE_NAMES[dtype], M, N, p):
+            out.append(p)
+    return out
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("M,N", SHAPES)
+def test_parity_small(gpu_handle, op, dtype, M, N):
+    print(f"[parity] {op} {dtype} M={M} N={N}", flush=True)
+    case = Case(op, dtype, M, N, seed=M * 1000 + N)
+    ref = case.reference()
+    plans = legal_plans(gpu_handle, op, dtype, M, N)
+    assert any(p.variant == C.TWO_PASS for p in plans)
+    for p in plans:
+        out = case.run(gpu_handle, p, ref=ref)
+        try:
+            check_case(case, out, ref)
+        except AssertionError as e:
+            raise AssertionError(f"{p}: {e}") from None
+
+
+@pytest.mark.parametrize("op", ["layernorm_bwd", "rmsnorm_bwd"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_parity_backward_recomputed_statistics(gpu_handle, op, dtype):
+    M, N = 9, 3001
+    case = Case(op, dtype, M, N, seed=7, recompute=True)
+    ref = case.reference()
+    for p in legal_plans(gpu_handle, op, dtype, M, N):
+        print(f"[recompute] {op} {dtype} {p}", flush=True)
+        check_case(case, case.run(gpu_handle, p, ref=ref), ref)
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("ld_pad,offset", [(4, 0), (1, 1), (3, 5)])
+def test_parity_strided_and_misaligned(gpu_handle, op, dtype, ld_pad, offset):
+    M, N = 6, 1029
+    case = Case(op, dtype, M, N, seed=11)
+    ref = case.reference()
+    for p in legal_plans(gpu_handle, op, dtype, M, N):
+        print(f"[strided] {op} {dtype} pad={ld_pad} off={offset} {p}", flush=True)
+        check_case(case, case.run(gpu_handle, p, ld_pad=ld_pad, offset=offset, ref=ref), ref)
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_more_rows_than_row_groups(gpu_handle, op):
+    # few concurrent row groups force every persistent group through many rows
+    M, N = 203, 777
+    case = Case(op, "f32", M, N, seed=3)
+    ref = case.reference()
+    gpu_handle.set_option(C.OPT_MAX_GROUPS, 3)
+    try:
+        for p in legal_plans(gpu_handle, op, "f32", M, N):
+            if p.variant == C.TWO_PASS:
+                continue
+            print(f"[groups=3] {op} {p}", flush=True)
+            check_case(case, case.run(gpu_handle, p, ref=ref), ref)
+    finally:
+        gpu_handle.set_option(C.OPT_MAX_GROUPS, 0)
+
+
+def test_softmax_config0_all_plans(gpu_handle):
+    # plain FP32 softmax, M = 64 rows x N = 32768, x ~ 4 N(0, 1), seed 0
+    case = Case("softmax_fwd", "f32", 64, 32768, seed=0)
+    ref = case.reference()
+    for p in legal_plans(gpu_handle, "softmax_fwd", "f32", 64, 32768):
+        print(f"[config0] {p}", flush=True)
+        out = case.run(gpu_handle, p, ref=ref)
+        check_case(case, out, ref)
+        # invariant: GPU rows sum to 1 within 1e-6
+        assert np.max(np.abs(out["y"].sum(1) - 1.0)) < 1e-6
+
+
+def test_split_row_is_deterministic(gpu_handle):
+    # the k partials are combined in a fixed order: repeated runs are bitwise equal
+    case = Case("layernorm_fwd", "f32", 64, 65536, seed=5)
+    outs = [case.run(gpu_handle, C.plan("split", 8))["y"] for _ in range(3)]
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+def test_zero_rows_is_a_noop(gpu_handle):
+    x = torch.empty((0, 64), device="cuda")
+    y, _ = C.softmax_fwd(x, h=gpu_handle)
+    assert y.shape == (0, 64)
+    g = torch.ones(64, device="cuda")
+    dx, _, dg, db = C.layernorm_bwd(x, x, g, torch.empty(0, device="cuda"), torch.empty(0, device="cuda"),
+                                    h=gpu_handle)
+    torch.cuda.synchronize()
+    assert torch.all(dg == 0) and torch.all(db == 0)
+
+
+def test_illegal_plan_and_bad_arguments_are_rejected(gpu_handle):
+    x = torch.randn(4, 40000, device="cuda")
+    with pytest.raises(C.CreditError) as e:
+        C.softmax_fwd(x, p=C.plan("resident"), h=gpu_handle)
+    assert e.value.status == C.ERR_UNSUPPORTED
+    L = C.lib()
+    y = torch.empty_like(x)
+    s = L.credit_softmax_fwd(gpu_handle.ptr, 4, 40000, C.F32, x.data_ptr(), 100, None, y.data_ptr(), 40000, None,
+                             None, None, 0, None)
+    assert s == C.ERR_INVALID_ARG  # ld < N
+    s = L.credit_softmax_fwd(gpu_handle.ptr, 4, 40000, C.F32, x.data_ptr(), 40000, None, y.data_ptr(), 40000, None,
+                             None, None, 0, None)
+    assert s == C.ERR_WORKSPACE
