@@ -35,6 +35,7 @@ const void *colreduce_kernel();
 const void *colstats_kernel(int, bool);
 const void *control_kernel();
 const void *zero_kernel();
+const void *flush_kernel();
 const void *fill_kernel();
 const void *copy_kernel();
 const void *encode_kernel(int);
@@ -144,6 +145,7 @@ struct credit_handle_s {
     char *flushbuf = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float copy_gbps = 0.f;
+    std::tuple<int, int, int64_t, int64_t> prepared{-1, -1, -1, -1};  // inputs currently filled
     // learned selector
     bool has_model = false;
     std::vector<float> params = std::vector<float>(kMlpParams, 0.f);
@@ -459,6 +461,7 @@ credit_status_t ensure_arena(credit_handle_t h, size_t bytes) {
     if (h->arena) hipFree(h->arena);
     h->arena = nullptr;
     h->arena_bytes = 0;
+    h->prepared = std::make_tuple(-1, -1, (int64_t)-1, (int64_t)-1);
     size_t want = std::max(bytes, (size_t)64 << 20);
     if (hipMalloc(&h->arena, want) != hipSuccess) {
         h->arena = nullptr;
@@ -466,10 +469,13 @@ credit_status_t ensure_arena(credit_handle_t h, size_t bytes) {
         return CREDIT_ERR_HIP;
     }
     h->arena_bytes = want;
-    if (!h->flushbuf && hipMalloc(&h->flushbuf, kFlushBytes) != hipSuccess) {
-        h->flushbuf = nullptr;
-        hipGetLastError();
-        return CREDIT_ERR_HIP;
+    if (!h->flushbuf) {
+        if (hipMalloc(&h->flushbuf, kFlushBytes) != hipSuccess) {
+            h->flushbuf = nullptr;
+            hipGetLastError();
+            return CREDIT_ERR_HIP;
+        }
+        if (zero_words(h->flushbuf, (int64_t)(kFlushBytes / 4), h->stream) != hipSuccess) return CREDIT_ERR_HIP;
     }
     // deterministic contents: inputs valid for every dtype, workspace zero
     int64_t nwords = (int64_t)(want / 4);
@@ -505,13 +511,16 @@ credit_status_t prepare(credit_handle_t h, int k_op, int dt, int64_t M, int64_t 
     b.ws = p;
     b.ws_bytes = ws_bytes;
     // inputs in the dtype's format; scales / statistics as plain FP32
-    int64_t wmat = (int64_t)(2 * mat / 4);
-    unsigned seed = 7u;
-    void *pin = b.in0;
-    void *a1[] = {&pin, &wmat, &seed, &dt};
-    if (launch(fill_kernel(), 4096, 256, 0, h->stream, a1) != hipSuccess) return CREDIT_ERR_HIP;
+    auto key = std::make_tuple(k_op, dt, M, N);
+    if (h->prepared != key) {
+        int64_t wmat = (int64_t)(2 * mat / 4);
+        unsigned seed = 7u;
+        void *pin = b.in0;
+        void *a1[] = {&pin, &wmat, &seed, &dt};
+        if (launch(fill_kernel(), 4096, 256, 0, h->stream, a1) != hipSuccess) return CREDIT_ERR_HIP;
+        h->prepared = key;
+    }
     if (zero_words(b.ws, (int64_t)(align256(ws_bytes) / 4), h->stream) != hipSuccess) return CREDIT_ERR_HIP;
-    (void)k_op;
     return CREDIT_OK;
 }
 
@@ -537,7 +546,11 @@ float median(std::vector<float> v) {
 }
 
 credit_status_t flush(credit_handle_t h) {
-    return zero_words(h->flushbuf, (int64_t)(kFlushBytes / 4), h->stream) == hipSuccess ? CREDIT_OK : CREDIT_ERR_HIP;
+    const void *p = h->flushbuf;
+    int64_t n = (int64_t)(kFlushBytes / 16);
+    unsigned *sink = h->errflag + 32;  // never matched: the flag word stays untouched
+    void *args[] = {&p, &n, &sink};
+    return launch(flush_kernel(), h->cus * 8, 256, 0, h->stream, args) == hipSuccess ? CREDIT_OK : CREDIT_ERR_HIP;
 }
 
 template <class F> credit_status_t time_median(credit_handle_t h, int reps, int do_flush, F issue_fn, float *us) {
@@ -587,13 +600,16 @@ credit_status_t time_control(credit_handle_t h, int k_op, int dt, int64_t M, int
     // pin the control kernel to the same workgroups per CU
     size_t shmem = (size_t)(kLdsBytes / std::max(1, L.per_cu)) - 1024;
     if (occupancy(h, control_kernel(), kBlockThreads, shmem) > L.per_cu) shmem += 512;
-    Bufs b;
-    st = prepare(h, k_op, dt, M, N, L.ws_bytes, b);
+    // the control kernel touches no row data: only a zeroed workspace for its slots
+    st = ensure_arena(h, align256(L.ws_bytes));
     if (st != CREDIT_OK) return st;
+    char *ws = h->arena + h->arena_bytes - align256(L.ws_bytes);
+    if (zero_words(ws, (int64_t)(align256(L.ws_bytes) / 4), h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+    h->prepared = std::make_tuple(-1, -1, (int64_t)-1, (int64_t)-1);  // may overlap prepared inputs
     RowArgs a;
     std::memset(&a, 0, sizeof(a));
     a.M = M; a.N = N; a.k = L.k; a.groups = L.groups;
-    a.slots = (unsigned long long *)(b.ws + L.off_slots);
+    a.slots = (unsigned long long *)(ws + L.off_slots);
     a.errflag = h->errflag;
     a.spin_limit = (unsigned)std::min<int64_t>(h->spin_limit, 0xffffffffLL);
     int stages = stages_of(k_op, dt, false);

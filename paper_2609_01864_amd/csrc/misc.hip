@@ -61,6 +61,20 @@ __global__ __launch_bounds__(256) void k_zero(unsigned *p, int64_t n) {
 }
 const void *zero_kernel() { return (const void *)&k_zero; }
 
+// Cache flush by reading: streams n 16-byte vectors so the L2s and the
+// Infinity Cache hold clean lines of this buffer, not the operator's data
+// (a write sweep would leave dirty lines to be written back during the
+// timed kernel).  The sink is written only on an impossible sum.
+__global__ __launch_bounds__(256) void k_flush_read(const u32x4 *__restrict__ p, int64_t n, unsigned *sink) {
+    unsigned acc = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        u32x4 v = p[i];
+        acc ^= v[0] ^ v[1] ^ v[2] ^ v[3];
+    }
+    if (acc == 0x9e3779b9u && threadIdx.x == 0x1ff) sink[0] = acc;
+}
+const void *flush_kernel() { return (const void *)&k_flush_read; }
+
 // Deterministic pseudo-random fill of a timing buffer with values valid for
 // the dtype: FP32 / BF16 in [-2, 2), FP8 any finite code.
 __device__ __forceinline__ unsigned mix32(unsigned long long x) {

@@ -11,16 +11,16 @@
 // Eq. (5)).  It then applies h to its own retained slice and writes it.  The
 // workgroup is persistent: row group `grp` processes rows grp, grp + groups, ...
 //
-// Slot j of thread t holds vector j * 256 + t of the slice.  Three row loops
-// exist, chosen once per workgroup (the choice is uniform, and every loop
-// contains workgroup barriers):
+// Slot j of thread t holds vector j * 256 + t of the slice.  Two row loops
+// exist, chosen once per workgroup (the choice is uniform, and both contain
+// workgroup barriers):
 //   AL && FULLS   every slot of every thread is a full, 16-byte aligned vector:
 //                 straight-line 128-bit loads and stores, no masks;
-//   AL && !FULLS  aligned rows, slice not an exact multiple: slots past the
-//                 last full vector re-read the slice's first vector and are
-//                 zeroed / masked, the trailing partial vector (if any) is
-//                 handled by its owner;
-//   !AL           misaligned rows: element-wise accesses, same masking.
+//   !AL, !FULLS   any alignment and length: 128-bit accesses through
+//                 under-aligned pointer types; slots past the last full vector
+//                 re-read the slice's first vector and are zeroed / masked; the
+//                 trailing partial vector (< 16 bytes) is handled element-wise
+//                 by the thread that owns it.
 #pragma once
 #include "device.h"
 
@@ -41,32 +41,39 @@ template <int OP, int DT, int VPT> constexpr int resident_waves() {
     return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
-// Aligned accesses address a slot as (uniform base pointer, 32-bit per-thread
-// byte offset), so the compiler emits SGPR-base + VGPR-offset instructions and
-// keeps no 64-bit address per slot alive across passes.
-__device__ __forceinline__ u32x4 vload_nt(const char *base, uint32_t off) {
-    return __builtin_nontemporal_load((const u32x4 *)(base + off));
+// Slots are addressed as (uniform base pointer, 32-bit per-thread byte
+// offset), so the compiler emits SGPR-base + VGPR-offset instructions and keeps
+// no 64-bit address per slot alive across passes.  AL: 16-byte aligned
+// pointer types; otherwise the same 128-bit accesses through 1-byte aligned
+// types (gfx950 runs in unaligned-access mode), so rows of any alignment keep
+// vector loads and stores.
+typedef u32x4 u32x4_u __attribute__((aligned(1)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef f32x4 f32x4_u __attribute__((aligned(1)));
+
+template <bool AL> __device__ __forceinline__ u32x4 vload_nt(const char *base, uint32_t off) {
+    if constexpr (AL)
+        return __builtin_nontemporal_load((const u32x4 *)(base + off));
+    else
+        return __builtin_nontemporal_load((const u32x4_u *)(base + off));
 }
-__device__ __forceinline__ void vstore_nt(char *base, uint32_t off, u32x4 v) {
-    __builtin_nontemporal_store(v, (u32x4 *)(base + off));
+template <bool AL> __device__ __forceinline__ void vstore_nt(char *base, uint32_t off, u32x4 v) {
+    if constexpr (AL)
+        __builtin_nontemporal_store(v, (u32x4 *)(base + off));
+    else
+        __builtin_nontemporal_store(v, (u32x4_u *)(base + off));
 }
 
-// EPV FP32 parameters (gamma / beta) of one vector slot: aligned form from a
-// uniform base and a byte offset; element-wise form for misaligned rows.
-template <int DT>
-__device__ __forceinline__ void load_params_al(const float *base, uint32_t off, float *out) {
+// EPV FP32 parameters (gamma / beta) of one vector slot.
+template <int DT, bool AL>
+__device__ __forceinline__ void load_params_v(const float *base, uint32_t off, float *out) {
     constexpr int EPV = Io<DT>::EPV;
     const char *p = (const char *)base + off;
 #pragma unroll
     for (int i = 0; i < EPV; i += 4) {
-        float4 v = *(const float4 *)(p + 4 * i);
+        f32x4 v = AL ? *(const f32x4 *)(p + 4 * i) : *(const f32x4_u *)(p + 4 * i);
         out[i] = v.x; out[i + 1] = v.y; out[i + 2] = v.z; out[i + 3] = v.w;
     }
-}
-template <int DT>
-__device__ __forceinline__ void load_params_el(const float *p, int64_t col, bool ok, float *out) {
-#pragma unroll
-    for (int i = 0; i < Io<DT>::EPV; ++i) out[i] = ok ? p[col + i] : 0.f;
 }
 
 // Parameters of the trailing partial vector (n valid elements, n < EPV).
@@ -180,41 +187,33 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
         uint32_t toff = (uint32_t)tid * 16u, poff = (uint32_t)tid * (EPV * 4u);
         asm volatile("" : "+v"(toff));
         asm volatile("" : "+v"(poff));
-        // masked slots read the slice's first vector (AL needs nfv >= 1); their
-        // data is zeroed before use and their stores are skipped
+        // masked slots re-read the slice's first vector (only when nfv >= 1);
+        // their data is zeroed before use and their stores are skipped
         auto doff = [&](int j) -> uint32_t {
             return (FULLS || ok_of(j)) ? toff + (uint32_t)j * (kBlock * 16u) : 0u;
         };
         auto pofs = [&](int j) -> uint32_t {
             return (FULLS || ok_of(j)) ? poff + (uint32_t)j * (kBlock * EPV * 4u) : 0u;
         };
-        auto LD = [&](const char *base, const char *rowp, int j) -> u32x4 {
-            if constexpr (AL)
-                return vload_nt(base, doff(j));
-            else
-                return load_vec<DT, false>(rowp, col_of(j), ok_of(j) ? EPV : 0, false);
-        };
         auto ST = [&](int j, u32x4 v) {
-            if (FULLS || ok_of(j)) {
-                if constexpr (AL)
-                    vstore_nt(bo, toff + (uint32_t)j * (kBlock * 16u), v);
-                else
-                    store_vec<DT>(orow, col_of(j), EPV, false, v);
-            }
+            if (FULLS || ok_of(j)) vstore_nt<AL>(bo, toff + (uint32_t)j * (kBlock * 16u), v);
         };
-        auto PAR = [&](const float *p, int j, float *out) {
-            if constexpr (AL)
-                load_params_al<DT>(p + sl.c0, pofs(j), out);
-            else
-                load_params_el<DT>(p, col_of(j), ok_of(j), out);
-        };
+        auto PAR = [&](const float *p, int j, float *out) { load_params_v<DT, AL>(p + sl.c0, pofs(j), out); };
         u32x4 d0[VPT];
         u32x4 d1[T::TWO ? VPT : 1];
+        if (FULLS || sl.nfv > 0) {  // uniform: a slice without full vectors issues no vector load
 #pragma unroll
-        for (int j = 0; j < VPT; ++j) d0[j] = LD(b0, r0, j);
-        if constexpr (T::TWO) {
+            for (int j = 0; j < VPT; ++j) d0[j] = vload_nt<AL>(b0, doff(j));
+            if constexpr (T::TWO) {
 #pragma unroll
-            for (int j = 0; j < VPT; ++j) d1[j] = LD(b1, r1, j);
+                for (int j = 0; j < VPT; ++j) d1[j] = vload_nt<AL>(b1, doff(j));
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                d0[j] = u32x4{0u, 0u, 0u, 0u};
+                if constexpr (T::TWO) d1[j] = u32x4{0u, 0u, 0u, 0u};
+            }
         }
         u32x4 t0 = {0u, 0u, 0u, 0u}, t1 = {0u, 0u, 0u, 0u};
         if (tail) {
@@ -711,8 +710,6 @@ void k_resident(RowArgs a) {
     const bool al = (a.flags & AL_ALL) == AL_ALL;
     if (al && sl.nval == (int64_t)VPT * kBlock * EPV)
         row_loop<OP, DT, VPT, true, true>(a, c, grp, sl, red, xb);
-    else if (al && sl.nfv >= 1)
-        row_loop<OP, DT, VPT, true, false>(a, c, grp, sl, red, xb);
     else
         row_loop<OP, DT, VPT, false, false>(a, c, grp, sl, red, xb);
 }

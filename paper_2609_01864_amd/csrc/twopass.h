@@ -29,8 +29,24 @@ __device__ __forceinline__ void load_params_n(const float *p, int64_t col, int n
     }
 }
 
+// One vector of a row: full vectors use a 128-bit load through an
+// under-aligned type (any row alignment), the trailing partial vector goes
+// element by element; vectors past the end read as zero.
+template <int DT, bool NT>
+__device__ __forceinline__ u32x4 row_vec(const char *row, int64_t v, int nv) {
+    constexpr int EPV = Io<DT>::EPV, B = Io<DT>::BYTES;
+    if (nv == EPV) {
+        const u32x4_u *p = (const u32x4_u *)(row + v * EPV * B);
+        if constexpr (NT)
+            return __builtin_nontemporal_load(p);
+        else
+            return *p;
+    }
+    return load_vec<DT, false>(row, v * EPV, nv, false);
+}
+
 template <int DT, int BLOCK, int U, bool NT, class F>
-__device__ __forceinline__ void stream_row(const char *r0, const char *r1, int64_t N, bool al0, bool al1, F f) {
+__device__ __forceinline__ void stream_row(const char *r0, const char *r1, int64_t N, bool, bool, F f) {
     constexpr int EPV = Io<DT>::EPV;
     const int64_t nvec = (N + EPV - 1) / EPV;
     for (int64_t v0 = threadIdx.x; v0 < nvec; v0 += (int64_t)BLOCK * U) {
@@ -41,12 +57,22 @@ __device__ __forceinline__ void stream_row(const char *r0, const char *r1, int64
             int64_t v = v0 + (int64_t)u * BLOCK;
             int64_t r = N - v * EPV;
             nv[u] = r <= 0 ? 0 : (r >= EPV ? EPV : (int)r);
-            d0[u] = load_vec<DT, NT>(r0, v * EPV, nv[u], al0);
-            if (r1) d1[u] = load_vec<DT, NT>(r1, v * EPV, nv[u], al1);
+            d0[u] = row_vec<DT, NT>(r0, v, nv[u]);
+            if (r1) d1[u] = row_vec<DT, NT>(r1, v, nv[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) f(v0 + (int64_t)u * BLOCK, d0[u], r1 ? d1[u] : d0[u], nv[u]);
     }
+}
+
+// Stores one vector of a row (full: one under-aligned 128-bit store).
+template <int DT>
+__device__ __forceinline__ void row_store(char *row, int64_t v, int nv, u32x4 x) {
+    constexpr int EPV = Io<DT>::EPV, B = Io<DT>::BYTES;
+    if (nv == EPV)
+        __builtin_nontemporal_store(x, (u32x4_u *)(row + v * EPV * B));
+    else
+        store_vec<DT>(row, v * EPV, nv, false, x);
 }
 
 template <int OP, int DT, int BLOCK, int U>
@@ -97,7 +123,7 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
                 decode<DT>(d, q, 1.f);
 #pragma unroll
                 for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, -cmax)) * omul;
-                store_vec<DT>(orow, v * EPV, nv, alo, encode<DT>(y, 1.f));
+                row_store<DT>(orow, v, nv, encode<DT>(y, 1.f));
             });
         } else if constexpr (OP == OP_LN_FWD || OP == OP_RMS_FWD || OP == OP_LN_BWD || OP == OP_RMS_BWD) {
             constexpr bool LN = OP == OP_LN_FWD || OP == OP_LN_BWD;
@@ -207,7 +233,7 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
                 if (nv == 0) return;
                 float y[EPV];
                 apply(v, d0v, d1v, nv, y);
-                store_vec<DT>(orow, v * EPV, nv, alo, encode<DT>(y, oinv));
+                row_store<DT>(orow, v, nv, encode<DT>(y, oinv));
             });
         } else {  // OP_SOFTMAX_BWD
             const float ys = FP8 ? a.s0[row] : 1.f, gs = FP8 ? a.s1[row] : 1.f;
@@ -242,7 +268,7 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
                 decode<DT>(gv, g, gs);
 #pragma unroll
                 for (int i = 0; i < EPV; ++i) dx[i] = y[i] * (g[i] - cs);
-                store_vec<DT>(orow, v * EPV, nv, alo, encode<DT>(dx, oinv));
+                row_store<DT>(orow, v, nv, encode<DT>(dx, oinv));
             });
         }
     }

@@ -1,0 +1,270 @@
+"""Timing-dataset collection, training and evaluation of the learned plan
+selector, and the regret of every selector against exhaustive timing.
+
+    python -m paper_2609_01864_amd.tune all --out DIR [--shapes 2000] [--model PATH]
+
+collect  For 2000 seeded shapes (op x direction x dtype stratified over the 18
+         combinations; M log-uniform in [1, 16384]; N log-uniform in
+         [1024, 4194304]; at most 16e9 bytes of operator I/O) every legal plan is
+         timed with credit_time_plan (cache flush, median of 15), and the
+         work-free control kernel (Sec. III-D) for k = 1, 2, ..., 32.  Records
+         are appended to a JSONL file keyed by shape, so an interrupted
+         collection resumes where it stopped.
+train    Seeded stratified 80/20 split; soft targets t_c ~ exp(-(T_c/T_best - 1)
+         / tau) over legal plans (tau = 0.02); full-batch Adam on the GPU through
+         credit_mlp_train; the model is saved with credit_save_model.
+eval     Held-out regret T(pick)/T(best) - 1 of the learned, analytic (Eq. (9)
+         with the measured baseline and control timings), peak-bandwidth and
+         fixed-rule selectors.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import credit as C
+
+OPS = [(C.SOFTMAX, C.FWD), (C.LAYERNORM, C.FWD), (C.RMSNORM, C.FWD),
+       (C.SOFTMAX, C.BWD), (C.LAYERNORM, C.BWD), (C.RMSNORM, C.BWD)]
+SPLIT_KS = (2, 4, 8, 16, 32)
+TAU = 0.02
+MAX_IO_BYTES = 16e9
+
+
+def log(msg):
+    print(f"[tune] {msg}", file=sys.stderr, flush=True)
+
+
+def io_bytes(op: int, direction: int, dtype: int, M: int, N: int) -> float:
+    e = {C.F32: 4, C.BF16: 2, C.FP8: 1}[dtype]
+    tensors = 3 if direction == C.BWD else 2
+    return float(M) * N * e * tensors
+
+
+def sample_shapes(n: int = 2000, seed: int = 4):
+    """n shapes stratified over the 18 (op, direction, dtype) combinations."""
+    rng = np.random.default_rng(seed)
+    combos = [(o, d, t) for (o, d) in OPS for t in (C.F32, C.BF16, C.FP8)]
+    out = []
+    i = 0
+    while len(out) < n:
+        o, d, t = combos[i % len(combos)]
+        i += 1
+        while True:
+            M = int(round(math.exp(rng.uniform(math.log(1), math.log(16384)))))
+            N = int(round(math.exp(rng.uniform(math.log(1024), math.log(4194304)))))
+            if io_bytes(o, d, t, M, N) <= MAX_IO_BYTES:
+                break
+        out.append({"op": o, "dir": d, "dt": t, "M": max(1, M), "N": N})
+    return out
+
+
+def key_of(s) -> str:
+    return f"{s['op']}:{s['dir']}:{s['dt']}:{s['M']}:{s['N']}"
+
+
+def legal_classes(h, s):
+    return [c for c in range(C.NUM_PLANS)
+            if h.plan_legal(s["op"], s["dir"], s["dt"], s["M"], s["N"], C.plan_of_class(c))]
+
+
+def collect(h, shapes, path: str, reps: int = 15):
+    done = set()
+    if os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                try:
+                    done.add(key_of(json.loads(line)))
+                except Exception:
+                    pass
+    todo = [s for s in shapes if key_of(s) not in done]
+    # largest first: the timing arena is allocated once
+    todo.sort(key=lambda s: -io_bytes(s["op"], s["dir"], s["dt"], s["M"], s["N"]))
+    log(f"collect: {len(done)} done, {len(todo)} to time -> {path}")
+    t0 = time.time()
+    with open(path, "a") as f:
+        for i, s in enumerate(todo):
+            legal = legal_classes(h, s)
+            times = {}
+            for c in legal:
+                times[str(c)] = h.time_plan(s["op"], s["dir"], s["dt"], s["M"], s["N"], C.plan_of_class(c), reps,
+                                            True)
+            ctrl = {}
+            for k in (1,) + SPLIT_KS:
+                p = C.plan("resident" if k == 1 else "split", k)
+                if k == 1 or h.plan_legal(s["op"], s["dir"], s["dt"], s["M"], s["N"], p):
+                    ctrl[str(k)] = h.time_control(s["op"], s["dir"], s["dt"], s["M"], s["N"], k, 7)
+            rec = dict(s, legal=legal, times=times, ctrl=ctrl,
+                       feats=[float(v) for v in C.features(s["op"], s["dir"], s["dt"], s["M"], s["N"])])
+            f.write(json.dumps(rec) + "\n")
+            f.flush()
+            if (i + 1) % 50 == 0 or i + 1 == len(todo):
+                log(f"collect {i + 1}/{len(todo)} ({time.time() - t0:.0f} s)")
+
+
+def load(path: str):
+    with open(path) as f:
+        return [json.loads(line) for line in f if line.strip()]
+
+
+def split(recs, seed: int = 4, frac: float = 0.8):
+    """Stratified by (op, direction, dtype)."""
+    rng = np.random.default_rng(seed)
+    groups = {}
+    for r in recs:
+        groups.setdefault((r["op"], r["dir"], r["dt"]), []).append(r)
+    train, test = [], []
+    for g in sorted(groups):
+        rs = sorted(groups[g], key=key_of)
+        idx = rng.permutation(len(rs))
+        cut = int(round(frac * len(rs)))
+        train += [rs[i] for i in idx[:cut]]
+        test += [rs[i] for i in idx[cut:]]
+    return train, test
+
+
+def soft_targets(rec, tau: float = TAU):
+    t = np.zeros(C.NUM_PLANS)
+    m = np.zeros(C.NUM_PLANS, np.uint8)
+    times = {int(c): v for c, v in rec["times"].items()}
+    best = min(times.values())
+    for c, v in times.items():
+        t[c] = math.exp(-(v / best - 1.0) / tau)
+        m[c] = 1
+    return t / t.sum(), m
+
+
+def arrays(recs):
+    X = np.array([r["feats"] for r in recs], np.float32)
+    T = np.zeros((len(recs), C.NUM_PLANS), np.float32)
+    Mk = np.zeros((len(recs), C.NUM_PLANS), np.uint8)
+    for i, r in enumerate(recs):
+        T[i], Mk[i] = soft_targets(r)
+    return X, T, Mk
+
+
+def train(h, recs, epochs: int = 4000, lr: float = 3e-3, seed: int = 1):
+    X, T, Mk = arrays(recs)
+    loss = h.mlp_train(X, T, Mk, epochs, lr, seed)
+    log(f"train: {len(recs)} samples, {epochs} epochs, final loss {loss:.4f}")
+    return loss
+
+
+# -------------------------------------------------------------- selectors
+def pick_learned(h, recs):
+    X = np.array([r["feats"] for r in recs], np.float32)
+    logits = h.mlp_predict(X)
+    out = []
+    for i, r in enumerate(recs):
+        legal = [int(c) for c in r["times"]]
+        out.append(max(legal, key=lambda c: logits[i, c]))
+    return out
+
+
+def baseline_class(r):
+    # one-workgroup staged kernel if the row fits, else the global-reread kernel
+    return 1 if "1" in r["times"] else 0
+
+
+def pick_analytic(r, t_base=None):
+    """Eq. (9) with the measured baseline (Eq. (7)) and control excess."""
+    base = baseline_class(r)
+    tb = r["times"][str(base)] if t_base is None else t_base
+    c1 = r["ctrl"].get("1", 0.0)
+    ctrl = [max(0.0, r["ctrl"].get(str(k), c1) - c1) for k in SPLIT_KS]
+    delta = C.model_delta(None, r["op"], r["dir"], r["dt"], r["M"], r["N"], tb, ctrl)
+    best = None
+    for i, k in enumerate(SPLIT_KS):
+        c = 2 + i
+        if str(c) not in r["times"] or not np.isfinite(delta[i]) or delta[i] <= 0:
+            continue
+        if best is None or delta[i] > delta[best - 2]:
+            best = c
+    return base if best is None else best
+
+
+def pick_peak(r, copy_gbps: float):
+    """The same rule with the baseline priced at copy bandwidth (Table V row 1)."""
+    w = C.workload_info(r["op"], r["dir"], r["dt"])
+    tb = r["M"] * r["N"] * w.b_base / (copy_gbps * 1e3)  # us
+    dep = r["M"] * r["N"] * w.b_keep / (copy_gbps * 1e3)
+    base = baseline_class(r)
+    c1 = r["ctrl"].get("1", 0.0)
+    ctrl = [max(0.0, r["ctrl"].get(str(k), c1) - c1) for k in SPLIT_KS]
+    delta = C.model_delta(None, r["op"], r["dir"], r["dt"], r["M"], r["N"], tb, ctrl) - dep
+    best = None
+    for i in range(5):
+        c = 2 + i
+        if str(c) in r["times"] and np.isfinite(delta[i]) and delta[i] > 0 and (best is None or delta[i] > delta[best - 2]):
+            best = c
+    return base if best is None else best
+
+
+def pick_fixed(r):
+    for c in range(1, C.NUM_PLANS):
+        if str(c) in r["times"]:
+            return c
+    return 0
+
+
+def regret_stats(recs, picks):
+    ratios = []
+    for r, c in zip(recs, picks):
+        times = {int(k): v for k, v in r["times"].items()}
+        ratios.append(times[c] / min(times.values()))
+    a = np.array(ratios)
+    return {"geomean": float(np.exp(np.mean(np.log(a)))), "p95": float(np.percentile(a, 95)),
+            "max": float(a.max()), "share_within_5pct": float(np.mean(a <= 1.05)),
+            "exact": float(np.mean(a <= 1.0 + 1e-9)), "n": int(a.size)}
+
+
+def evaluate(h, recs, copy_gbps: float):
+    out = {"learned": regret_stats(recs, pick_learned(h, recs)),
+           "analytic": regret_stats(recs, [pick_analytic(r) for r in recs]),
+           "peak": regret_stats(recs, [pick_peak(r, copy_gbps) for r in recs]),
+           "fixed": regret_stats(recs, [pick_fixed(r) for r in recs]),
+           "always_two_pass": regret_stats(recs, [0 for _ in recs])}
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["collect", "train", "eval", "all"])
+    ap.add_argument("--out", default="tune_out")
+    ap.add_argument("--shapes", type=int, default=2000)
+    ap.add_argument("--reps", type=int, default=15)
+    ap.add_argument("--epochs", type=int, default=4000)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--model", default=None)
+    args = ap.parse_args(argv)
+    os.makedirs(args.out, exist_ok=True)
+    data = os.path.join(args.out, "timings.jsonl")
+    model = args.model or os.path.join(args.out, "selector_gfx950.txt")
+    h = C.Handle(0, load_default_model=False)
+    if args.cmd in ("collect", "all"):
+        collect(h, sample_shapes(args.shapes), data, args.reps)
+    recs = load(data)
+    tr, te = split(recs)
+    if args.cmd in ("train", "all"):
+        train(h, tr, args.epochs, args.lr)
+        h.save_model(model)
+        log(f"saved {model}")
+    if args.cmd in ("eval", "all"):
+        if args.cmd == "eval":
+            assert h.load_model(model) == C.OK, "model failed to load"
+        copy = h.copy_bandwidth(1 << 30, 7)
+        res = {"held_out": evaluate(h, te, copy), "train": evaluate(h, tr, copy), "copy_gbps": copy,
+               "n_train": len(tr), "n_test": len(te)}
+        with open(os.path.join(args.out, "regret.json"), "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res["held_out"]), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,88 @@
+"""The learned selector's HIP kernels (forward, masked soft-target loss and
+gradient, Adam) against the FP64 CPU network from identical parameters, model
+file round trip and rejection, and learnability of a known rule."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+from paper_2609_01864_amd import credit as C
+
+pytestmark = pytest.mark.gpu
+NC = C.NUM_PLANS
+
+
+def _case(n=257, seed=0):
+    rng = np.random.default_rng(seed)
+    params = (rng.standard_normal(ref.num_params(NC)) * 0.2).astype(np.float32)
+    feats = (rng.standard_normal((n, 12)) * 3 + 2).astype(np.float32)
+    mu = feats.mean(0).astype(np.float32)
+    sd = (feats.std(0) + 0.5).astype(np.float32)
+    mask = (rng.random((n, NC)) < 0.6).astype(np.uint8)
+    mask[:, 0] = 1
+    t = rng.random((n, NC)) * mask
+    t = (t / t.sum(1, keepdims=True)).astype(np.float32)
+    return params, mu, sd, feats, t, mask
+
+
+def test_param_count_matches_reference(lib_built):
+    assert C.lib().credit_mlp_num_params() == ref.num_params(NC) == 12 * 64 + 64 + 64 * 64 + 64 + NC * 64 + NC
+
+
+def test_forward_and_gradient_match_fp64(gpu_handle):
+    params, mu, sd, feats, t, mask = _case()
+    gpu_handle.mlp_set(params, mu, sd)
+    logits = gpu_handle.mlp_predict(feats)
+    rl, _ = ref.forward(params, mu, sd, feats, NC)
+    assert np.max(np.abs(logits - rl)) <= 1e-5 * max(1.0, np.abs(rl).max())
+    loss, g = gpu_handle.mlp_grad(feats, t, mask)
+    rloss, rg = ref.loss_and_grad(params, mu, sd, feats, t, mask.astype(bool), NC)
+    assert abs(loss - rloss) <= 1e-5 * max(1.0, abs(rloss))
+    assert np.max(np.abs(g - rg)) <= 1e-5 * max(1e-3, np.abs(rg).max())
+
+
+def test_one_adam_step_matches_fp64(gpu_handle):
+    params, mu, sd, feats, t, mask = _case(seed=1)
+    gpu_handle.mlp_set(params, mu, sd)
+    gpu_handle.mlp_train(feats, t, mask, epochs=1, lr=1e-3, seed=0)
+    got, _, _ = gpu_handle.mlp_get()
+    _, rg = ref.loss_and_grad(params, mu, sd, feats, t, mask.astype(bool), NC)
+    want, _, _ = ref.adam_step(params.astype(np.float64), rg, np.zeros_like(rg), np.zeros_like(rg), 1, 1e-3)
+    # the first step moves each weight by ~lr: compare the step itself
+    step, rstep = got - params, want - params
+    assert np.max(np.abs(step - rstep)) <= 1e-5 * 1e-3 + 2e-7
+
+
+def test_training_learns_a_rule_and_reduces_loss(gpu_handle):
+    rng = np.random.default_rng(3)
+    n = 600
+    feats = rng.standard_normal((n, 12)).astype(np.float32) * 2
+    cls = np.where(feats[:, 8] > 0.5, 4, np.where(feats[:, 7] < -1, 0, 1))
+    mask = np.ones((n, NC), np.uint8)
+    t = np.full((n, NC), 1e-3, np.float32)
+    t[np.arange(n), cls] = 1.0
+    t /= t.sum(1, keepdims=True)
+    l0 = gpu_handle.mlp_train(feats, t, mask, epochs=1, lr=3e-3, seed=7)
+    l1 = gpu_handle.mlp_train(feats, t, mask, epochs=1500, lr=3e-3, seed=7)
+    assert l1 < 0.5 * l0
+    acc = np.mean(gpu_handle.mlp_predict(feats).argmax(1) == cls)
+    assert acc >= 0.95, acc
+
+
+def test_model_file_round_trip_and_rejection(gpu_handle, tmp_path):
+    params, mu, sd, feats, t, mask = _case(seed=2)
+    gpu_handle.mlp_set(params, mu, sd)
+    path = str(tmp_path / "m.txt")
+    gpu_handle.save_model(path)
+    before = gpu_handle.mlp_predict(feats)
+    assert gpu_handle.load_model(path) == C.OK
+    assert np.array_equal(gpu_handle.mlp_predict(feats), before)
+    txt = open(path).read()
+    bad = str(tmp_path / "bad.txt")
+    open(bad, "w").write(txt.replace("arch gfx950", "arch gfx942"))
+    assert gpu_handle.load_model(bad) == C.ERR_MODEL
+    open(bad, "w").write(txt[: len(txt) // 2])
+    assert gpu_handle.load_model(bad) == C.ERR_MODEL
+    assert gpu_handle.load_model(str(tmp_path / "missing.txt")) == C.ERR_MODEL
+    # without a model the default selection falls back to the fixed rule

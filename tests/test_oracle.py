@@ -307,3 +307,65 @@ def test_bf16_encode_from_double_has_no_double_rounding():
 def test_fsum_is_compensated():
     v = np.array([1e16, 1.0, -1e16, 1.0] * 1000)
     assert oracle.fsum(v) == math.fsum(v) == 2000.0
+
+
+# -------------------------------------------------------- selector network
+def _mlp_case(n=9, C=7, seed=0):
+    from oracle import mlp
+
+    rng = np.random.default_rng(seed)
+    params = rng.standard_normal(mlp.num_params(C)) * 0.3
+    feats = rng.standard_normal((n, 12)) * 2 + 1
+    mu, sd = feats.mean(0), feats.std(0) + 0.5
+    mask = rng.random((n, C)) < 0.7
+    mask[:, 0] = True
+    t = rng.random((n, C)) * mask
+    t /= t.sum(1, keepdims=True)
+    return params, mu, sd, feats, t, mask
+
+
+def test_mlp_forward_closed_form():
+    from oracle import mlp
+
+    C = 3
+    P = {"W1": np.zeros((64, 12)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
+         "W3": np.zeros((C, 64)), "b3": np.array([1.0, -2.0, 0.5])}
+    P["W1"][0, 3] = 2.0   # h1_0 = ReLU(2 z_3)
+    P["W2"][5, 0] = -1.0  # h2_5 = ReLU(-h1_0)
+    P["W3"][1, 5] = 3.0
+    P["W3"][2, 0] = 7.0   # h2_0 = 0 always
+    f = np.zeros((2, 12)); f[0, 3] = 1.5; f[1, 3] = -1.5
+    logits, _ = mlp.forward(mlp.pack(P, C), np.zeros(12), np.ones(12), f, C)
+    assert np.allclose(logits[0], [1.0, -2.0, 0.5])          # h1_0 = 3 -> h2_5 = 0
+    assert np.allclose(logits[1], [1.0, -2.0, 0.5])          # h1_0 = 0
+    # uniform logits over the legal set, one-hot target -> loss = log(#legal)
+    P["b3"][:] = 0.0
+    mask = np.array([[True, True, False], [True, True, True]])
+    tgt = np.array([[1.0, 0, 0], [0, 0, 1.0]])
+    loss, _ = mlp.loss_and_grad(mlp.pack(P, C), np.zeros(12), np.ones(12), np.zeros((2, 12)), tgt, mask, C)
+    assert abs(loss - (math.log(2) + math.log(3)) / 2) < 1e-15
+
+
+def test_mlp_gradient_finite_differences():
+    from oracle import mlp
+
+    params, mu, sd, feats, t, mask = _mlp_case()
+    loss, g = mlp.loss_and_grad(params, mu, sd, feats, t, mask, 7)
+    rng = np.random.default_rng(1)
+    idx = rng.choice(params.size, 60, replace=False)
+    h = 1e-6
+    for i in idx:
+        pp = params.copy(); pp[i] += h
+        pm = params.copy(); pm[i] -= h
+        fd = (mlp.loss_and_grad(pp, mu, sd, feats, t, mask, 7)[0] - mlp.loss_and_grad(pm, mu, sd, feats, t, mask, 7)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])) + 1e-9
+
+
+def test_mlp_adam_first_step_is_signed_lr():
+    from oracle import mlp
+
+    # with bias correction the first Adam step moves each weight by ~lr * sign(g)
+    p = np.array([1.0, -2.0, 3.0])
+    g = np.array([0.5, -4.0, 1e-3])
+    new, m, v = mlp.adam_step(p, g, np.zeros(3), np.zeros(3), 1, 0.01)
+    assert np.allclose(new, p - 0.01 * np.sign(g) * np.abs(g) / (np.abs(g) + 1e-8), rtol=1e-12)
