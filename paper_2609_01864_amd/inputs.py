@@ -98,11 +98,12 @@ def to_fp8_rows(x64: np.ndarray):
     values clamped to the finite range."""
     import torch
 
-    amax = np.abs(x64).max(axis=1)
-    scale = np.where(amax > 0, amax / 448.0, 1.0).astype(np.float32)
-    q = np.clip(x64 / scale.astype(np.float64)[:, None], -448.0, 448.0).astype(np.float32)
-    codes = torch.from_numpy(q).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
-    return codes, scale
+    xt = torch.from_numpy(np.ascontiguousarray(x64, dtype=np.float64))
+    amax = xt.abs().amax(dim=1)
+    scale = torch.where(amax > 0, amax / 448.0, torch.ones_like(amax)).to(torch.float32)
+    q = (xt / scale.to(torch.float64)[:, None]).clamp_(-448.0, 448.0).to(torch.float32)
+    codes = q.to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    return codes, scale.numpy()
 
 
 def store(x64: np.ndarray, dtype: str):

@@ -1,0 +1,77 @@
+"""Split-row exchange protocol: bounded waits end in CREDIT_ERR_TIMEOUT when a
+member never publishes (forced from the host: a test-only flag plus a tiny
+spin limit, so every kernel still exits normally), epoch wrap-around, a
+workspace poisoned with stale epochs, and run-to-run determinism."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2609_01864_amd import credit as C
+
+from _cases import Case, check_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _ln_case():
+    case = Case("layernorm_fwd", "f32", 40, 30000, seed=21)
+    return case, case.reference()
+
+
+def test_missing_partial_times_out_and_is_reported(gpu_handle):
+    case, ref = _ln_case()
+    h = gpu_handle
+    assert h.check_errors() == C.OK
+    h.set_option(C.OPT_SPIN_LIMIT, 64)
+    h.set_option(C.OPT_TEST_DROP_PUBLISH, 1)
+    try:
+        print("[protocol] forced timeout", flush=True)
+        x = torch.from_numpy(case.raw["x"][0]).cuda()
+        g = torch.from_numpy(case.gamma).cuda()
+        b = torch.from_numpy(case.beta).cuda()
+        C.layernorm_fwd(x, g, b, 1e-5, p=C.plan("split", 4), h=h)
+        torch.cuda.synchronize()
+        assert h.check_errors() == C.ERR_TIMEOUT
+        assert h.check_errors() == C.OK  # the flag is cleared once reported
+    finally:
+        h.set_option(C.OPT_TEST_DROP_PUBLISH, 0)
+        h.set_option(C.OPT_SPIN_LIMIT, 1 << 22)
+    # the library is usable again afterwards
+    check_case(case, case.run(h, C.plan("split", 4), ref=ref), ref)
+
+
+def test_epoch_wraparound(gpu_handle):
+    case, ref = _ln_case()
+    C.set_epoch(0xFFFFFFFE)
+    for _ in range(4):  # epochs 0xFFFFFFFE, 0xFFFFFFFF, (0 skipped) 1, 2
+        print("[protocol] epoch wrap", flush=True)
+        check_case(case, case.run(gpu_handle, C.plan("split", 8), ref=ref), ref)
+
+
+def test_poisoned_workspace(gpu_handle):
+    # stale slot words from earlier launches (random epochs and values) must not
+    # be taken for the current launch's partials
+    case, ref = _ln_case()
+    h = gpu_handle
+    p = C.plan("split", 8)
+    n = h.workspace_size(C.LAYERNORM, C.FWD, C.F32, case.M, case.N, p)
+    ws = h.workspace(n, h._stream())
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    ws.copy_(torch.randint(0, 256, ws.shape, generator=gen, dtype=torch.uint8, device="cuda"))
+    C.set_epoch(0x7FFFFFF0)
+    print("[protocol] poisoned workspace", flush=True)
+    check_case(case, case.run(h, p, ref=ref), ref)
+
+
+def test_determinism_across_runs_and_plans_agree(gpu_handle):
+    case = Case("softmax_fwd", "bf16", 16, 65536, seed=8)
+    outs = {}
+    for v, k in [("split", 2), ("split", 4), ("split", 8), ("split", 16)]:
+        runs = [case.run(gpu_handle, C.plan(v, k))["y"] for _ in range(3)]
+        assert all(np.array_equal(runs[0], r) for r in runs[1:]), (v, k)
+        outs[k] = runs[0]
+    # different split factors combine in different orders: equal to 1 BF16 ulp
+    ref = case.reference()
+    for k, y in outs.items():
+        check_case(case, {"y": y}, ref)
