@@ -52,9 +52,10 @@ def algorithmic_bytes(op: str, M: int, N: int) -> int:
     return M * N * 4 * 2 + vec * N * 4 + vec * M * 4
 
 
-def cpu_baseline(rows: int = 64):
-    """The FP64 oracle (as it stands) on the first `rows` rows of every
-    (op, N) of the workload, all host threads."""
+def cpu_baseline(target_s: float = 10.0):
+    """The FP64 oracle (as it stands) on the whole workload -- every (op, N),
+    all 1024 rows -- repeated until about `target_s` seconds of oracle time,
+    on all host threads.  Input generation is outside the timed calls."""
     import numpy as np
 
     import oracle
@@ -62,22 +63,67 @@ def cpu_baseline(rows: int = 64):
 
     total_bytes = 0
     total_s = 0.0
-    for N in WIDTHS:
-        x = I.norm_rows(M_ROWS, N, seed=1, tensor=0, rows=np.arange(rows)).astype(np.float32).astype(np.float64)
-        g, b = I.norm_params(N, seed=1)
-        g = g.astype(np.float64)
-        b = b.astype(np.float64)
-        t0 = time.perf_counter()
-        oracle.layernorm_fwd(x, g, b, EPS)
-        t1 = time.perf_counter()
-        oracle.rmsnorm_fwd(x, g, EPS)
-        t2 = time.perf_counter()
-        total_s += t2 - t0
-        total_bytes += algorithmic_bytes("layernorm_fwd", rows, N) + algorithmic_bytes("rmsnorm_fwd", rows, N)
+    passes = 0
+    while total_s < target_s and passes < 60:
+        for N in WIDTHS:
+            x = I.norm_rows(M_ROWS, N, seed=1, tensor=0).astype(np.float32).astype(np.float64)
+            g, b = I.norm_params(N, seed=1)
+            g = g.astype(np.float64)
+            b = b.astype(np.float64)
+            t0 = time.perf_counter()
+            oracle.layernorm_fwd(x, g, b, EPS)
+            oracle.rmsnorm_fwd(x, g, EPS)
+            total_s += time.perf_counter() - t0
+            total_bytes += algorithmic_bytes("layernorm_fwd", M_ROWS, N) + algorithmic_bytes("rmsnorm_fwd", M_ROWS, N)
+            del x
+        passes += 1
     return {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"first {rows} of {M_ROWS} rows of each (op, N) of the workload, FP64 C oracle, "
-                      f"{total_s:.1f} s"}
+            "sample": f"the whole workload (LayerNorm + RMSNorm forward, all 1024 rows of each N) x {passes} "
+                      f"passes, FP64 C oracle with OpenMP, {total_s:.1f} s of oracle time"}
+
+
+def kernel_symbol(C, h, op_num, dt_num, M, N, p):
+    """Demangled name prefix and grid (work-items) of the launch of plan p."""
+    g = h.geometry(op_num, C.FWD if op_num < 3 else C.BWD, dt_num, M, N, p)
+    kop = op_num
+    if p.variant == C.TWO_PASS:
+        return f"void credit::k_twopass<{kop}, {dt_num}, {g['block']}, 4>", g["grid"] * g["block"]
+    return f"void credit::k_resident<{kop}, {dt_num}, {g['vpt']}>", g["grid"] * g["block"]
+
+
+def forms(C, h):
+    """Cold-cache times (flush, median of 15) of the precision workload
+    (softmax and LayerNorm forward, M = 4096, N in {65536, 262144}, BF16 and
+    FP8 I/O vs the FP32 two-pass kernel) and of the backward workload
+    (softmax and LayerNorm backward, M = 2048, N = 131072, FP32 and BF16)
+    with the selector's plans."""
+    out = {"precision": [], "backward": []}
+    e = {C.F32: 4, C.BF16: 2, C.FP8: 1}
+    for op, name in ((C.SOFTMAX, "softmax_fwd"), (C.LAYERNORM, "layernorm_fwd")):
+        for N in (65536, 262144):
+            M = 4096
+            t2 = h.time_plan(op, C.FWD, C.F32, M, N, C.plan("two_pass"), 15, True)
+            row = {"op": name, "M": M, "N": N, "fp32_two_pass_us": round(t2, 1)}
+            for dt, dn in ((C.F32, "f32"), (C.BF16, "bf16"), (C.FP8, "fp8")):
+                p, _ = h.select(op, C.FWD, dt, M, N)
+                t = h.time_plan(op, C.FWD, dt, M, N, p, 15, True)
+                row[dn] = {"plan": list(p.as_tuple()), "us": round(t, 1),
+                           "gbps": round(M * N * e[dt] * 2 / (t * 1e3), 1),
+                           "speedup_vs_fp32_two_pass": round(t2 / t, 3)}
+            out["precision"].append(row)
+            log(f"precision {name} N={N}: {row}")
+    for op, name in ((C.SOFTMAX, "softmax_bwd"), (C.LAYERNORM, "layernorm_bwd")):
+        M, N = 2048, 131072
+        for dt, dn in ((C.F32, "f32"), (C.BF16, "bf16")):
+            p, _ = h.select(op, C.BWD, dt, M, N)
+            t = h.time_plan(op, C.BWD, dt, M, N, p, 15, True)
+            t2 = h.time_plan(op, C.BWD, dt, M, N, C.plan("two_pass"), 15, True)
+            out["backward"].append({"op": name, "dtype": dn, "M": M, "N": N, "plan": list(p.as_tuple()),
+                                    "us": round(t, 1), "gbps": round(M * N * e[dt] * 3 / (t * 1e3), 1),
+                                    "two_pass_us": round(t2, 1)})
+            log(f"backward {name} {dn}: {out['backward'][-1]}")
+    return out
 
 
 def traffic_for(kernel_key: str):
@@ -104,6 +150,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-regret", action="store_true", help="skip exhaustive timing of all plans")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision / backward workloads")
     ap.add_argument("--selector", default="auto", choices=["auto", "learned", "analytic", "fixed", "exhaustive"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -208,9 +255,11 @@ def main():
                               "gbps": round(gb, 1), "frac": round(gb / PEAK_GBPS, 4)})
     dom = max(per_shape, key=lambda r: r["us"])
     dom_key = f"{dom['op']}:N={dom['N']}:plan={dom['plan'][0]},{dom['plan'][1]}"
+    sym, grid_threads = kernel_symbol(C, h, opnum[dom["op"]], C.F32, M_ROWS, dom["N"], picks[(dom["op"], dom["N"])][0])
     roofline = {"bound": "hbm", "achieved": dom["gbps"], "peak": PEAK_GBPS, "unit": "GB/s",
                 "frac": round(dom["gbps"] / PEAK_GBPS, 4), "traffic": traffic_for(dom_key),
-                "kernel": dom_key, "avg_launch_us": dom["us"],
+                "kernel": dom_key, "kernel_symbol": sym, "grid_threads": grid_threads,
+                "avg_launch_us": dom["us"],
                 "algorithmic_bytes_per_launch": algorithmic_bytes(dom["op"], M_ROWS, dom["N"])}
 
     # --------------------------------------------- regret vs exhaustive
@@ -237,6 +286,7 @@ def main():
             log(f"{r['op']} N={r['N']}: times {times} pick {r['plan']} regret {r['regret']:+.3f}")
     copy_gbps = h.copy_bandwidth(1 << 30, 15)
     log(f"copy kernel: {copy_gbps:.1f} GB/s")
+    extra = None if args.no_forms else forms(C, h)
 
     cpu = None
     if not args.no_cpu:
@@ -266,7 +316,9 @@ def main():
         "regret_geomean": round(math.exp(sum(math.log(x) for x in regrets) / len(regrets)) - 1.0, 4)
         if regrets else None,
         "copy_kernel_gbps": round(copy_gbps, 1),
+        "copy_kernel_bytes": 1 << 30,
         "per_shape": per_shape,
+        "forms": extra,
         "source_hash": source_hash(),
     }
     print(json.dumps(out), flush=True)

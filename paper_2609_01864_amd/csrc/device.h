@@ -250,6 +250,31 @@ struct MergeChan {
     }
 };
 
+// ------------------------------------------------- workgroup -> (member, group)
+// Hardware workgroup ids are dealt round-robin to the 8 XCDs (id % 8), each
+// with its own L2.  With F_XCD, an XCD hosts only some member indices c, i.e.
+// the same column slices for every row group it runs, so the gamma / beta
+// columns it reads (N bytes per XCD) stay in its L2 across rows.  Row groups
+// are spread over XCDs instead; the exchange does not care, because its
+// agent-scope slot accesses are served at the memory side either way.
+__device__ __forceinline__ void member_of(const RowArgs &a, int bid, int &c, int &grp) {
+    if (a.flags & F_XCD) {
+        const int x = bid & 7, idx = bid >> 3;
+        if (a.k >= 8) {
+            const int per = a.k >> 3;
+            c = x + 8 * (idx % per);
+            grp = idx / per;
+        } else {
+            const int per = 8 / a.k;
+            c = x % a.k;
+            grp = idx * per + x / a.k;
+        }
+    } else {
+        c = bid % a.k;
+        grp = bid / a.k;
+    }
+}
+
 // --------------------------------------------------- split-row exchange
 // Slot word: high 32 bits = launch epoch, low 32 bits = FP32 partial.  Each
 // word is written with one agent-scope atomic store and polled with

@@ -229,7 +229,7 @@ credit_status_t resolve(credit_handle_t h, int k_op, int dt, int64_t M, int64_t 
     if (h && h->max_groups > 0) gmax = std::min<int64_t>(gmax, h->max_groups);
     if (gmax < 1) return CREDIT_ERR_UNSUPPORTED;  // k members cannot be co-resident
     int64_t groups = std::min<int64_t>(std::max<int64_t>(M, 1), gmax);
-    if (k > 1 && groups >= 8) {
+    if (groups >= 8) {  // XCD-aware member mapping needs grid % 8 == 0
         groups = groups / 8 * 8;
         L.xcd = true;
     }
@@ -341,8 +341,8 @@ credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void 
         if (L.k > 1) {
             a.slots = (unsigned long long *)(w + L.off_slots);
             a.epoch = next_epoch();
-            if (L.xcd) flags |= F_XCD;
         }
+        if (L.xcd) flags |= F_XCD;
         if (ncp) a.colpart = (float *)(w + L.off_colpart);
         a.flags = flags;
         void *args[] = {&a};

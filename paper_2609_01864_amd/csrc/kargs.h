@@ -17,7 +17,7 @@ enum KFlags {
     F_ALIGN0 = 1,              // rows of in0 start 16-byte aligned
     F_ALIGN1 = 2,              // rows of in1 start 16-byte aligned
     F_ALIGNO = 4,              // rows of out start 16-byte aligned
-    F_XCD = 8,                 // group members share an XCD (grid % 8 == 0)
+    F_XCD = 8,                 // XCD-aware member mapping (grid % 8 == 0)
     F_RECOMPUTE = 16,          // norm backward: recompute mean/rstd from x
     F_TEST_DROP_PUBLISH = 32,  // test only: member 1 never publishes
     F_ALIGNP = 64,             // gamma / beta 16-byte aligned

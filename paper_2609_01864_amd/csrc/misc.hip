@@ -39,9 +39,8 @@ __global__ __launch_bounds__(kBlock) void k_control(RowArgs a, int stages) {
     __shared__ float red[2 * 4 * 2];
     __shared__ float xb[kMaxK * kMaxQ];
     int parity = 0;
-    const int G = gridDim.x, bid = blockIdx.x;
-    const int lb = (a.flags & F_XCD) ? (bid & 7) * (G >> 3) + (bid >> 3) : bid;
-    const int c = lb % a.k, grp = lb / a.k;
+    int c, grp;
+    member_of(a, blockIdx.x, c, grp);
     for (int64_t row = grp; row < a.M; row += a.groups) {
         for (int s = 0; s < stages; ++s) {
             float v[2] = {(float)threadIdx.x, 0.f};

@@ -693,12 +693,8 @@ void k_resident(RowArgs a) {
     constexpr int EPV = Io<DT>::EPV;
     __shared__ float red[2 * 4 * 3];
     __shared__ float xb[kMaxK * kMaxQ];
-    const int G = gridDim.x, bid = blockIdx.x;
-    // XCD-aware numbering: hardware workgroup ids are dealt round-robin to the
-    // 8 XCDs, so logical ids that are consecutive within one XCD (and thus the
-    // k members of a row group) share that XCD's L2.
-    const int lb = (a.flags & F_XCD) ? (bid & 7) * (G >> 3) + (bid >> 3) : bid;
-    const int c = lb % a.k, grp = lb / a.k;
+    int c, grp;
+    member_of(a, blockIdx.x, c, grp);
     Slice sl;
     sl.c0 = (int64_t)c * a.chunk;
     const int64_t rem = a.N - sl.c0;

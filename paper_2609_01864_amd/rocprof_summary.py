@@ -1,0 +1,171 @@
+"""Summaries of rocprofv3 CSV output for the library's kernels.
+
+    python -m paper_2609_01864_amd.rocprof_summary trace  --trace DIR --bench BENCH.json --out profiles/X.md
+    python -m paper_2609_01864_amd.rocprof_summary traffic --fetch DIR --write DIR --bench BENCH.json \
+        --json profiles/traffic.json --out profiles/Y.md
+
+trace    per-kernel dispatch counts and average durations from a
+         `rocprofv3 --kernel-trace --stats --output-format csv` run of the
+         benchmark, with the benchmark's own HIP-event average for its dominant
+         kernel beside the trace's average for the same kernel and grid.
+traffic  HBM bytes per launch of the dominant kernel from two `--pmc` runs
+         (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each divided by the
+         counter-per-byte factor the same counter reads on the plain copy
+         kernel (k_copy moves a known number of bytes each way).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+import statistics
+import sys
+
+
+def _find(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[-1]
+
+
+def _rows(path: str):
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _grid(r) -> int:
+    for k in ("Grid_Size", "Grid_Size_X", "grid_size", "Grid_X"):
+        if k in r and r[k] not in ("", None):
+            return int(float(r[k]))
+    return -1
+
+
+def _dur_us(r) -> float:
+    s = r.get("Start_Timestamp") or r.get("start")
+    e = r.get("End_Timestamp") or r.get("end")
+    return (int(e) - int(s)) / 1e3
+
+
+def kernel_name(bench: dict) -> tuple:
+    """(demangled name prefix, grid in work-items) of the dominant launch."""
+    d = bench["roofline"]
+    return d["kernel_symbol"], int(d["grid_threads"])
+
+
+def trace(args):
+    bench = json.loads(open(args.bench).read().strip().splitlines()[-1])
+    rows = _rows(_find(args.trace, "kernel_trace.csv"))
+    by = {}
+    for r in rows:
+        name = r.get("Kernel_Name") or r.get("kernel_name")
+        by.setdefault(name, []).append(r)
+    sym, grid = kernel_name(bench)
+    avg = bench["roofline"]["avg_launch_us"]
+    same = [_dur_us(r) for r in rows if (r.get("Kernel_Name") or "").startswith(sym) and _grid(r) == grid]
+    # other shapes of the workload can launch the same kernel instance with the
+    # same grid; the dominant launch's dispatches are those within a factor
+    # 1.5 of the benchmark's own average for it
+    dom = [d for d in same if avg / 1.5 <= d <= avg * 1.5]
+    lines = [f"# rocprofv3 kernel trace: {args.title}", "",
+             f"Command: `{args.command}`", "",
+             f"Dominant kernel (benchmark roofline): `{sym}` grid {grid} work-items", "",
+             f"* benchmark HIP-event average over the timed steps: {bench['roofline']['avg_launch_us']:.2f} us",
+             f"* rocprofv3 average of the same kernel and grid: {statistics.mean(dom):.2f} us over {len(dom)} "
+             f"dispatches (median {statistics.median(dom):.2f} us); {len(same) - len(dom)} other dispatches of "
+             f"this kernel and grid (other shapes, outside 1/1.5..1.5x of the benchmark average) excluded"
+             if dom else "* (not found in trace)",
+             "", "| kernel | dispatches | total ms | avg us |", "|---|---:|---:|---:|"]
+    tot = []
+    for name, rs in by.items():
+        ds = [_dur_us(r) for r in rs]
+        tot.append((sum(ds), name, len(ds), statistics.mean(ds)))
+    for s, name, n, avg in sorted(tot, reverse=True)[:25]:
+        short = name if len(name) < 90 else name[:87] + "..."
+        lines.append(f"| `{short}` | {n} | {s / 1e3:.2f} | {avg:.2f} |")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines[:10]))
+
+
+def _counter_rows(d: str, counter: str):
+    rows = _rows(_find(d, "counter_collection.csv"))
+    out = []
+    for r in rows:
+        if (r.get("Counter_Name") or r.get("counter_name")) != counter:
+            continue
+        out.append((r.get("Kernel_Name") or "", _grid(r), float(r.get("Counter_Value") or r.get("value"))))
+    return out
+
+
+def traffic(args):
+    bench = json.loads(open(args.bench).read().strip().splitlines()[-1])
+    sym, grid = kernel_name(bench)
+    copy_bytes = float(bench["copy_kernel_bytes"])  # bytes read (= bytes written) per copy launch
+    res = {}
+    for counter, d in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
+        rows = _counter_rows(d, counter)
+        # counters are summed over the dispatch's instances by rocprofv3
+        cp = [v for n, g, v in rows if n.startswith("credit::k_copy")]
+        same = [v for n, g, v in rows if n.startswith(sym) and g == grid]
+        if not cp or not same:
+            raise SystemExit(f"{counter}: copy dispatches {len(cp)}, dominant dispatches {len(same)}")
+        factor = statistics.median(cp) * 1024.0 / copy_bytes  # counter bytes per real byte
+        # other shapes may launch the same kernel and grid: keep the dispatches
+        # within a factor 2 of the dominant launch's algorithmic bytes for this
+        # direction (read: inputs, write: outputs; half each for these ops)
+        expect = 0.5 * bench["roofline"]["algorithmic_bytes_per_launch"] * factor / 1024.0
+        dom = [v for v in same if expect / 2 <= v <= expect * 2]
+        if not dom:
+            raise SystemExit(f"{counter}: no dispatch near {expect:.0f} KiB among {sorted(same)[:8]}")
+        res[counter] = {"kib_per_dispatch": statistics.median(dom), "copy_kib_per_dispatch": statistics.median(cp),
+                        "dispatches": len(dom), "excluded": len(same) - len(dom),
+                        "factor": factor, "bytes_per_launch": statistics.median(dom) * 1024.0 / factor}
+    total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+    key = bench["roofline"]["kernel"]
+    entry = {"bytes_per_launch": round(total), "fetch_bytes": round(res["FETCH_SIZE"]["bytes_per_launch"]),
+             "write_bytes": round(res["WRITE_SIZE"]["bytes_per_launch"]),
+             "algorithmic_bytes": bench["roofline"]["algorithmic_bytes_per_launch"],
+             "source_hash": bench["source_hash"], "kernel_symbol": sym, "grid_threads": grid,
+             "copy_factor_fetch": res["FETCH_SIZE"]["factor"], "copy_factor_write": res["WRITE_SIZE"]["factor"]}
+    data = {"kernels": {}}
+    if os.path.exists(args.json):
+        data = json.load(open(args.json))
+    data.setdefault("kernels", {})[key] = entry
+    json.dump(data, open(args.json, "w"), indent=1)
+    lines = [f"# HBM traffic of the dominant kernel: {args.title}", "",
+             f"Commands: `{args.command}` with `--pmc FETCH_SIZE` and, separately, `--pmc WRITE_SIZE`", "",
+             f"Kernel `{sym}`, grid {grid} work-items ({key})", "",
+             "| counter | kernel KiB/dispatch | copy-kernel KiB/dispatch | counter bytes per byte moved | HBM bytes/launch |",
+             "|---|---:|---:|---:|---:|"]
+    for c, r in res.items():
+        lines.append(f"| {c} | {r['kib_per_dispatch']:.0f} | {r['copy_kib_per_dispatch']:.0f} | {r['factor']:.4f} | "
+                     f"{r['bytes_per_launch']:.4e} |")
+    alg = entry["algorithmic_bytes"]
+    lines += ["", "Dispatches used (kept / other shapes sharing kernel and grid, outside 0.5..2x of the expected "
+                  "bytes): " + ", ".join(f"{c} {r['dispatches']}/{r['excluded']}" for c, r in res.items()),
+              "", f"Total {total:.4e} bytes per launch against {alg:.4e} algorithmic bytes "
+                  f"(ratio {total / alg:.3f}).", "",
+              f"The copy kernel moves {copy_bytes:.0f} bytes each way per launch."]
+    open(args.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["trace", "traffic"])
+    ap.add_argument("--trace")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--bench", required=True)
+    ap.add_argument("--json", default="profiles/traffic.json")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--title", default="")
+    ap.add_argument("--command", default="python3 bench.py")
+    args = ap.parse_args(argv)
+    trace(args) if args.mode == "trace" else traffic(args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
