@@ -72,7 +72,7 @@ template <> __device__ __forceinline__ u32x4 encode<DT_BF16>(const float *f, flo
     for (int i = 0; i < 4; ++i) v[i] = bf16_bits(f[2 * i]) | (bf16_bits(f[2 * i + 1]) << 16);
     return v;
 }
-__device__ __forceinline__ float sat448(float x) { return fminf(fmaxf(x, -kFp8Max), kFp8Max); }
+__device__ __forceinline__ float sat448(float x) { return __builtin_amdgcn_fmed3f(x, -kFp8Max, kFp8Max); }
 template <> __device__ __forceinline__ u32x4 encode<DT_FP8>(const float *f, float inv_scale) {
     u32x4 v;
 #pragma unroll

@@ -297,82 +297,96 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             }
         } else if constexpr (OP == OP_LN_FWD || OP == OP_RMS_FWD) {
             constexpr bool LN = OP == OP_LN_FWD;
+            // Statistics on the decoded codes q (x = xs * q for FP8, q = x
+            // otherwise), so the per-row scale is applied once per row, not per
+            // element: mean_x = xs mean_q, var_x = xs^2 var_q, y uses xs * rstd.
             const float xs = FP8 ? a.s0[row] : 1.f;
-            float mean = 0.f, rstd;
+            float mean_q = 0.f, amul;
             if constexpr (LN) {
-                float sum = 0.f;
+                // one pass of moments about a per-thread shift (its first held
+                // value), turned into (count, mean, M2) and Chan-merged
+                float K = 0.f;
+                {
+                    float q[EPV];
+                    decode<DT>(d0[0], q, 1.f);
+                    float qt[EPV];
+                    decode<DT>(t0, qt, 1.f);
+                    K = (FULLS || ok_of(0)) ? q[0] : (tail ? qt[0] : 0.f);
+                }
+                float s1 = 0.f, s2 = 0.f;
                 fresh();
 #pragma unroll
                 for (int j = 0; j < VPT; ++j) {
-                    float x[EPV];
-                    decode<DT>(d0[j], x, xs);
-#pragma unroll
-                    for (int i = 0; i < EPV; ++i) sum += x[i];  // masked slots hold zeros
-                }
-                if (tail) {
-                    float x[EPV];
-                    decode<DT>(t0, x, xs);
-#pragma unroll
-                    for (int i = 0; i < EPV; ++i) sum += x[i];
-                }
-                const float tm = held > 0.f ? sum / held : 0.f;
-                float m2 = 0.f;
-                fresh();
-#pragma unroll
-                for (int j = 0; j < VPT; ++j) {
-                    float x[EPV];
-                    decode<DT>(d0[j], x, xs);
+                    float q[EPV];
+                    decode<DT>(d0[j], q, 1.f);
                     const bool ok = ok_of(j);
 #pragma unroll
                     for (int i = 0; i < EPV; ++i) {
-                        float d = ok ? x[i] - tm : 0.f;
-                        m2 = fmaf(d, d, m2);
+                        float d = ok ? q[i] - K : 0.f;
+                        s1 += d;
+                        s2 = fmaf(d, d, s2);
                     }
                 }
                 if (tail) {
-                    float x[EPV];
-                    decode<DT>(t0, x, xs);
+                    float q[EPV];
+                    decode<DT>(t0, q, 1.f);
                     for (int i = 0; i < tn; ++i) {
-                        float d = x[i] - tm;
-                        m2 = fmaf(d, d, m2);
+                        float d = q[i] - K;
+                        s1 += d;
+                        s2 = fmaf(d, d, s2);
                     }
                 }
-                float st[3] = {held, tm, m2};
+                float st[3] = {held, 0.f, 0.f};
+                if (held > 0.f) {
+                    const float m = s1 / held;
+                    st[1] = K + m;
+                    st[2] = fmaxf(s2 - s1 * m, 0.f);
+                }
                 row_reduce_chan(st, a, row, 0, c, red, xb, parity);
-                mean = st[1];
-                rstd = rsqrtf(st[2] * invN + a.eps);
+                mean_q = st[1];
+                const float rstd = rsqrtf(xs * xs * (st[2] * invN) + a.eps);
+                amul = xs * rstd;
+                if (writer) {
+                    if (a.mean_out) a.mean_out[row] = xs * mean_q;
+                    if (a.rstd_out) a.rstd_out[row] = rstd;
+                }
             } else {
                 float st[1] = {0.f};
                 fresh();
 #pragma unroll
                 for (int j = 0; j < VPT; ++j) {
-                    float x[EPV];
-                    decode<DT>(d0[j], x, xs);
+                    float q[EPV];
+                    decode<DT>(d0[j], q, 1.f);
 #pragma unroll
-                    for (int i = 0; i < EPV; ++i) st[0] = fmaf(x[i], x[i], st[0]);
+                    for (int i = 0; i < EPV; ++i) st[0] = fmaf(q[i], q[i], st[0]);
                 }
                 if (tail) {
-                    float x[EPV];
-                    decode<DT>(t0, x, xs);
+                    float q[EPV];
+                    decode<DT>(t0, q, 1.f);
 #pragma unroll
-                    for (int i = 0; i < EPV; ++i) st[0] = fmaf(x[i], x[i], st[0]);
+                    for (int i = 0; i < EPV; ++i) st[0] = fmaf(q[i], q[i], st[0]);
                 }
                 row_reduce<1>(st, MergeSum(), a, row, 0, c, red, xb, parity);
-                rstd = rsqrtf(st[0] * invN + a.eps);
+                const float rstd = rsqrtf(xs * xs * (st[0] * invN) + a.eps);
+                amul = xs * rstd;
+                if (writer) {
+                    if (a.mean_out) a.mean_out[row] = 0.f;
+                    if (a.rstd_out) a.rstd_out[row] = rstd;
+                }
             }
-            if (writer) {
-                if (a.mean_out) a.mean_out[row] = mean;
-                if (a.rstd_out) a.rstd_out[row] = rstd;
-            }
-            auto h = [&](const float *x, const float *g, const float *bb, float *y) {
+            auto h = [&](const float *q, const float *g, const float *bb, float *y) {
 #pragma unroll
                 for (int i = 0; i < EPV; ++i) {
                     if constexpr (LN)
-                        y[i] = fmaf((x[i] - mean) * rstd, g[i], bb[i]);
+                        y[i] = fmaf((q[i] - mean_q) * amul, g[i], bb[i]);
                     else
-                        y[i] = x[i] * rstd * g[i];
+                        y[i] = q[i] * amul * g[i];
                 }
             };
+            // FP8 output with a small slice keeps y in registers between the
+            // amax stage and the quantize pass: gamma / beta are read once
+            constexpr bool YC = FP8 && VPT * EPV <= 32;
+            float yc[YC ? VPT * EPV : 1], yct[YC ? EPV : 1];
             // output pass over the slots in batches of GB: the parameter loads of
             // a batch are issued together; store == false only measures amax
             auto out_pass = [&](bool store, float oinv, float &amax) {
@@ -391,28 +405,35 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
 #pragma unroll
                     for (int u = 0; u < GB; ++u) {
                         const int j = jb + u;
-                        float x[EPV], y[EPV];
-                        decode<DT>(d0[j], x, xs);
-                        h(x, g[u], LN ? bb[u] : g[u], y);
+                        float q[EPV], y[EPV];
+                        decode<DT>(d0[j], q, 1.f);
+                        h(q, g[u], LN ? bb[u] : g[u], y);
                         if (store) {
                             ST(j, encode<DT>(y, oinv));
                         } else {
                             const bool ok = ok_of(j);
 #pragma unroll
-                            for (int i = 0; i < EPV; ++i) amax = fmaxf(amax, ok ? fabsf(y[i]) : 0.f);
+                            for (int i = 0; i < EPV; ++i) {
+                                amax = fmaxf(amax, ok ? fabsf(y[i]) : 0.f);
+                                if constexpr (YC) yc[j * EPV + i] = y[i];
+                            }
                         }
                     }
                 }
                 if (tail) {
-                    float x[EPV], y[EPV], g[EPV], bb[EPV];
-                    decode<DT>(t0, x, xs);
+                    float q[EPV], y[EPV], g[EPV], bb[EPV];
+                    decode<DT>(t0, q, 1.f);
                     load_params_tail<DT>(a.gamma, tcol, tn, g);
                     if constexpr (LN) load_params_tail<DT>(a.beta, tcol, tn, bb);
-                    h(x, g, bb, y);
+                    h(q, g, bb, y);
                     if (store) {
                         store_vec<DT>(orow, tcol, tn, false, encode<DT>(y, oinv));
                     } else {
                         for (int i = 0; i < tn; ++i) amax = fmaxf(amax, fabsf(y[i]));
+                        if constexpr (YC) {
+#pragma unroll
+                            for (int i = 0; i < EPV; ++i) yct[i] = y[i];
+                        }
                     }
                 }
             };
@@ -424,8 +445,14 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 oinv = am[0] > 0.f ? kFp8Max / am[0] : 1.f;
                 if (writer) a.so[row] = am[0] > 0.f ? am[0] / kFp8Max : 1.f;
             }
-            float unused = 0.f;
-            out_pass(true, oinv, unused);
+            if constexpr (YC) {
+#pragma unroll
+                for (int j = 0; j < VPT; ++j) ST(j, encode<DT>(&yc[j * EPV], oinv));
+                if (tail) store_vec<DT>(orow, tcol, tn, false, encode<DT>(yct, oinv));
+            } else {
+                float unused = 0.f;
+                out_pass(true, oinv, unused);
+            }
         } else if constexpr (OP == OP_SOFTMAX_BWD) {
             const float ys = FP8 ? a.s0[row] : 1.f, gs = FP8 ? a.s1[row] : 1.f;
             float st[1] = {0.f};
@@ -493,23 +520,15 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             float mean = 0.f, rstd;
             if (a.flags & F_RECOMPUTE) {
                 if constexpr (LN) {
-                    float sum = 0.f;
-                    fresh();
-#pragma unroll
-                    for (int j = 0; j < VPT; ++j) {
-                        float x[EPV];
-                        decode<DT>(d0[j], x, xs);
-#pragma unroll
-                        for (int i = 0; i < EPV; ++i) sum += x[i];
+                    // one pass of moments about a per-thread shift, Chan-merged
+                    float K = 0.f;
+                    {
+                        float x[EPV], xt[EPV];
+                        decode<DT>(d0[0], x, xs);
+                        decode<DT>(t0, xt, xs);
+                        K = (FULLS || ok_of(0)) ? x[0] : (tail ? xt[0] : 0.f);
                     }
-                    if (tail) {
-                        float x[EPV];
-                        decode<DT>(t0, x, xs);
-#pragma unroll
-                        for (int i = 0; i < EPV; ++i) sum += x[i];
-                    }
-                    const float tm = held > 0.f ? sum / held : 0.f;
-                    float m2 = 0.f;
+                    float s1 = 0.f, s2 = 0.f;
                     fresh();
 #pragma unroll
                     for (int j = 0; j < VPT; ++j) {
@@ -518,19 +537,26 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                         const bool ok = ok_of(j);
 #pragma unroll
                         for (int i = 0; i < EPV; ++i) {
-                            float d = ok ? x[i] - tm : 0.f;
-                            m2 = fmaf(d, d, m2);
+                            float d = ok ? x[i] - K : 0.f;
+                            s1 += d;
+                            s2 = fmaf(d, d, s2);
                         }
                     }
                     if (tail) {
                         float x[EPV];
                         decode<DT>(t0, x, xs);
                         for (int i = 0; i < tn; ++i) {
-                            float d = x[i] - tm;
-                            m2 = fmaf(d, d, m2);
+                            float d = x[i] - K;
+                            s1 += d;
+                            s2 = fmaf(d, d, s2);
                         }
                     }
-                    float st[3] = {held, tm, m2};
+                    float st[3] = {held, 0.f, 0.f};
+                    if (held > 0.f) {
+                        const float m = s1 / held;
+                        st[1] = K + m;
+                        st[2] = fmaxf(s2 - s1 * m, 0.f);
+                    }
                     row_reduce_chan(st, a, row, 2, c, red, xb, parity);
                     mean = st[1];
                     rstd = rsqrtf(st[2] * invN + a.eps);
