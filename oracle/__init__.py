@@ -68,6 +68,10 @@ def _load():
         "oracle_layernorm_bwd": ([_I64, _I64, P, P, P, ctypes.c_double, P, P, P, P], None),
         "oracle_rmsnorm_fwd": ([_I64, _I64, P, P, ctypes.c_double, P, P], None),
         "oracle_rmsnorm_bwd": ([_I64, _I64, P, P, P, ctypes.c_double, P, P, P], None),
+        "oracle_softmax_logits_bwd": ([_I64, _I64, P, P, P], None),
+        "oracle_quantize_rows": ([_I64, _I64, P, ctypes.c_int, P, P], None),
+        "oracle_pearson_bwd": ([_I64, _I64, P, P, P, P, P], None),
+        "oracle_wvar_bwd": ([_I64, _I64, P, P, P, P, P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -205,3 +209,43 @@ def rmsnorm_bwd(x, dy, gamma, eps: float):
     ws = np.empty_like(x)
     _load().oracle_rmsnorm_bwd(M, N, _p(x), _p(dy), _p(g), float(eps), _p(dx), _p(dg), _p(ws))
     return dx, dg
+
+
+def softmax_logits_bwd(x, dy) -> np.ndarray:
+    """dx = y * (dy - sum(dy * y)) with y = softmax(x) (the softmax-logits workload)."""
+    x, dy = _f64(x), _f64(dy)
+    M, N = x.shape
+    dx = np.empty_like(x)
+    _load().oracle_softmax_logits_bwd(M, N, _p(x), _p(dy), _p(dx))
+    return dx
+
+
+def quantize_rows(x, fmt: str):
+    """Row-wise quantisation of FP32-representable values; decisions in FP32.
+    fmt 'int8' -> (int8 codes, FP32 scales); 'fp8' -> (uint8 e4m3 codes, scales)."""
+    x32 = np.ascontiguousarray(x, dtype=np.float32)
+    if x32.astype(np.float64).tolist() != np.asarray(x, dtype=np.float64).tolist():
+        raise ValueError("quantize_rows takes values exactly representable in FP32")
+    M, N = x32.shape
+    codes = np.empty((M, N), dtype=np.uint8)
+    scale = np.empty(M, dtype=np.float32)
+    _load().oracle_quantize_rows(M, N, _p(x32), 0 if fmt == "int8" else 1, _p(codes), _p(scale))
+    return (codes.view(np.int8) if fmt == "int8" else codes), scale
+
+
+def pearson_bwd(x, y, dr):
+    """Backward of the per-row Pearson correlation; returns (dx, dy)."""
+    x, y, dr = _f64(x), _f64(y), _f64(dr)
+    M, N = x.shape
+    gx, gy = np.empty_like(x), np.empty_like(x)
+    _load().oracle_pearson_bwd(M, N, _p(x), _p(y), _p(dr), _p(gx), _p(gy))
+    return gx, gy
+
+
+def wvar_bwd(x, w, dv):
+    """Backward of the per-row weighted variance; returns (dx, dw)."""
+    x, w, dv = _f64(x), _f64(w), _f64(dv)
+    M, N = x.shape
+    gx, gw = np.empty_like(x), np.empty_like(x)
+    _load().oracle_wvar_bwd(M, N, _p(x), _p(w), _p(dv), _p(gx), _p(gw))
+    return gx, gw

@@ -322,3 +322,118 @@ void oracle_rmsnorm_bwd(int64_t M, int64_t N, const double *x, const double *dy,
     }
     if (dgamma) column_sums(M, N, dy, xhat_ws, dgamma);
 }
+
+/* ------------------------------------------- the other evaluation workloads */
+
+/* Softmax backward taking the logits (the softmax-logits workload): y is the
+ * softmax of x as defined above, then dx_i = y_i * (dy_i - sum_j dy_j y_j). */
+void oracle_softmax_logits_bwd(int64_t M, int64_t N, const double *x, const double *dy, double *dx)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m) {
+        const double *xr = x + m * N, *gr = dy + m * N;
+        double *dr = dx + m * N;
+        double mx = -INFINITY;
+        for (int64_t i = 0; i < N; ++i)
+            if (xr[i] > mx) mx = xr[i];
+        acc_t s = {0, 0};
+        for (int64_t i = 0; i < N; ++i) acc_add(&s, exp(xr[i] - mx));
+        const double sum = acc_get(&s);
+        acc_t c = {0, 0};
+        for (int64_t i = 0; i < N; ++i) acc_add(&c, gr[i] * (exp(xr[i] - mx) / sum));
+        const double cs = acc_get(&c);
+        for (int64_t i = 0; i < N; ++i) dr[i] = exp(xr[i] - mx) / sum * (gr[i] - cs);
+    }
+}
+
+/* Row-wise quantisation (the int8-quantisation workload).  The codes are
+ * integer decisions, so they are taken in the precision the library computes
+ * in, FP32, step by step: amax = max |x| (exact), inv = Q / amax and
+ * scale = amax / Q, each one correctly rounded FP32 division (1 and 1 for an
+ * all-zero row), v = x * inv rounded to FP32.  fmt 0 (int8, Q = 127):
+ * code = v rounded half to even, clamped to [-127, 127], stored two's
+ * complement.  fmt 1 (e4m3, Q = 448): code = e4m3 RNE of v saturated to +-448.
+ * x holds FP32 values (BF16 inputs are exact in FP32). */
+void oracle_quantize_rows(int64_t M, int64_t N, const float *x, int fmt, uint8_t *codes, float *scale)
+{
+    const float Q = fmt == 0 ? 127.0f : 448.0f;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m) {
+        const float *xr = x + m * N;
+        uint8_t *cr = codes + m * N;
+        float amax = 0.0f;
+        for (int64_t i = 0; i < N; ++i) {
+            float a = fabsf(xr[i]);
+            if (a > amax) amax = a;
+        }
+        volatile float inv = amax > 0.0f ? Q / amax : 1.0f;
+        volatile float sc = amax > 0.0f ? amax / Q : 1.0f;
+        scale[m] = sc;
+        for (int64_t i = 0; i < N; ++i) {
+            volatile float v = xr[i] * inv;
+            if (fmt == 0) {
+                float r = rintf(v);  /* round half to even in the default mode */
+                if (r > 127.0f) r = 127.0f;
+                if (r < -127.0f) r = -127.0f;
+                cr[i] = (uint8_t)(int8_t)r;
+            } else {
+                cr[i] = e4m3_from_double((double)v);
+            }
+        }
+    }
+}
+
+/* Pearson-correlation backward.  Per row: xc = x - mean(x), yc = y - mean(y),
+ * Sxx = sum xc^2, Syy = sum yc^2, Sxy = sum xc yc, r = Sxy / sqrt(Sxx Syy);
+ * dr/dx_i = yc_i / sqrt(Sxx Syy) - r xc_i / Sxx (the terms through the means
+ * vanish because sum yc = 0), symmetrically for y; scaled by dr[m]. */
+void oracle_pearson_bwd(int64_t M, int64_t N, const double *x, const double *y, const double *dr,
+                        double *dx, double *dy)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m) {
+        const double *xr = x + m * N, *yr = y + m * N;
+        const double mx = csum(xr, N, 1) / (double)N, my = csum(yr, N, 1) / (double)N;
+        acc_t sxx = {0, 0}, syy = {0, 0}, sxy = {0, 0};
+        for (int64_t i = 0; i < N; ++i) {
+            const double a = xr[i] - mx, b = yr[i] - my;
+            acc_add(&sxx, a * a);
+            acc_add(&syy, b * b);
+            acc_add(&sxy, a * b);
+        }
+        const double Sxx = acc_get(&sxx), Syy = acc_get(&syy), Sxy = acc_get(&sxy);
+        const double den = sqrt(Sxx * Syy), r = Sxy / den;
+        for (int64_t i = 0; i < N; ++i) {
+            const double a = xr[i] - mx, b = yr[i] - my;
+            dx[m * N + i] = dr[m] * (b / den - r * a / Sxx);
+            dy[m * N + i] = dr[m] * (a / den - r * b / Syy);
+        }
+    }
+}
+
+/* Weighted-variance backward.  Per row: W = sum w, mu = sum w x / W,
+ * v = sum w (x - mu)^2 / W; dv/dx_i = 2 w_i (x_i - mu) / W and
+ * dv/dw_i = ((x_i - mu)^2 - v) / W (the terms through mu vanish because
+ * sum w (x - mu) = 0); scaled by dv[m]. */
+void oracle_wvar_bwd(int64_t M, int64_t N, const double *x, const double *w, const double *dv,
+                     double *dx, double *dw)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m) {
+        const double *xr = x + m * N, *wr = w + m * N;
+        acc_t sw = {0, 0}, swx = {0, 0};
+        for (int64_t i = 0; i < N; ++i) {
+            acc_add(&sw, wr[i]);
+            acc_add(&swx, wr[i] * xr[i]);
+        }
+        const double W = acc_get(&sw), mu = acc_get(&swx) / W;
+        acc_t s2 = {0, 0};
+        for (int64_t i = 0; i < N; ++i) acc_add(&s2, wr[i] * (xr[i] - mu) * (xr[i] - mu));
+        const double v = acc_get(&s2) / W;
+        for (int64_t i = 0; i < N; ++i) {
+            const double d = xr[i] - mu;
+            dx[m * N + i] = dv[m] * 2.0 * wr[i] * d / W;
+            dw[m * N + i] = dv[m] * (d * d - v) / W;
+        }
+    }
+}
