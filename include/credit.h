@@ -66,7 +66,21 @@ typedef enum {
 } credit_status_t;
 
 typedef enum { CREDIT_F32 = 0, CREDIT_BF16 = 1, CREDIT_FP8_E4M3 = 2 } credit_dtype_t;
-typedef enum { CREDIT_SOFTMAX = 0, CREDIT_LAYERNORM = 1, CREDIT_RMSNORM = 2 } credit_op_t;
+/* Operators.  The first three exist in both directions; the others are the
+ * remaining reduction-reuse workloads of the paper's evaluation suite
+ * (Sec. IV-A) and exist in one direction each: SOFTMAX_LOGITS, PEARSON and
+ * WVAR backward only, the two QUANT operators forward only.  Where a call
+ * names an (operator, direction) pair, any other pair is CREDIT_ERR_INVALID_ARG. */
+typedef enum {
+    CREDIT_SOFTMAX = 0,
+    CREDIT_LAYERNORM = 1,
+    CREDIT_RMSNORM = 2,
+    CREDIT_SOFTMAX_LOGITS = 3, /* softmax backward taking the logits x (y is rebuilt in the row) */
+    CREDIT_QUANT_INT8 = 4,     /* row-wise int8 quantisation (codes + per-row scale)             */
+    CREDIT_QUANT_FP8 = 5,      /* row-wise e4m3 quantisation (codes + per-row scale)             */
+    CREDIT_PEARSON = 6,        /* Pearson correlation of two rows                                */
+    CREDIT_WVAR = 7            /* weighted variance of a row                                     */
+} credit_op_t;
 typedef enum { CREDIT_FWD = 0, CREDIT_BWD = 1 } credit_dir_t;
 typedef enum { CREDIT_TWO_PASS = 0, CREDIT_ROW_RESIDENT = 1, CREDIT_SPLIT_ROW = 2 } credit_variant_t;
 typedef enum {
@@ -181,6 +195,54 @@ credit_status_t credit_rmsnorm_bwd(credit_handle_t h, int64_t M, int64_t N, cred
                                    const credit_plan_t *plan, void *ws, size_t ws_bytes,
                                    void *stream);
 
+/* Softmax backward from the logits (the softmax-logits workload, Sec. IV-A):
+ * y = softmax(x) is recomputed inside the row from the resident x, then
+ * dx = y * (dy - sum(dy * y)).  One statistics stage carries (max, sum of
+ * exponentials, sum of dy times the exponentials); FP8 output adds its amax
+ * stage.  All three dtypes; x, dy and dx share `dt` (FP8 scales as above). */
+credit_status_t credit_softmax_logits_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                                          const void *x, int64_t ldx, const float *x_scale,
+                                          const void *dy, int64_t lddy, const float *dy_scale,
+                                          void *dx, int64_t lddx, float *dx_scale,
+                                          const credit_plan_t *plan, void *ws, size_t ws_bytes,
+                                          void *stream);
+
+/* Row-wise quantisation (the int8-quantisation workload, Sec. IV-A):
+ * amax = max |x| over the row, q_scale[row] = amax / Q (1 for an all-zero
+ * row), codes from v = x * (Q / amax) computed in FP32 (Q / amax rounded to
+ * FP32 first).  op = CREDIT_QUANT_INT8: Q = 127, code = round-half-even(v)
+ * clamped to [-127, 127], stored as int8.  op = CREDIT_QUANT_FP8: Q = 448,
+ * code = OCP e4m3fn RNE of v saturated to +-448, stored as uint8.
+ * x is CREDIT_F32 or CREDIT_BF16 (`dt`); q is [M, ldq] bytes. */
+credit_status_t credit_quantize_rows(credit_handle_t h, credit_op_t op, int64_t M, int64_t N,
+                                     credit_dtype_t dt, const void *x, int64_t ldx, void *q,
+                                     int64_t ldq, float *q_scale, const credit_plan_t *plan,
+                                     void *ws, size_t ws_bytes, void *stream);
+
+/* Pearson-correlation backward (Sec. IV-A): per row, with xc = x - mean(x),
+ * yc = y - mean(y), Sxx = sum xc^2, Syy = sum yc^2, Sxy = sum xc yc and
+ * r = Sxy / sqrt(Sxx Syy), given the upstream gradient dr[row]:
+ *   dx = dr * (yc / sqrt(Sxx Syy) - r * xc / Sxx),
+ *   dy = dr * (xc / sqrt(Sxx Syy) - r * yc / Syy).
+ * One stage of five co-moment statistics.  A row with Sxx or Syy == 0 gives
+ * non-finite outputs (r is undefined there).  CREDIT_F32 or CREDIT_BF16;
+ * dr is FP32 [M]. */
+credit_status_t credit_pearson_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                                   const void *x, int64_t ldx, const void *y, int64_t ldy,
+                                   const float *dr, void *dx, int64_t lddx, void *dy, int64_t lddy,
+                                   const credit_plan_t *plan, void *ws, size_t ws_bytes,
+                                   void *stream);
+
+/* Weighted-variance backward (Sec. IV-A): per row, W = sum w,
+ * mu = sum w x / W, v = sum w (x - mu)^2 / W, given the upstream gradient
+ * dv[row]:  dx = dv * 2 w (x - mu) / W,  dw = dv * ((x - mu)^2 - v) / W.
+ * One stage of three statistics (W, mu, sum w (x - mu)^2).  A row with
+ * W == 0 gives non-finite outputs.  CREDIT_F32 or CREDIT_BF16; dv is FP32 [M]. */
+credit_status_t credit_wvar_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                                const void *x, int64_t ldx, const void *w, int64_t ldw,
+                                const float *dv, void *dx, int64_t lddx, void *dw, int64_t lddw,
+                                const credit_plan_t *plan, void *ws, size_t ws_bytes, void *stream);
+
 /* Elementwise FP32 -> dtype encode of an [M, N] matrix with optional per-row
  * output scale (FP8: code = RNE_sat(x / scale[row])); and the inverse decode.
  * Contiguous rows (ld == N). */
@@ -253,7 +315,9 @@ credit_status_t credit_workload_info(credit_op_t op, credit_dir_t dir, credit_dt
 /* Plan of class c in [0, CREDIT_NUM_PLANS). */
 credit_status_t credit_plan_of_class(int32_t c, credit_plan_t *out);
 
-/* The 12 raw (unstandardized) features of a shape. */
+/* The 12 raw (unstandardized) features of a shape.  Defined for the softmax,
+ * LayerNorm and RMSNorm operators (the learned selector's domain; the other
+ * operators are planned by the analytic model): CREDIT_ERR_UNSUPPORTED else. */
 credit_status_t credit_features(credit_op_t op, credit_dir_t dir, credit_dtype_t dt, int64_t M,
                                 int64_t N, float *feat12);
 

@@ -23,6 +23,7 @@ MODEL_PATH = os.path.join(_HERE, "models", "selector_gfx950.txt")
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_TIMEOUT, ERR_MODEL = range(7)
 F32, BF16, FP8 = 0, 1, 2
 SOFTMAX, LAYERNORM, RMSNORM = 0, 1, 2
+SOFTMAX_LOGITS, QUANT_INT8, QUANT_FP8, PEARSON, WVAR = 3, 4, 5, 6, 7
 FWD, BWD = 0, 1
 TWO_PASS, ROW_RESIDENT, SPLIT_ROW = 0, 1, 2
 SEL_LEARNED, SEL_ANALYTIC, SEL_EXHAUSTIVE, SEL_FIXED, SEL_PEAK = range(5)
@@ -87,6 +88,11 @@ _SIGS = {
     "credit_rmsnorm_fwd": ([_P, _I64, _I64, _S, _P, _I64, _P, _P, _F, _P, _I64, _P, _P, _PP, _P, _SZ, _P], _S),
     "credit_rmsnorm_bwd": ([_P, _I64, _I64, _S, _P, _I64, _P, _P, _I64, _P, _P, _P, _F, _P, _I64, _P, _P, _PP, _P,
                             _SZ, _P], _S),
+    "credit_softmax_logits_bwd": ([_P, _I64, _I64, _S, _P, _I64, _P, _P, _I64, _P, _P, _I64, _P, _PP, _P, _SZ, _P],
+                                  _S),
+    "credit_quantize_rows": ([_P, _S, _I64, _I64, _S, _P, _I64, _P, _I64, _P, _PP, _P, _SZ, _P], _S),
+    "credit_pearson_bwd": ([_P, _I64, _I64, _S, _P, _I64, _P, _I64, _P, _P, _I64, _P, _I64, _PP, _P, _SZ, _P], _S),
+    "credit_wvar_bwd": ([_P, _I64, _I64, _S, _P, _I64, _P, _I64, _P, _P, _I64, _P, _I64, _PP, _P, _SZ, _P], _S),
     "credit_encode": ([_P, _I64, _I64, _S, _P, _P, _P, _P], _S),
     "credit_decode": ([_P, _I64, _I64, _S, _P, _P, _P, _P], _S),
     "credit_check_errors": ([_P, _P], _S),
@@ -506,6 +512,73 @@ def rmsnorm_bwd(x, dy, gamma, rstd=None, eps: float = 1e-5, x_scale=None, dy_sca
                            _ptr(gamma), _ptr(rstd), float(eps), _ptr(dx), _ld(dx), _ptr(dxs), _ptr(dg), pp, w, wn,
                            s))
     return dx, dxs, dg
+
+
+def softmax_logits_bwd(x, dy, x_scale=None, dy_scale=None, p: Optional[Plan] = None, out=None,
+                       h: Optional[Handle] = None):
+    """Softmax backward from the logits x: y = softmax(x) is rebuilt inside
+    the row, dx = y * (dy - sum(dy * y)).  Returns (dx, dx_scale)."""
+    h = h or handle(x.device.index)
+    dt = io_dtype(x)
+    M, N = x.shape
+    dx = out if out is not None else _empty_like_out(x, M, N)
+    dxs = _scale_out(x, M) if dt == FP8 else None
+    s = h._stream()
+    pp = None if p is None else ctypes.byref(p)
+    _launch(h, "credit_softmax_logits_bwd", SOFTMAX_LOGITS, BWD, dt, M, N, p, s,
+            lambda w, wn: (h.ptr, M, N, dt, _ptr(x), _ld(x), _ptr(x_scale), _ptr(dy), _ld(dy), _ptr(dy_scale),
+                           _ptr(dx), _ld(dx), _ptr(dxs), pp, w, wn, s))
+    return dx, dxs
+
+
+def quantize_rows(x, fmt: str = "int8", p: Optional[Plan] = None, out=None, out_scale=None,
+                  h: Optional[Handle] = None):
+    """Row-wise quantisation of an FP32 / BF16 matrix.  fmt 'int8': codes
+    torch.int8 in [-127, 127], scale = amax / 127; fmt 'fp8': e4m3 codes as
+    torch.uint8, scale = amax / 448.  Returns (codes, scale)."""
+    torch = _torch()
+    h = h or handle(x.device.index)
+    dt = io_dtype(x)
+    op = {"int8": QUANT_INT8, "fp8": QUANT_FP8}[fmt]
+    M, N = x.shape
+    q = out if out is not None else torch.empty((M, N), dtype=torch.int8 if fmt == "int8" else torch.uint8,
+                                                device=x.device)
+    qs = out_scale if out_scale is not None else _scale_out(x, M)
+    s = h._stream()
+    pp = None if p is None else ctypes.byref(p)
+    _launch(h, "credit_quantize_rows", op, FWD, dt, M, N, p, s,
+            lambda w, wn: (h.ptr, op, M, N, dt, _ptr(x), _ld(x), _ptr(q), _ld(q), _ptr(qs), pp, w, wn, s))
+    return q, qs
+
+
+def pearson_bwd(x, y, dr, p: Optional[Plan] = None, h: Optional[Handle] = None):
+    """Backward of the per-row Pearson correlation r(x, y) given dr [M].
+    Returns (dx, dy)."""
+    h = h or handle(x.device.index)
+    dt = io_dtype(x)
+    M, N = x.shape
+    gx, gy = _empty_like_out(x, M, N), _empty_like_out(x, M, N)
+    s = h._stream()
+    pp = None if p is None else ctypes.byref(p)
+    _launch(h, "credit_pearson_bwd", PEARSON, BWD, dt, M, N, p, s,
+            lambda w, wn: (h.ptr, M, N, dt, _ptr(x), _ld(x), _ptr(y), _ld(y), _ptr(dr), _ptr(gx), _ld(gx),
+                           _ptr(gy), _ld(gy), pp, w, wn, s))
+    return gx, gy
+
+
+def wvar_bwd(x, w, dv, p: Optional[Plan] = None, h: Optional[Handle] = None):
+    """Backward of the per-row weighted variance v(x, w) given dv [M].
+    Returns (dx, dw)."""
+    h = h or handle(x.device.index)
+    dt = io_dtype(x)
+    M, N = x.shape
+    gx, gw = _empty_like_out(x, M, N), _empty_like_out(x, M, N)
+    s = h._stream()
+    pp = None if p is None else ctypes.byref(p)
+    _launch(h, "credit_wvar_bwd", WVAR, BWD, dt, M, N, p, s,
+            lambda ws, wn: (h.ptr, M, N, dt, _ptr(x), _ld(x), _ptr(w), _ld(w), _ptr(dv), _ptr(gx), _ld(gx),
+                            _ptr(gw), _ld(gw), pp, ws, wn, s))
+    return gx, gw
 
 
 def encode(x, dtype: int, row_scale=None, h: Optional[Handle] = None):

@@ -86,6 +86,29 @@ template <> __device__ __forceinline__ u32x4 encode<DT_FP8>(const float *f, floa
     return v;
 }
 
+// Row-quantisation codes of EPV values (one byte each, packed little-endian
+// into EPV / 4 words).  The code decision is taken in FP32 on v = f * inv:
+// int8 rounds half to even and clamps to [-127, 127]; e4m3 rounds to nearest
+// even with saturation to +-448.
+template <bool I8, int EPV> __device__ __forceinline__ void quant_codes(const float *f, float inv, unsigned *w) {
+#pragma unroll
+    for (int i = 0; i < EPV / 4; ++i) {
+        if constexpr (I8) {
+            unsigned word = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const float v = __builtin_rintf(__builtin_amdgcn_fmed3f(f[4 * i + b] * inv, -127.f, 127.f));
+                word |= ((unsigned)(int)v & 0xffu) << (8 * b);
+            }
+            w[i] = word;
+        } else {
+            int word = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(f[4 * i] * inv), sat448(f[4 * i + 1] * inv), 0, false);
+            word = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(f[4 * i + 2] * inv), sat448(f[4 * i + 3] * inv), word, true);
+            w[i] = (unsigned)word;
+        }
+    }
+}
+
 // ------------------------------------------------------------ loads/stores
 // Vector at element e of a row starting at byte pointer `row`; nv in [0, EPV]
 // elements are valid.  Full vectors of aligned rows use one 128-bit access;
@@ -250,6 +273,42 @@ struct MergeChan {
     }
 };
 
+// Online softmax statistics with a weighted sum riding along: (c, s, t) with
+// s = sum 2^(q - c) and t = sum g * 2^(q - c); both sums rescale together.
+struct MergeSoftmax3 {
+    __device__ __forceinline__ void operator()(float (&a)[3], const float (&b)[3]) const {
+        float c = fmaxf(a[0], b[0]);
+        float fa = a[0] == -INFINITY ? 0.f : fast_exp2(a[0] - c);
+        float fb = b[0] == -INFINITY ? 0.f : fast_exp2(b[0] - c);
+        a[0] = c;
+        a[1] = a[1] * fa + b[1] * fb;
+        a[2] = a[2] * fa + b[2] * fb;
+    }
+};
+// Pairwise combination of bivariate co-moments (count, mean_x, mean_y, Cxx,
+// Cyy, Cxy): Chan's update applied to the cross term as well.
+__device__ __forceinline__ void co_merge(float (&a)[6], float nb, float mxb, float myb, float cxxb, float cyyb,
+                                         float cxyb) {
+    if (nb == 0.f) return;
+    if (a[0] == 0.f) {
+        a[0] = nb; a[1] = mxb; a[2] = myb; a[3] = cxxb; a[4] = cyyb; a[5] = cxyb;
+        return;
+    }
+    const float n = a[0] + nb, dx = mxb - a[1], dy = myb - a[2];
+    const float wb = nb / n, f = a[0] * wb;
+    a[1] = a[1] + dx * wb;
+    a[2] = a[2] + dy * wb;
+    a[3] = a[3] + cxxb + dx * dx * f;
+    a[4] = a[4] + cyyb + dy * dy * f;
+    a[5] = a[5] + cxyb + dx * dy * f;
+    a[0] = n;
+}
+struct MergeCo {
+    __device__ __forceinline__ void operator()(float (&a)[6], const float (&b)[6]) const {
+        co_merge(a, b[0], b[1], b[2], b[3], b[4], b[5]);
+    }
+};
+
 // ------------------------------------------------- workgroup -> (member, group)
 // Hardware workgroup ids are dealt round-robin to the 8 XCDs (id % 8), each
 // with its own L2.  With F_XCD, an XCD hosts only some member indices c, i.e.
@@ -281,7 +340,7 @@ __device__ __forceinline__ void member_of(const RowArgs &a, int bid, int &c, int
 // agent-scope atomic loads, so a reader that sees the current epoch also sees
 // the value that came with it; no fence and no counter reset are needed.
 __device__ __forceinline__ unsigned long long *slot_ptr(const RowArgs &a, int64_t row, int stage, int c, int j) {
-    return a.slots + (((row * kMaxStages + stage) * (int64_t)a.k + c) * kMaxQ + j);
+    return a.slots + (((row * kMaxStages + stage) * (int64_t)a.k + c) * a.qs + j);
 }
 
 // Publishes this workgroup's q partials for (row, stage) and gathers all k*q
@@ -302,17 +361,31 @@ __device__ __forceinline__ void exchange(const RowArgs &a, int64_t row, int stag
         }
     }
     if (tid < 64) {
+        // wave 0 polls the k * Q slots, P per lane (P = 1 unless k * Q > 64)
+        constexpr int P = (kMaxK * Q + 63) / 64;
         const int lane = tid;
-        bool ok = lane >= kq;
-        unsigned long long w = 0;
-        unsigned long long *p = ok ? nullptr : slot_ptr(a, row, stage, lane / Q, lane % Q);
+        bool ok[P];
+        unsigned long long w[P];
+        unsigned long long *p[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int s = lane + 64 * i;
+            ok[i] = s >= kq;
+            w[i] = 0;
+            p[i] = ok[i] ? nullptr : slot_ptr(a, row, stage, s / Q, s % Q);
+        }
         unsigned spins = 0;
         while (true) {
-            if (!ok) {
-                w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = (unsigned)(w >> 32) == a.epoch;
+            bool all = true;
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                if (!ok[i]) {
+                    w[i] = __hip_atomic_load(p[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok[i] = (unsigned)(w[i] >> 32) == a.epoch;
+                }
+                all = all && ok[i];
             }
-            if (__all(ok)) break;
+            if (__all(all)) break;
             // The flag holds the epoch of the launch that timed out, so a stale
             // flag from an earlier launch never cuts this launch's waits short.
             if (++spins > a.spin_limit ||
@@ -323,7 +396,11 @@ __device__ __forceinline__ void exchange(const RowArgs &a, int64_t row, int stag
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        if (lane < kq) xb[lane] = ok ? __uint_as_float((unsigned)w) : 0.f;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int s = lane + 64 * i;
+            if (s < kq) xb[s] = ok[i] ? __uint_as_float((unsigned)w[i]) : 0.f;
+        }
     }
     __syncthreads();
 }

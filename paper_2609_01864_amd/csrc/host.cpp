@@ -31,6 +31,16 @@ const void *twopass_kernel_rms_fwd(int, int);
 const void *twopass_kernel_softmax_bwd(int, int);
 const void *twopass_kernel_ln_bwd(int, int);
 const void *twopass_kernel_rms_bwd(int, int);
+const void *resident_kernel_smxl_bwd(int, int);
+const void *resident_kernel_quant_i8(int, int);
+const void *resident_kernel_quant_f8(int, int);
+const void *resident_kernel_pearson_bwd(int, int);
+const void *resident_kernel_wvar_bwd(int, int);
+const void *twopass_kernel_smxl_bwd(int, int);
+const void *twopass_kernel_quant_i8(int, int);
+const void *twopass_kernel_quant_f8(int, int);
+const void *twopass_kernel_pearson_bwd(int, int);
+const void *twopass_kernel_wvar_bwd(int, int);
 const void *colreduce_kernel();
 const void *colstats_kernel(int, bool);
 const void *control_kernel();
@@ -65,11 +75,31 @@ uint32_t next_epoch() {
     return e;
 }
 
-int kop(int op, int dir) { return op + 3 * dir; }
+// Public (operator, direction) -> kernel operator; -1 for a pair that does
+// not exist (e.g. a forward of the backward-only workloads).
+int kop(int op, int dir) {
+    if (dir != CREDIT_FWD && dir != CREDIT_BWD) return -1;
+    if (op >= CREDIT_SOFTMAX && op <= CREDIT_RMSNORM) return op + 3 * dir;
+    if (op == CREDIT_SOFTMAX_LOGITS && dir == CREDIT_BWD) return OP_SMXL_BWD;
+    if (op == CREDIT_QUANT_INT8 && dir == CREDIT_FWD) return OP_QUANT_I8;
+    if (op == CREDIT_QUANT_FP8 && dir == CREDIT_FWD) return OP_QUANT_F8;
+    if (op == CREDIT_PEARSON && dir == CREDIT_BWD) return OP_PEARSON_BWD;
+    if (op == CREDIT_WVAR && dir == CREDIT_BWD) return OP_WVAR_BWD;
+    return -1;
+}
+// I/O dtypes an operator is built for: quantisation reads FP32 / BF16 and
+// writes codes; Pearson and weighted variance take FP32 / BF16.
+bool dt_ok(int k_op, int dt) {
+    if (dt < CREDIT_F32 || dt > CREDIT_FP8_E4M3) return false;
+    if (is_quant(k_op) || k_op == OP_PEARSON_BWD || k_op == OP_WVAR_BWD) return dt != CREDIT_FP8_E4M3;
+    return k_op >= 0 && k_op < OP_COUNT;
+}
+bool core_op(int k_op) { return k_op >= OP_SOFTMAX_FWD && k_op <= OP_RMS_BWD; }
 int dt_bytes(int dt) { return dt == CREDIT_F32 ? 4 : dt == CREDIT_BF16 ? 2 : 1; }
 int dt_epv(int dt) { return 16 / dt_bytes(dt); }
 int ncp_of(int k_op) { return k_op == OP_LN_BWD ? 2 : k_op == OP_RMS_BWD ? 1 : 0; }
-bool two_inputs(int k_op) { return k_op >= OP_SOFTMAX_BWD; }
+bool two_inputs(int k_op) { return two_in(k_op); }
+int out_bytes(int k_op, int dt) { return is_quant(k_op) ? 1 : dt_bytes(dt); }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 const void *resident_fn(int k_op, int dt, int vpt) {
@@ -80,6 +110,11 @@ const void *resident_fn(int k_op, int dt, int vpt) {
     case OP_SOFTMAX_BWD: return resident_kernel_softmax_bwd(dt, vpt);
     case OP_LN_BWD: return resident_kernel_ln_bwd(dt, vpt);
     case OP_RMS_BWD: return resident_kernel_rms_bwd(dt, vpt);
+    case OP_SMXL_BWD: return resident_kernel_smxl_bwd(dt, vpt);
+    case OP_QUANT_I8: return resident_kernel_quant_i8(dt, vpt);
+    case OP_QUANT_F8: return resident_kernel_quant_f8(dt, vpt);
+    case OP_PEARSON_BWD: return resident_kernel_pearson_bwd(dt, vpt);
+    case OP_WVAR_BWD: return resident_kernel_wvar_bwd(dt, vpt);
     }
     return nullptr;
 }
@@ -91,6 +126,11 @@ const void *twopass_fn(int k_op, int dt, int block) {
     case OP_SOFTMAX_BWD: return twopass_kernel_softmax_bwd(dt, block);
     case OP_LN_BWD: return twopass_kernel_ln_bwd(dt, block);
     case OP_RMS_BWD: return twopass_kernel_rms_bwd(dt, block);
+    case OP_SMXL_BWD: return twopass_kernel_smxl_bwd(dt, block);
+    case OP_QUANT_I8: return twopass_kernel_quant_i8(dt, block);
+    case OP_QUANT_F8: return twopass_kernel_quant_f8(dt, block);
+    case OP_PEARSON_BWD: return twopass_kernel_pearson_bwd(dt, block);
+    case OP_WVAR_BWD: return twopass_kernel_wvar_bwd(dt, block);
     }
     return nullptr;
 }
@@ -107,7 +147,7 @@ int model_waves(int k_op, int dt, int vpt) {
 // Number of exchange stages of a row (for the control kernel and the model).
 int stages_of(int k_op, int dt, bool recompute) {
     int L = 1;
-    if (dt == CREDIT_FP8_E4M3 && k_op != OP_SOFTMAX_FWD) L += 1;
+    if (dt == CREDIT_FP8_E4M3 && k_op != OP_SOFTMAX_FWD && !is_quant(k_op)) L += 1;
     if (recompute && (k_op == OP_LN_BWD || k_op == OP_RMS_BWD)) L += 1;
     return L;
 }
@@ -238,7 +278,7 @@ credit_status_t resolve(credit_handle_t h, int k_op, int dt, int64_t M, int64_t 
     size_t off = 256;
     if (k > 1) {
         L.off_slots = off;
-        off = align256(off + (size_t)M * kMaxStages * k * kMaxQ * 8);
+        off = align256(off + (size_t)M * kMaxStages * k * q_of(k_op) * 8);
     }
     if (ncp) {
         L.parts = L.groups;
@@ -276,6 +316,9 @@ struct OpCall {
     float *mean_out, *rstd_out;
     float *dgamma, *dbeta;
     float eps;
+    void *out1;         // second output (Pearson dy, weighted-variance dw)
+    int64_t ldo1;
+    const float *rowg;  // per-row upstream gradient (Pearson dr, weighted-variance dv)
 };
 
 credit_status_t pick_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t *out, float *pred);
@@ -283,11 +326,13 @@ credit_status_t pick_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_
 // Issues an operator with a resolved launch on `stream`.
 credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void *ws, hipStream_t stream,
                       bool recompute) {
-    const int B = dt_bytes(c.dt);
+    const int B = dt_bytes(c.dt), OB = out_bytes(c.k_op, c.dt);
     RowArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.in0 = c.in0; a.in1 = c.in1; a.out = c.out;
-    a.ld0 = c.ld0; a.ld1 = c.ld1; a.ldo = c.ldo;
+    a.in0 = c.in0; a.in1 = c.in1; a.out = c.out; a.out1 = c.out1;
+    a.ld0 = c.ld0; a.ld1 = c.ld1; a.ldo = c.ldo; a.ldo1 = c.ldo1;
+    a.rowg = c.rowg;
+    a.qs = q_of(c.k_op);
     a.s0 = c.s0; a.s1 = c.s1; a.so = c.so;
     a.gamma = c.gamma; a.beta = c.beta;
     a.mean_in = c.mean_in; a.rstd_in = c.rstd_in;
@@ -295,12 +340,12 @@ credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void 
     a.M = c.M; a.N = c.N;
     a.eps = c.eps;
     a.errflag = h->errflag;
-    a.safe = (const char *)h->errflag + 256;  // 256 zero bytes, never written
     a.spin_limit = (unsigned)std::min<int64_t>(h->spin_limit, 0xffffffffLL);
     int flags = 0;
     if (al16(c.in0) && (c.ld0 * B) % 16 == 0) flags |= F_ALIGN0;
     if (c.in1 && al16(c.in1) && (c.ld1 * B) % 16 == 0) flags |= F_ALIGN1;
-    if (al16(c.out) && (c.ldo * B) % 16 == 0) flags |= F_ALIGNO;
+    if (al16(c.out) && (c.ldo * OB) % 16 == 0) flags |= F_ALIGNO;
+    if (c.out1 && al16(c.out1) && (c.ldo1 * B) % 16 == 0) flags |= F_ALIGNO1;
     if ((!c.gamma || al16(c.gamma)) && (!c.beta || al16(c.beta))) flags |= F_ALIGNP;
     if (recompute) flags |= F_RECOMPUTE;
     if (h->drop_publish) flags |= F_TEST_DROP_PUBLISH;
@@ -366,8 +411,9 @@ credit_status_t run_op(credit_handle_t h, const OpCall &c, const credit_plan_t *
                        void *stream, bool recompute) {
     if (!h) return CREDIT_ERR_INVALID_ARG;
     if (c.M < 0 || c.N <= 0) return CREDIT_ERR_INVALID_ARG;
-    if (c.dt < 0 || c.dt > 2) return CREDIT_ERR_INVALID_ARG;
+    if (!dt_ok(c.k_op, c.dt)) return CREDIT_ERR_INVALID_ARG;
     if (c.ld0 < c.N || c.ldo < c.N || (two_inputs(c.k_op) && c.ld1 < c.N)) return CREDIT_ERR_INVALID_ARG;
+    if (two_out(c.k_op) && c.ldo1 < c.N) return CREDIT_ERR_INVALID_ARG;
     if (c.M == 0) {
         hipStream_t s = (hipStream_t)stream;
         if (c.dgamma && zero_words(c.dgamma, c.N, s) != hipSuccess) return CREDIT_ERR_HIP;
@@ -375,9 +421,11 @@ credit_status_t run_op(credit_handle_t h, const OpCall &c, const credit_plan_t *
         return CREDIT_OK;
     }
     if (!c.in0 || !c.out || (two_inputs(c.k_op) && !c.in1)) return CREDIT_ERR_INVALID_ARG;
+    if (two_out(c.k_op) && (!c.out1 || !c.rowg)) return CREDIT_ERR_INVALID_ARG;
     if (c.dt == CREDIT_FP8_E4M3) {
         if (!c.s0 || !c.so || (two_inputs(c.k_op) && !c.s1)) return CREDIT_ERR_INVALID_ARG;
     }
+    if (is_quant(c.k_op) && !c.so) return CREDIT_ERR_INVALID_ARG;
     const bool norm = c.k_op == OP_LN_FWD || c.k_op == OP_RMS_FWD || c.k_op == OP_LN_BWD || c.k_op == OP_RMS_BWD;
     if (norm && !c.gamma) return CREDIT_ERR_INVALID_ARG;
     if (c.k_op == OP_LN_FWD && !c.beta) return CREDIT_ERR_INVALID_ARG;
@@ -406,21 +454,25 @@ credit_workload_t workload(int k_op, int dt, bool recompute) {
     std::memset(&w, 0, sizeof(w));
     const float e = (float)dt_bytes(dt);
     const int nin = two_inputs(k_op) ? 2 : 1;
+    const float eo = (float)out_bytes(k_op, dt) * (two_out(k_op) ? 2.f : 1.f);  // output bytes per element
     int L = 0;
     float stage_bytes = 0.f;
     if (recompute && (k_op == OP_LN_BWD || k_op == OP_RMS_BWD)) {
         w.q[L++] = k_op == OP_LN_BWD ? 2 : 1;
         stage_bytes += e;  // reads x only
     }
-    w.q[L++] = (k_op == OP_SOFTMAX_FWD || k_op == OP_LN_FWD || k_op == OP_LN_BWD) ? 2 : 1;
+    int q = (k_op == OP_SOFTMAX_FWD || k_op == OP_LN_FWD || k_op == OP_LN_BWD) ? 2 : 1;
+    if (k_op == OP_SMXL_BWD || k_op == OP_WVAR_BWD) q = 3;
+    if (k_op == OP_PEARSON_BWD) q = 5;
+    w.q[L++] = q;
     stage_bytes += nin * e;
-    if (dt == CREDIT_FP8_E4M3 && k_op != OP_SOFTMAX_FWD) {
+    if (dt == CREDIT_FP8_E4M3 && k_op != OP_SOFTMAX_FWD && !is_quant(k_op)) {
         w.q[L++] = 1;  // amax of the output before it can be scaled
         stage_bytes += nin * e;
     }
     w.stages = L;
-    w.b_staged = nin * e + e;
-    w.b_base = stage_bytes + nin * e + e;
+    w.b_staged = nin * e + eo;
+    w.b_base = stage_bytes + nin * e + eo;
     w.b_reread = w.b_base - w.b_staged;
     w.b_keep = nin * e;
     return w;
@@ -451,7 +503,7 @@ void model_delta(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, doub
 
 // ---------------------------------------------------------------- timing
 struct Bufs {
-    char *in0, *in1, *out, *ws;
+    char *in0, *in1, *out, *out1, *ws;
     float *s0, *s1, *so, *gamma, *beta, *mean, *rstd, *dgamma, *dbeta;
     size_t ws_bytes;
 };
@@ -492,13 +544,14 @@ credit_status_t ensure_arena(credit_handle_t h, size_t bytes) {
 credit_status_t prepare(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, size_t ws_bytes, Bufs &b) {
     const size_t mat = align256((size_t)M * N * dt_bytes(dt));
     const size_t vecM = align256((size_t)M * 4), vecN = align256((size_t)N * 4);
-    size_t total = mat * 3 + vecM * 5 + vecN * 4 + align256(ws_bytes);
+    size_t total = mat * 4 + vecM * 5 + vecN * 4 + align256(ws_bytes);
     credit_status_t st = ensure_arena(h, total);
     if (st != CREDIT_OK) return st;
     char *p = h->arena;
     b.in0 = p; p += mat;
     b.in1 = p; p += mat;
     b.out = p; p += mat;
+    b.out1 = p; p += mat;
     b.s0 = (float *)p; p += vecM;
     b.s1 = (float *)p; p += vecM;
     b.so = (float *)p; p += vecM;
@@ -536,6 +589,11 @@ OpCall call_for(int k_op, int dt, int64_t M, int64_t N, const Bufs &b) {
     c.mean_in = b.mean; c.rstd_in = b.rstd;
     c.dgamma = b.dgamma; c.dbeta = b.dbeta;
     c.eps = 1e-5f;
+    if (two_out(k_op)) {
+        c.out1 = b.out1;
+        c.ldo1 = N;
+        c.rowg = b.mean;  // any finite per-row values
+    }
     return c;
 }
 
@@ -609,6 +667,7 @@ credit_status_t time_control(credit_handle_t h, int k_op, int dt, int64_t M, int
     RowArgs a;
     std::memset(&a, 0, sizeof(a));
     a.M = M; a.N = N; a.k = L.k; a.groups = L.groups;
+    a.qs = q_of(k_op);
     a.slots = (unsigned long long *)(ws + L.off_slots);
     a.errflag = h->errflag;
     a.spin_limit = (unsigned)std::min<int64_t>(h->spin_limit, 0xffffffffLL);
@@ -633,7 +692,7 @@ credit_status_t copy_bw(credit_handle_t h, size_t bytes, int reps, float *gbps) 
     const void *src = h->arena;
     void *dst = h->arena + bytes;
     int64_t n = (int64_t)(bytes / 16);
-    int grid = h->cus * 8;
+    int grid = (int)((n + 255) / 256);
     float us = 0.f;
     st = time_median(h, reps > 0 ? reps : 15, 0,
                      [&]() {
@@ -785,7 +844,9 @@ credit_status_t pick_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_
     credit_status_t st = CREDIT_OK;
     switch (sel) {
     case CREDIT_SEL_LEARNED:
-        if (h->has_model) {
+        // the learned selector's features cover the softmax / LayerNorm /
+        // RMSNorm operators; the other workloads use the analytic model
+        if (h->has_model && core_op(k_op)) {
             st = learned_pick(h, k_op, dt, M, N, out);
             if (st == CREDIT_OK) break;
         }
@@ -979,7 +1040,8 @@ credit_status_t credit_set_selector(credit_handle_t h, credit_selector_t s) {
 }
 
 static bool valid_enum(credit_op_t op, credit_dir_t dir, credit_dtype_t dt) {
-    return (int)op >= 0 && (int)op <= 2 && (int)dir >= 0 && (int)dir <= 1 && (int)dt >= 0 && (int)dt <= 2;
+    const int k = kop((int)op, (int)dir);
+    return k >= 0 && dt_ok(k, (int)dt);
 }
 
 credit_status_t credit_workspace_size(credit_handle_t h, credit_op_t op, credit_dir_t dir, credit_dtype_t dt,
@@ -1139,6 +1201,61 @@ credit_status_t credit_rmsnorm_bwd(credit_handle_t h, int64_t M, int64_t N, cred
     try { return run_op(h, c, plan, ws, ws_bytes, stream, rstd == nullptr); } catch (...) { return CREDIT_ERR_HIP; }
 }
 
+credit_status_t credit_softmax_logits_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const void *x,
+                                          int64_t ldx, const float *x_scale, const void *dy, int64_t lddy,
+                                          const float *dy_scale, void *dx, int64_t lddx, float *dx_scale,
+                                          const credit_plan_t *plan, void *ws, size_t ws_bytes, void *stream) {
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = OP_SMXL_BWD; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = x; c.ld0 = ldx; c.s0 = x_scale;
+    c.in1 = dy; c.ld1 = lddy; c.s1 = dy_scale;
+    c.out = dx; c.ldo = lddx; c.so = dx_scale;
+    try { return run_op(h, c, plan, ws, ws_bytes, stream, false); } catch (...) { return CREDIT_ERR_HIP; }
+}
+
+credit_status_t credit_quantize_rows(credit_handle_t h, credit_op_t op, int64_t M, int64_t N, credit_dtype_t dt,
+                                     const void *x, int64_t ldx, void *q, int64_t ldq, float *q_scale,
+                                     const credit_plan_t *plan, void *ws, size_t ws_bytes, void *stream) {
+    if (op != CREDIT_QUANT_INT8 && op != CREDIT_QUANT_FP8) return CREDIT_ERR_INVALID_ARG;
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = op == CREDIT_QUANT_INT8 ? OP_QUANT_I8 : OP_QUANT_F8; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = x; c.ld0 = ldx;
+    c.out = q; c.ldo = ldq; c.so = q_scale;
+    try { return run_op(h, c, plan, ws, ws_bytes, stream, false); } catch (...) { return CREDIT_ERR_HIP; }
+}
+
+credit_status_t credit_pearson_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const void *x,
+                                   int64_t ldx, const void *y, int64_t ldy, const float *dr, void *dx, int64_t lddx,
+                                   void *dy, int64_t lddy, const credit_plan_t *plan, void *ws, size_t ws_bytes,
+                                   void *stream) {
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = OP_PEARSON_BWD; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = x; c.ld0 = ldx;
+    c.in1 = y; c.ld1 = ldy;
+    c.rowg = dr;
+    c.out = dx; c.ldo = lddx;
+    c.out1 = dy; c.ldo1 = lddy;
+    try { return run_op(h, c, plan, ws, ws_bytes, stream, false); } catch (...) { return CREDIT_ERR_HIP; }
+}
+
+credit_status_t credit_wvar_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const void *x,
+                                int64_t ldx, const void *w, int64_t ldw, const float *dv, void *dx, int64_t lddx,
+                                void *dw, int64_t lddw, const credit_plan_t *plan, void *ws, size_t ws_bytes,
+                                void *stream) {
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = OP_WVAR_BWD; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = x; c.ld0 = ldx;
+    c.in1 = w; c.ld1 = ldw;
+    c.rowg = dv;
+    c.out = dx; c.ldo = lddx;
+    c.out1 = dw; c.ldo1 = lddw;
+    try { return run_op(h, c, plan, ws, ws_bytes, stream, false); } catch (...) { return CREDIT_ERR_HIP; }
+}
+
 credit_status_t credit_encode(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const float *x,
                               const float *row_scale, void *out, void *stream) {
     if (!h || M < 0 || N <= 0 || (int)dt < 0 || (int)dt > 2 || (M > 0 && (!x || !out))) return CREDIT_ERR_INVALID_ARG;
@@ -1230,6 +1347,7 @@ credit_status_t credit_plan_of_class(int32_t c, credit_plan_t *out) {
 credit_status_t credit_features(credit_op_t op, credit_dir_t dir, credit_dtype_t dt, int64_t M, int64_t N,
                                 float *feat12) {
     if (!feat12 || !valid_enum(op, dir, dt) || M <= 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
+    if (!core_op(kop(op, dir))) return CREDIT_ERR_UNSUPPORTED;
     features(kop(op, dir), dt, M, N, feat12);
     return CREDIT_OK;
 }

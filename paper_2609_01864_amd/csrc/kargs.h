@@ -5,11 +5,20 @@
 
 namespace credit {
 
-enum KOp { OP_SOFTMAX_FWD = 0, OP_LN_FWD = 1, OP_RMS_FWD = 2, OP_SOFTMAX_BWD = 3, OP_LN_BWD = 4, OP_RMS_BWD = 5 };
+enum KOp {
+    OP_SOFTMAX_FWD = 0, OP_LN_FWD = 1, OP_RMS_FWD = 2, OP_SOFTMAX_BWD = 3, OP_LN_BWD = 4, OP_RMS_BWD = 5,
+    // the other reduction-reuse workloads of the evaluation suite (Sec. IV-A)
+    OP_SMXL_BWD = 6,     // softmax backward from the logits (y recomputed in the row)
+    OP_QUANT_I8 = 7,     // row-wise int8 quantisation, scale = amax / 127
+    OP_QUANT_F8 = 8,     // row-wise e4m3 quantisation, scale = amax / 448
+    OP_PEARSON_BWD = 9,  // Pearson-correlation backward (x, y, dr -> dx, dy)
+    OP_WVAR_BWD = 10,    // weighted-variance backward (x, w, dv -> dx, dw)
+    OP_COUNT = 11
+};
 enum KDt { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };
 
 constexpr int kMaxStages = 3;  // statistics stages per row (recompute, main, amax)
-constexpr int kMaxQ = 2;       // statistics per stage
+constexpr int kMaxQ = 5;       // statistics per stage (Pearson co-moments)
 constexpr int kMaxK = 32;      // largest split factor
 constexpr int kBlockThreads = 256;  // threads per row-resident / split-row workgroup
 
@@ -21,7 +30,17 @@ enum KFlags {
     F_RECOMPUTE = 16,          // norm backward: recompute mean/rstd from x
     F_TEST_DROP_PUBLISH = 32,  // test only: member 1 never publishes
     F_ALIGNP = 64,             // gamma / beta 16-byte aligned
+    F_ALIGNO1 = 128,           // rows of out1 start 16-byte aligned
 };
+
+// Statistics exchanged per stage (slot stride of the exchange workspace).
+constexpr int q_of(int op) {
+    return op == OP_PEARSON_BWD ? 5 : (op == OP_SMXL_BWD || op == OP_WVAR_BWD) ? 3 : 2;
+}
+// Operators with two resident input tensors / two output tensors.
+constexpr bool two_in(int op) { return (op >= OP_SOFTMAX_BWD && op <= OP_SMXL_BWD) || op >= OP_PEARSON_BWD; }
+constexpr bool two_out(int op) { return op >= OP_PEARSON_BWD; }
+constexpr bool is_quant(int op) { return op == OP_QUANT_I8 || op == OP_QUANT_F8; }
 
 // Register-resident slice sizes: vectors (16 bytes) per thread per tensor.
 constexpr int kVpts[] = {1, 2, 4, 8, 12, 16, 24, 32};
@@ -30,17 +49,19 @@ constexpr int kNumVpts = 8;
 // register file (data of one or two tensors, plus FP32 dgamma/dbeta column
 // partials for normalisation backward).
 constexpr int max_vpt(int op, int dt) {
-    return op <= OP_RMS_FWD ? (dt == DT_FP8 ? 16 : 32)
-         : op == OP_SOFTMAX_BWD ? 16
+    return (op <= OP_RMS_FWD || op == OP_QUANT_I8 || op == OP_QUANT_F8) ? (dt == DT_FP8 ? 16 : 32)
+         : (op == OP_SOFTMAX_BWD || op == OP_SMXL_BWD || op == OP_PEARSON_BWD || op == OP_WVAR_BWD) ? 16
          : op == OP_LN_BWD ? (dt == DT_F32 ? 8 : dt == DT_BF16 ? 4 : 2)
          : (dt == DT_F32 ? 8 : dt == DT_BF16 ? 8 : 4);
 }
 
 struct RowArgs {
     const void *in0;   // x (forward, norm backward) or y (softmax backward)
-    const void *in1;   // dy (backward)
-    void *out;         // y (forward) or dx (backward)
-    int64_t ld0, ld1, ldo;
+    const void *in1;   // dy (backward); y (Pearson); w (weighted variance)
+    void *out;         // y (forward), dx (backward) or the codes (quantisation)
+    void *out1;        // second output: dy (Pearson), dw (weighted variance)
+    int64_t ld0, ld1, ldo, ldo1;
+    const float *rowg; // per-row upstream gradient dr / dv (Pearson, weighted variance)
     const float *s0, *s1;  // FP8 per-row input scales
     float *so;             // FP8 per-row output scales
     const float *gamma, *beta;
@@ -49,10 +70,10 @@ struct RowArgs {
     float *colpart;                  // [groups][ncp][N] dgamma/dbeta partials
     unsigned long long *slots;       // split-row exchange slots
     unsigned *errflag;               // exchange-timeout flag (holds the epoch)
-    const void *safe;                // 16 readable bytes (target of masked-off vector loads)
     int64_t M, N;
     int64_t chunk;     // elements per slice (multiple of the vector width)
     int k;             // split factor
+    int qs;            // slot stride: statistics per stage of this operator
     int groups;        // concurrent row groups = grid / k
     unsigned epoch;    // exchange epoch of this launch (never 0)
     unsigned spin_limit;

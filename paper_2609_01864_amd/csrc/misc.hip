@@ -107,21 +107,13 @@ __global__ __launch_bounds__(256) void k_fill(unsigned *p, int64_t nwords, unsig
 const void *fill_kernel() { return (const void *)&k_fill; }
 
 // Streaming copy used to calibrate the achievable read+write bandwidth and the
-// hardware traffic counters: 4 independent 128-bit loads in flight per thread.
+// hardware traffic counters.
 __global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        u32x4 a = __builtin_nontemporal_load(src + i);
-        u32x4 b = __builtin_nontemporal_load(src + i + stride);
-        u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
-        u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
-        __builtin_nontemporal_store(a, dst + i);
-        __builtin_nontemporal_store(b, dst + i + stride);
-        __builtin_nontemporal_store(c, dst + i + 2 * stride);
-        __builtin_nontemporal_store(d, dst + i + 3 * stride);
-    }
-    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    // one 16-byte vector per work-item over a grid that covers the buffer:
+    // the hardware dispatcher streams workgroups through the CUs, which
+    // measured faster than any grid-stride or multi-vector form
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 const void *copy_kernel() { return (const void *)&k_copy; }
 

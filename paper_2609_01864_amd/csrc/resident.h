@@ -27,7 +27,9 @@
 namespace credit {
 
 template <int OP> struct OpTraits {
-    static constexpr bool TWO = OP >= OP_SOFTMAX_BWD;  // two resident input tensors
+    static constexpr bool TWO = two_in(OP);    // two resident input tensors
+    static constexpr bool TWOO = two_out(OP);  // two output tensors
+    static constexpr bool QUANT = is_quant(OP);  // one-byte codes out
     static constexpr int NCP = OP == OP_LN_BWD ? 2 : (OP == OP_RMS_BWD ? 1 : 0);  // column partials
 };
 
@@ -37,6 +39,7 @@ template <int OP> struct OpTraits {
 template <int OP, int DT, int VPT> constexpr int resident_waves() {
     constexpr int data = VPT * 4 * (OpTraits<OP>::TWO ? 2 : 1) + OpTraits<OP>::NCP * VPT * Io<DT>::EPV;
     constexpr int work = 64 + (DT == DT_FP8 ? 32 : 0) + (OP == OP_SOFTMAX_FWD || OP == OP_SOFTMAX_BWD ? 0 : 16);
+    static_assert(OP < OP_COUNT, "operator");
     constexpr int w = 512 / (data + work);
     return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
@@ -50,6 +53,9 @@ template <int OP, int DT, int VPT> constexpr int resident_waves() {
 typedef u32x4 u32x4_u __attribute__((aligned(1)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef f32x4 f32x4_u __attribute__((aligned(1)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef u32x2 u32x2_u __attribute__((aligned(1)));
+typedef unsigned u32_u __attribute__((aligned(1)));
 
 template <bool AL> __device__ __forceinline__ u32x4 vload_nt(const char *base, uint32_t off) {
     if constexpr (AL)
@@ -62,6 +68,22 @@ template <bool AL> __device__ __forceinline__ void vstore_nt(char *base, uint32_
         __builtin_nontemporal_store(v, (u32x4 *)(base + off));
     else
         __builtin_nontemporal_store(v, (u32x4_u *)(base + off));
+}
+
+// NB (4, 8 or 16) bytes of quantisation codes at base + off.
+template <int NB, bool AL> __device__ __forceinline__ void bstore_nt(char *base, uint32_t off, const unsigned *w) {
+    char *p = base + off;
+    if constexpr (NB == 4) {
+        if constexpr (AL) __builtin_nontemporal_store(w[0], (unsigned *)p);
+        else __builtin_nontemporal_store(w[0], (u32_u *)p);
+    } else if constexpr (NB == 8) {
+        u32x2 v = {w[0], w[1]};
+        if constexpr (AL) __builtin_nontemporal_store(v, (u32x2 *)p);
+        else __builtin_nontemporal_store(v, (u32x2_u *)p);
+    } else {
+        u32x4 v = {w[0], w[1], w[2], w[3]};
+        vstore_nt<AL>(base, off, v);
+    }
 }
 
 // EPV FP32 parameters (gamma / beta) of one vector slot.
@@ -127,6 +149,27 @@ __device__ __forceinline__ void row_reduce_chan(float (&v)[3], const RowArgs &a,
     }
 }
 
+// Bivariate co-moments (n, mean_x, mean_y, Cxx, Cyy, Cxy) over the workgroup
+// and the row group; the exchange carries the five moments, each member's
+// count follows from its slice.
+__device__ __forceinline__ void row_reduce_co(float (&v)[6], const RowArgs &a, int64_t row, int stage, int c,
+                                              float *red, float *xb, int &parity) {
+    block_reduce<4, 6>(v, MergeCo(), red, parity);
+    if (a.k > 1) {
+        float mine[5] = {v[1], v[2], v[3], v[4], v[5]};
+        exchange<5>(a, row, stage, c, mine, xb);
+        float t[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int m = 0; m < a.k; ++m) {
+            int64_t lo = (int64_t)m * a.chunk;
+            int64_t cnt = a.N - lo < a.chunk ? a.N - lo : a.chunk;
+            const float *p = xb + 5 * m;
+            co_merge(t, cnt > 0 ? (float)cnt : 0.f, p[0], p[1], p[2], p[3], p[4]);
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[i] = t[i];
+    }
+}
+
 // Geometry of a workgroup's slice.
 struct Slice {
     int64_t c0;    // first column
@@ -140,6 +183,7 @@ template <int OP, int DT, int VPT, bool AL, bool FULLS>
 __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const Slice &sl, float *red, float *xb) {
     using T = OpTraits<OP>;
     constexpr int EPV = Io<DT>::EPV, B = Io<DT>::BYTES, NCP = T::NCP;
+    constexpr int OB = T::QUANT ? 1 : B;  // output element bytes
     constexpr bool FP8 = DT == DT_FP8;
     // slots per batch of parameter loads: 16 FP32 parameter registers in flight
     constexpr int GBW = 16 / EPV / (OP == OP_LN_FWD ? 2 : 1);
@@ -176,17 +220,21 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
     for (int64_t row = grp; row < a.M; row += a.groups) {
         const char *r0 = (const char *)a.in0 + row * a.ld0 * B;
         const char *r1 = T::TWO ? (const char *)a.in1 + row * a.ld1 * B : nullptr;
-        char *orow = (char *)a.out + row * a.ldo * B;
+        char *orow = (char *)a.out + row * a.ldo * OB;
+        char *orow1 = T::TWOO ? (char *)a.out1 + row * a.ldo1 * B : nullptr;
         const bool writer = c == 0 && tid == 0;
         // Uniform bases of this row's slice and per-thread byte offsets that are
         // made opaque each row, so slot addresses are formed next to their use
         // instead of being hoisted out of the row loop as 64-bit registers.
         const char *b0 = r0 + sl.c0 * B;
         const char *b1 = T::TWO ? r1 + sl.c0 * B : nullptr;
-        char *bo = orow + sl.c0 * B;
+        char *bo = orow + sl.c0 * OB;
+        char *bo1 = T::TWOO ? orow1 + sl.c0 * B : nullptr;
         uint32_t toff = (uint32_t)tid * 16u, poff = (uint32_t)tid * (EPV * 4u);
         asm volatile("" : "+v"(toff));
         asm volatile("" : "+v"(poff));
+        uint32_t qoff = (uint32_t)tid * (uint32_t)EPV;  // codes: EPV bytes per slot
+        if constexpr (T::QUANT) asm volatile("" : "+v"(qoff));
         // masked slots re-read the slice's first vector (only when nfv >= 1);
         // their data is zeroed before use and their stores are skipped
         auto doff = [&](int j) -> uint32_t {
@@ -197,6 +245,12 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
         };
         auto ST = [&](int j, u32x4 v) {
             if (FULLS || ok_of(j)) vstore_nt<AL>(bo, toff + (uint32_t)j * (kBlock * 16u), v);
+        };
+        auto ST1 = [&](int j, u32x4 v) {
+            if (FULLS || ok_of(j)) vstore_nt<AL>(bo1, toff + (uint32_t)j * (kBlock * 16u), v);
+        };
+        auto QST = [&](int j, const unsigned *w) {
+            if (FULLS || ok_of(j)) bstore_nt<EPV, AL>(bo, qoff + (uint32_t)j * (uint32_t)(kBlock * EPV), w);
         };
         auto PAR = [&](const float *p, int j, float *out) { load_params_v<DT, AL>(p + sl.c0, pofs(j), out); };
         u32x4 d0[VPT];
@@ -514,7 +568,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 h(t0, t1, dx);
                 store_vec<DT>(orow, tcol, tn, false, encode<DT>(dx, oinv));
             }
-        } else {  // OP_LN_BWD, OP_RMS_BWD
+        } else if constexpr (OP == OP_LN_BWD || OP == OP_RMS_BWD) {
             constexpr bool LN = OP == OP_LN_BWD;
             const float xs = FP8 ? a.s0[row] : 1.f, gs = FP8 ? a.s1[row] : 1.f;
             float mean = 0.f, rstd;
@@ -694,6 +748,287 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             }
             float unused = 0.f;
             out_pass(true, oinv, unused);
+        } else if constexpr (OP == OP_SMXL_BWD) {
+            // Softmax backward from the logits: y = softmax(x) is rebuilt from the
+            // resident x.  One stage carries (c, s, t): c = max of x*log2(e),
+            // s = sum 2^(xK - c), t = sum dy 2^(xK - c), so sum dy*y = t / s.
+            const float K = (FP8 ? a.s0[row] : 1.f) * kLog2e;
+            const float gs = FP8 ? a.s1[row] : 1.f;
+            float qmax = -INFINITY;
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float q[EPV];
+                decode<DT>(d0[j], q, 1.f);
+                const bool ok = ok_of(j);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) qmax = fmaxf(qmax, ok ? q[i] : -INFINITY);
+            }
+            if (tail) {
+                float q[EPV];
+                decode<DT>(t0, q, 1.f);
+                for (int i = 0; i < tn; ++i) qmax = fmaxf(qmax, q[i]);
+            }
+            float st[3] = {qmax == -INFINITY ? -INFINITY : qmax * K, 0.f, 0.f};
+            const float ct = qmax == -INFINITY ? 0.f : st[0];
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float q[EPV], g[EPV];
+                decode<DT>(d0[j], q, 1.f);
+                decode<DT>(d1[j], g, gs);
+                const bool ok = ok_of(j);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    const float e = ok ? fast_exp2(fmaf(q[i], K, -ct)) : 0.f;
+                    st[1] += e;
+                    st[2] = fmaf(e, g[i], st[2]);
+                }
+            }
+            if (tail) {
+                float q[EPV], g[EPV];
+                decode<DT>(t0, q, 1.f);
+                decode<DT>(t1, g, gs);
+                for (int i = 0; i < tn; ++i) {
+                    const float e = fast_exp2(fmaf(q[i], K, -ct));
+                    st[1] += e;
+                    st[2] = fmaf(e, g[i], st[2]);
+                }
+            }
+            row_reduce<3>(st, MergeSoftmax3(), a, row, 0, c, red, xb, parity);
+            const float cmax = st[0], inv_s = 1.f / st[1];
+            const float cdot = st[2] * inv_s;
+            auto h = [&](u32x4 xv, u32x4 gv, float *dx) {
+                float q[EPV], g[EPV];
+                decode<DT>(xv, q, 1.f);
+                decode<DT>(gv, g, gs);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) dx[i] = fast_exp2(fmaf(q[i], K, -cmax)) * inv_s * (g[i] - cdot);
+            };
+            float oinv = 1.f;
+            if constexpr (FP8) {
+                float am[1] = {0.f};
+                fresh();
+#pragma unroll
+                for (int j = 0; j < VPT; ++j) {
+                    float dx[EPV];
+                    h(d0[j], d1[j], dx);
+                    const bool ok = ok_of(j);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) am[0] = fmaxf(am[0], ok ? fabsf(dx[i]) : 0.f);
+                }
+                if (tail) {
+                    float dx[EPV];
+                    h(t0, t1, dx);
+                    for (int i = 0; i < tn; ++i) am[0] = fmaxf(am[0], fabsf(dx[i]));
+                }
+                row_reduce<1>(am, MergeMax(), a, row, 1, c, red, xb, parity);
+                oinv = am[0] > 0.f ? kFp8Max / am[0] : 1.f;
+                if (writer) a.so[row] = am[0] > 0.f ? am[0] / kFp8Max : 1.f;
+            }
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float dx[EPV];
+                h(d0[j], d1[j], dx);
+                ST(j, encode<DT>(dx, oinv));
+            }
+            if (tail) {
+                float dx[EPV];
+                h(t0, t1, dx);
+                store_vec<DT>(orow, tcol, tn, false, encode<DT>(dx, oinv));
+            }
+        } else if constexpr (T::QUANT) {
+            // Row-wise quantisation: amax stage, then codes RNE(x * qmax / amax)
+            // with the row scale amax / qmax (1 for an all-zero row).
+            constexpr bool I8 = OP == OP_QUANT_I8;
+            float am[1] = {0.f};
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float q[EPV];
+                decode<DT>(d0[j], q, 1.f);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) am[0] = fmaxf(am[0], fabsf(q[i]));  // masked slots are 0
+            }
+            if (tail) {
+                float q[EPV];
+                decode<DT>(t0, q, 1.f);
+                for (int i = 0; i < tn; ++i) am[0] = fmaxf(am[0], fabsf(q[i]));
+            }
+            row_reduce<1>(am, MergeMax(), a, row, 0, c, red, xb, parity);
+            const float qm = I8 ? 127.f : kFp8Max;
+            const float inv = am[0] > 0.f ? qm / am[0] : 1.f;
+            if (writer) a.so[row] = am[0] > 0.f ? am[0] / qm : 1.f;
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float q[EPV];
+                decode<DT>(d0[j], q, 1.f);
+                unsigned w[EPV / 4];
+                quant_codes<I8, EPV>(q, inv, w);
+                QST(j, w);
+            }
+            if (tail) {
+                float q[EPV];
+                decode<DT>(t0, q, 1.f);
+                unsigned w[EPV / 4];
+                quant_codes<I8, EPV>(q, inv, w);
+                for (int i = 0; i < tn; ++i) orow[tcol + i] = (char)((w[i / 4] >> (8 * (i % 4))) & 0xffu);
+            }
+        } else if constexpr (OP == OP_PEARSON_BWD) {
+            // Pearson correlation r of the rows x and y: one stage of bivariate
+            // co-moments (one pass of sums about a per-thread shift), then
+            // dx = dr (yc / sqrt(Cxx Cyy) - r xc / Cxx) and symmetrically dy.
+            float Kx = 0.f, Ky = 0.f;
+            {
+                float x[EPV], y[EPV], xt[EPV], yt[EPV];
+                decode<DT>(d0[0], x, 1.f);
+                decode<DT>(d1[0], y, 1.f);
+                decode<DT>(t0, xt, 1.f);
+                decode<DT>(t1, yt, 1.f);
+                const bool first = FULLS || ok_of(0);
+                Kx = first ? x[0] : (tail ? xt[0] : 0.f);
+                Ky = first ? y[0] : (tail ? yt[0] : 0.f);
+            }
+            float sx = 0.f, sy = 0.f, sxx = 0.f, syy = 0.f, sxy = 0.f;
+            auto acc = [&](const float *x, const float *y, int n, bool ok) {
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    const bool v = ok && i < n;
+                    const float dx = v ? x[i] - Kx : 0.f, dy = v ? y[i] - Ky : 0.f;
+                    sx += dx;
+                    sy += dy;
+                    sxx = fmaf(dx, dx, sxx);
+                    syy = fmaf(dy, dy, syy);
+                    sxy = fmaf(dx, dy, sxy);
+                }
+            };
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float x[EPV], y[EPV];
+                decode<DT>(d0[j], x, 1.f);
+                decode<DT>(d1[j], y, 1.f);
+                acc(x, y, EPV, ok_of(j));
+            }
+            if (tail) {
+                float x[EPV], y[EPV];
+                decode<DT>(t0, x, 1.f);
+                decode<DT>(t1, y, 1.f);
+                acc(x, y, tn, true);
+            }
+            float st[6] = {held, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (held > 0.f) {
+                const float mx = sx / held, my = sy / held;
+                st[1] = Kx + mx;
+                st[2] = Ky + my;
+                st[3] = fmaxf(sxx - sx * mx, 0.f);
+                st[4] = fmaxf(syy - sy * my, 0.f);
+                st[5] = sxy - sx * my;
+            }
+            row_reduce_co(st, a, row, 0, c, red, xb, parity);
+            const float mx = st[1], my = st[2];
+            const float ix = rsqrtf(st[3]), iy = rsqrtf(st[4]);
+            const float dr = a.rowg[row];
+            const float r = st[5] * ix * iy;
+            const float ca = dr * ix * iy, cbx = dr * r / st[3], cby = dr * r / st[4];
+            auto h = [&](u32x4 xv, u32x4 yv, float *gx, float *gy) {
+                float x[EPV], y[EPV];
+                decode<DT>(xv, x, 1.f);
+                decode<DT>(yv, y, 1.f);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    const float xc = x[i] - mx, yc = y[i] - my;
+                    gx[i] = fmaf(ca, yc, -cbx * xc);
+                    gy[i] = fmaf(ca, xc, -cby * yc);
+                }
+            };
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float gx[EPV], gy[EPV];
+                h(d0[j], d1[j], gx, gy);
+                ST(j, encode<DT>(gx, 1.f));
+                ST1(j, encode<DT>(gy, 1.f));
+            }
+            if (tail) {
+                float gx[EPV], gy[EPV];
+                h(t0, t1, gx, gy);
+                store_vec<DT>(orow, tcol, tn, false, encode<DT>(gx, 1.f));
+                store_vec<DT>(orow1, tcol, tn, false, encode<DT>(gy, 1.f));
+            }
+        } else if constexpr (OP == OP_WVAR_BWD) {
+            // Weighted variance v = sum w (x - mu)^2 / W, mu = sum w x / W,
+            // W = sum w: one stage of weighted (W, mean, M2) (one pass of sums
+            // about a per-thread shift, Chan-merged with W as the count), then
+            // dx = dv 2 w (x - mu) / W and dw = dv ((x - mu)^2 - v) / W.
+            float K = 0.f;
+            {
+                float x[EPV], xt[EPV];
+                decode<DT>(d0[0], x, 1.f);
+                decode<DT>(t0, xt, 1.f);
+                K = (FULLS || ok_of(0)) ? x[0] : (tail ? xt[0] : 0.f);
+            }
+            float sw = 0.f, swd = 0.f, swdd = 0.f;
+            auto acc = [&](const float *x, const float *w, int n) {
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    const float wi = i < n ? w[i] : 0.f;  // masked slots hold w = 0
+                    const float d = x[i] - K, wd = wi * d;
+                    sw += wi;
+                    swd += wd;
+                    swdd = fmaf(wd, d, swdd);
+                }
+            };
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float x[EPV], w[EPV];
+                decode<DT>(d0[j], x, 1.f);
+                decode<DT>(d1[j], w, 1.f);
+                acc(x, w, EPV);
+            }
+            if (tail) {
+                float x[EPV], w[EPV];
+                decode<DT>(t0, x, 1.f);
+                decode<DT>(t1, w, 1.f);
+                acc(x, w, tn);
+            }
+            float st[3] = {sw, 0.f, 0.f};
+            if (sw != 0.f) {
+                const float m = swd / sw;
+                st[1] = K + m;
+                st[2] = fmaxf(swdd - swd * m, 0.f);
+            }
+            row_reduce<3>(st, MergeChan(), a, row, 0, c, red, xb, parity);
+            const float W = st[0], mu = st[1], var = st[2] / W;
+            const float f = a.rowg[row] / W, f2 = 2.f * f;
+            auto h = [&](u32x4 xv, u32x4 wv, float *gx, float *gw) {
+                float x[EPV], w[EPV];
+                decode<DT>(xv, x, 1.f);
+                decode<DT>(wv, w, 1.f);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    const float d = x[i] - mu;
+                    gx[i] = f2 * w[i] * d;
+                    gw[i] = f * fmaf(d, d, -var);
+                }
+            };
+            fresh();
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                float gx[EPV], gw[EPV];
+                h(d0[j], d1[j], gx, gw);
+                ST(j, encode<DT>(gx, 1.f));
+                ST1(j, encode<DT>(gw, 1.f));
+            }
+            if (tail) {
+                float gx[EPV], gw[EPV];
+                h(t0, t1, gx, gw);
+                store_vec<DT>(orow, tcol, tn, false, encode<DT>(gx, 1.f));
+                store_vec<DT>(orow1, tcol, tn, false, encode<DT>(gw, 1.f));
+            }
         }
     }
 
@@ -717,7 +1052,7 @@ template <int OP, int DT, int VPT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(resident_waves<OP, DT, VPT>())))
 void k_resident(RowArgs a) {
     constexpr int EPV = Io<DT>::EPV;
-    __shared__ float red[2 * 4 * 3];
+    __shared__ float red[2 * 4 * 6];  // up to six statistics per reduction
     __shared__ float xb[kMaxK * kMaxQ];
     int c, grp;
     member_of(a, blockIdx.x, c, grp);
@@ -728,7 +1063,8 @@ void k_resident(RowArgs a) {
     sl.nfv = sl.nval / EPV;
     sl.tail_n = (int)(sl.nval - sl.nfv * EPV);
     sl.owner = (int)(sl.nfv % kBlock);
-    constexpr int AL_ALL = F_ALIGN0 | F_ALIGNO | F_ALIGNP | (OpTraits<OP>::TWO ? F_ALIGN1 : 0);
+    constexpr int AL_ALL = F_ALIGN0 | F_ALIGNO | F_ALIGNP | (OpTraits<OP>::TWO ? F_ALIGN1 : 0) |
+                           (OpTraits<OP>::TWOO ? F_ALIGNO1 : 0);
     const bool al = (a.flags & AL_ALL) == AL_ALL;
     if (al && sl.nval == (int64_t)VPT * kBlock * EPV)
         row_loop<OP, DT, VPT, true, true>(a, c, grp, sl, red, xb);

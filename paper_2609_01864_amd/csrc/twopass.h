@@ -75,12 +75,31 @@ __device__ __forceinline__ void row_store(char *row, int64_t v, int nv, u32x4 x)
         store_vec<DT>(row, v * EPV, nv, false, x);
 }
 
+// Stores the EPV one-byte codes of vector v of a row (nv valid).
+template <int EPV>
+__device__ __forceinline__ void code_store(char *row, int64_t v, int nv, const unsigned *w) {
+    char *p = row + v * EPV;
+    if (nv == EPV) {
+        if constexpr (EPV == 4) {
+            __builtin_nontemporal_store(w[0], (u32_u *)p);
+        } else if constexpr (EPV == 8) {
+            u32x2 x = {w[0], w[1]};
+            __builtin_nontemporal_store(x, (u32x2_u *)p);
+        } else {
+            u32x4 x = {w[0], w[1], w[2], w[3]};
+            __builtin_nontemporal_store(x, (u32x4_u *)p);
+        }
+        return;
+    }
+    for (int i = 0; i < nv; ++i) p[i] = (char)((w[i / 4] >> (8 * (i % 4))) & 0xffu);
+}
+
 template <int OP, int DT, int BLOCK, int U>
 __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
     constexpr int EPV = Io<DT>::EPV, B = Io<DT>::BYTES, NW = BLOCK / 64;
     constexpr bool FP8 = DT == DT_FP8;
     constexpr bool TWO = OpTraits<OP>::TWO;
-    __shared__ float red[2 * NW * 3];
+    __shared__ float red[2 * NW * 6];  // up to six statistics per reduction
     int parity = 0;
     const int64_t N = a.N;
     const float invN = 1.f / (float)N;
@@ -90,7 +109,8 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
     for (int64_t row = blockIdx.x; row < a.M; row += gridDim.x) {
         const char *r0 = (const char *)a.in0 + row * a.ld0 * B;
         const char *r1 = TWO ? (const char *)a.in1 + row * a.ld1 * B : nullptr;
-        char *orow = (char *)a.out + row * a.ldo * B;
+        char *orow = (char *)a.out + row * a.ldo * (is_quant(OP) ? 1 : B);
+        char *orow1 = two_out(OP) ? (char *)a.out1 + row * a.ldo1 * B : nullptr;
         const bool writer = threadIdx.x == 0;
 
         if constexpr (OP == OP_SOFTMAX_FWD) {
@@ -235,7 +255,7 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
                 apply(v, d0v, d1v, nv, y);
                 row_store<DT>(orow, v, nv, encode<DT>(y, oinv));
             });
-        } else {  // OP_SOFTMAX_BWD
+        } else if constexpr (OP == OP_SOFTMAX_BWD) {
             const float ys = FP8 ? a.s0[row] : 1.f, gs = FP8 ? a.s1[row] : 1.f;
             float st[1] = {0.f};
             stream_row<DT, BLOCK, U, false>(r0, r1, N, al0, al1, [&](int64_t, u32x4 yv, u32x4 gv, int) {
@@ -269,6 +289,174 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
 #pragma unroll
                 for (int i = 0; i < EPV; ++i) dx[i] = y[i] * (g[i] - cs);
                 row_store<DT>(orow, v, nv, encode<DT>(dx, oinv));
+            });
+        } else if constexpr (OP == OP_SMXL_BWD) {
+            // pass 1 streams x and dy with online (c, s, t); the output pass
+            // streams them again
+            const float K = (FP8 ? a.s0[row] : 1.f) * kLog2e, gs = FP8 ? a.s1[row] : 1.f;
+            float st[3] = {-INFINITY, 0.f, 0.f};
+            stream_row<DT, BLOCK, U, false>(r0, r1, N, al0, al1, [&](int64_t, u32x4 xv, u32x4 gv, int nv) {
+                float q[EPV], g[EPV];
+                decode<DT>(xv, q, 1.f);
+                decode<DT>(gv, g, gs);
+                float bm = -INFINITY;
+#pragma unroll
+                for (int i = 0; i < EPV; ++i)
+                    if (i < nv) bm = fmaxf(bm, q[i]);
+                if (bm == -INFINITY) return;
+                const float cb = bm * K;
+                if (cb > st[0]) {
+                    const float f = st[0] == -INFINITY ? 0.f : fast_exp2(st[0] - cb);
+                    st[1] *= f;
+                    st[2] *= f;
+                    st[0] = cb;
+                }
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    if (i < nv) {
+                        const float e = fast_exp2(fmaf(q[i], K, -st[0]));
+                        st[1] += e;
+                        st[2] = fmaf(e, g[i], st[2]);
+                    }
+                }
+            });
+            block_reduce<NW, 3>(st, MergeSoftmax3(), red, parity);
+            const float cmax = st[0], inv_s = 1.f / st[1], cdot = st[2] * inv_s;
+            auto h = [&](u32x4 xv, u32x4 gv, float *dx) {
+                float q[EPV], g[EPV];
+                decode<DT>(xv, q, 1.f);
+                decode<DT>(gv, g, gs);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) dx[i] = fast_exp2(fmaf(q[i], K, -cmax)) * inv_s * (g[i] - cdot);
+            };
+            float oinv = 1.f;
+            if constexpr (FP8) {
+                float am[1] = {0.f};
+                stream_row<DT, BLOCK, U, false>(r0, r1, N, al0, al1, [&](int64_t, u32x4 xv, u32x4 gv, int nv) {
+                    float dx[EPV];
+                    h(xv, gv, dx);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i)
+                        if (i < nv) am[0] = fmaxf(am[0], fabsf(dx[i]));
+                });
+                block_reduce<NW, 1>(am, MergeMax(), red, parity);
+                oinv = am[0] > 0.f ? kFp8Max / am[0] : 1.f;
+                if (writer) a.so[row] = am[0] > 0.f ? am[0] / kFp8Max : 1.f;
+            }
+            stream_row<DT, BLOCK, U, true>(r0, r1, N, al0, al1, [&](int64_t v, u32x4 xv, u32x4 gv, int nv) {
+                if (nv == 0) return;
+                float dx[EPV];
+                h(xv, gv, dx);
+                row_store<DT>(orow, v, nv, encode<DT>(dx, oinv));
+            });
+        } else if constexpr (is_quant(OP)) {
+            constexpr bool I8 = OP == OP_QUANT_I8;
+            float am[1] = {0.f};
+            stream_row<DT, BLOCK, U, false>(r0, nullptr, N, al0, al1, [&](int64_t, u32x4 xv, u32x4, int) {
+                float q[EPV];
+                decode<DT>(xv, q, 1.f);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) am[0] = fmaxf(am[0], fabsf(q[i]));  // invalid elements read 0
+            });
+            block_reduce<NW, 1>(am, MergeMax(), red, parity);
+            const float qm = I8 ? 127.f : kFp8Max;
+            const float inv = am[0] > 0.f ? qm / am[0] : 1.f;
+            if (writer) a.so[row] = am[0] > 0.f ? am[0] / qm : 1.f;
+            stream_row<DT, BLOCK, U, true>(r0, nullptr, N, al0, al1, [&](int64_t v, u32x4 xv, u32x4, int nv) {
+                if (nv == 0) return;
+                float q[EPV];
+                decode<DT>(xv, q, 1.f);
+                unsigned w[EPV / 4];
+                quant_codes<I8, EPV>(q, inv, w);
+                code_store<EPV>(orow, v, nv, w);
+            });
+        } else if constexpr (OP == OP_PEARSON_BWD) {
+            // pass 1: exact per-vector co-moments, merged pairwise
+            float st[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            stream_row<DT, BLOCK, U, false>(r0, r1, N, al0, al1, [&](int64_t, u32x4 xv, u32x4 yv, int nv) {
+                if (nv == 0) return;
+                float x[EPV], y[EPV];
+                decode<DT>(xv, x, 1.f);
+                decode<DT>(yv, y, 1.f);
+                float sx = 0.f, sy = 0.f;
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    sx += x[i];
+                    sy += y[i];
+                }
+                const float n = (float)nv, mx = sx / n, my = sy / n;
+                float cxx = 0.f, cyy = 0.f, cxy = 0.f;
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    if (i < nv) {
+                        const float dx = x[i] - mx, dy = y[i] - my;
+                        cxx = fmaf(dx, dx, cxx);
+                        cyy = fmaf(dy, dy, cyy);
+                        cxy = fmaf(dx, dy, cxy);
+                    }
+                }
+                co_merge(st, n, mx, my, cxx, cyy, cxy);
+            });
+            block_reduce<NW, 6>(st, MergeCo(), red, parity);
+            const float mx = st[1], my = st[2];
+            const float ix = rsqrtf(st[3]), iy = rsqrtf(st[4]);
+            const float dr = a.rowg[row];
+            const float r = st[5] * ix * iy;
+            const float ca = dr * ix * iy, cbx = dr * r / st[3], cby = dr * r / st[4];
+            stream_row<DT, BLOCK, U, true>(r0, r1, N, al0, al1, [&](int64_t v, u32x4 xv, u32x4 yv, int nv) {
+                if (nv == 0) return;
+                float x[EPV], y[EPV], gx[EPV], gy[EPV];
+                decode<DT>(xv, x, 1.f);
+                decode<DT>(yv, y, 1.f);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    const float xc = x[i] - mx, yc = y[i] - my;
+                    gx[i] = fmaf(ca, yc, -cbx * xc);
+                    gy[i] = fmaf(ca, xc, -cby * yc);
+                }
+                row_store<DT>(orow, v, nv, encode<DT>(gx, 1.f));
+                row_store<DT>(orow1, v, nv, encode<DT>(gy, 1.f));
+            });
+        } else if constexpr (OP == OP_WVAR_BWD) {
+            // pass 1: exact per-vector weighted (W, mean, M2), Chan-merged
+            float st[3] = {0.f, 0.f, 0.f};
+            stream_row<DT, BLOCK, U, false>(r0, r1, N, al0, al1, [&](int64_t, u32x4 xv, u32x4 wv, int nv) {
+                if (nv == 0) return;
+                float x[EPV], w[EPV];
+                decode<DT>(xv, x, 1.f);
+                decode<DT>(wv, w, 1.f);
+                float sw = 0.f, swx = 0.f;
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    sw += w[i];
+                    swx = fmaf(w[i], x[i], swx);
+                }
+                if (sw == 0.f) return;
+                const float m = swx / sw;
+                float m2 = 0.f;
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    const float d = x[i] - m;
+                    m2 = fmaf(w[i] * d, d, m2);
+                }
+                chan_merge(st[0], st[1], st[2], sw, m, m2);
+            });
+            block_reduce<NW, 3>(st, MergeChan(), red, parity);
+            const float W = st[0], mu = st[1], var = st[2] / W;
+            const float f = a.rowg[row] / W, f2 = 2.f * f;
+            stream_row<DT, BLOCK, U, true>(r0, r1, N, al0, al1, [&](int64_t v, u32x4 xv, u32x4 wv, int nv) {
+                if (nv == 0) return;
+                float x[EPV], w[EPV], gx[EPV], gw[EPV];
+                decode<DT>(xv, x, 1.f);
+                decode<DT>(wv, w, 1.f);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) {
+                    const float d = x[i] - mu;
+                    gx[i] = f2 * w[i] * d;
+                    gw[i] = f * fmaf(d, d, -var);
+                }
+                row_store<DT>(orow, v, nv, encode<DT>(gx, 1.f));
+                row_store<DT>(orow1, v, nv, encode<DT>(gw, 1.f));
             });
         }
     }

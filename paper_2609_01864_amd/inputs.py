@@ -16,6 +16,10 @@ Distributions follow the synthetic FP32 shapes of the paper's evaluation
 * ``outlier_rows``   x = 3 * N(0, 1) with round(0.01 N) positions per row set to +-40
 * ``normal_rows``    N(mean, std), e.g. upstream gradients dy ~ N(0, 1)
 * ``norm_params``    gamma ~ U(0.5, 1.5), beta ~ N(0, 0.1)
+* ``correlated_rows`` (x, y) with x, z ~ N(0, 1) and y = 0.6 x + 0.8 z, so the
+                      per-row Pearson correlation is about 0.6
+* ``uniform_rows``   U(lo, hi), e.g. the weights of the weighted variance
+* ``row_vector``     one N(0, 1) value per row (upstream gradients dr, dv)
 """
 from __future__ import annotations
 
@@ -74,6 +78,20 @@ def outlier_rows(M: int, N: int, seed: int, tensor: int = 0, rows=None, frac: fl
         return v
 
     return _fill_rows(M, N, rows, row)
+
+
+def correlated_rows(M: int, N: int, seed: int, rho: float = 0.6, rows=None):
+    x = normal_rows(M, N, seed, 0, rows=rows)
+    z = normal_rows(M, N, seed, 1, rows=rows)
+    return x, rho * x + np.sqrt(1.0 - rho * rho) * z
+
+
+def uniform_rows(M: int, N: int, seed: int, tensor: int, lo: float = 0.0, hi: float = 1.0, rows=None):
+    return _fill_rows(M, N, rows, lambda r: _rng(seed, tensor, r).uniform(lo, hi, N))
+
+
+def row_vector(M: int, seed: int, tensor: int = 200):
+    return np.random.default_rng([int(seed), int(tensor)]).standard_normal(M).astype(np.float32)
 
 
 def norm_params(N: int, seed: int, tensor: int = 100):
