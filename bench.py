@@ -126,6 +126,77 @@ def forms(C, h):
     return out
 
 
+SUITE = (("layernorm_bwd", "LAYERNORM", "BWD", 2048), ("wvar_bwd", "WVAR", "BWD", 4096),
+         ("pearson_bwd", "PEARSON", "BWD", 4096), ("softmax_logits_bwd", "SOFTMAX_LOGITS", "BWD", 4096),
+         ("quant_int8", "QUANT_INT8", "FWD", 4096))
+SUITE_N = (4096, 8192, 16384, 32768, 65536)
+
+
+def suite(C, h, copy_gbps):
+    """The paper's evaluation suite on this GPU (Sec. IV-A: FP32 input, M =
+    2048 for LayerNorm and 4096 otherwise, N in 4K..64K; LayerNorm backward
+    with saved statistics here): cold-cache times of every legal plan, the
+    speedup of the best split-row plan over the best single-workgroup
+    baseline, and the profitability question of the model validation
+    (Sec. IV-D, Table V): is the split-row plan faster than the baseline the
+    model is given (row-resident if the row fits one workgroup, else
+    two-pass)?  Answered by Eq. (9) with the measured baseline time (Eq. (7))
+    and, as the ablation, with the baseline priced at copy bandwidth plus a
+    serialized deposit."""
+    rows, acc, acc_peak, n = [], 0, 0, 0
+    for name, opn, dirn, M in SUITE:
+        op, d = getattr(C, opn), getattr(C, dirn)
+        w = C.workload_info(op, d, C.F32)
+        for N in SUITE_N:
+            t = {}
+            for c in range(C.NUM_PLANS):
+                p = C.plan_of_class(c)
+                if h.plan_legal(op, d, C.F32, M, N, p):
+                    t[p.as_tuple()] = h.time_plan(op, d, C.F32, M, N, p, 15, True)
+            base = (C.ROW_RESIDENT, 1) if (C.ROW_RESIDENT, 1) in t else (C.TWO_PASS, 1)
+            single = min(v for k, v in t.items() if k[0] != C.SPLIT_ROW)
+            splits = {k: v for k, v in t.items() if k[0] == C.SPLIT_ROW}
+            ks = [2, 4, 8, 16, 32]
+            c1 = h.time_control(op, d, C.F32, M, N, 1, 7)
+            ctrl = [max(0.0, h.time_control(op, d, C.F32, M, N, k, 7) - c1) if (C.SPLIT_ROW, k) in splits else 0.0
+                    for k in ks]
+            delta = C.model_delta(h, op, d, C.F32, M, N, t[base], ctrl)
+            tb_peak = M * N * w.b_base / (copy_gbps * 1e3)
+            dep = M * N * w.b_keep / (copy_gbps * 1e3)
+            delta_peak = [x - dep for x in C.model_delta(h, op, d, C.F32, M, N, tb_peak, ctrl)]
+            row = {"workload": name, "M": M, "N": N,
+                   "plans_us": {f"{v},{k}": round(x, 2) for (v, k), x in t.items()},
+                   "baseline_plan": list(base), "baseline_us": round(t[base], 2), "best_single_us": round(single, 2)}
+            if splits:
+                kb, tbest = min(splits.items(), key=lambda kv: kv[1])
+                meas = bool(tbest < t[base])
+                pred = bool(max(delta) > 0)
+                pred_peak = bool(max(delta_peak) > 0)
+                n += 1
+                acc += pred == meas
+                acc_peak += pred_peak == meas
+                row.update(best_split=list(kb), best_split_us=round(tbest, 2),
+                           speedup_vs_best_single=round(single / tbest, 3),
+                           gbps_best=round(M * N * w.b_staged / (min(tbest, single) * 1e3), 1),
+                           measured_profitable=meas, predicted_profitable=pred, predicted_profitable_peak=pred_peak)
+            rows.append(row)
+            log(f"suite {name} N={N}: {row}")
+    # crossover width N*: the narrowest swept width from which the split-row
+    # plan stays ahead of the baseline (measured, and as the model predicts)
+    cross = {}
+    for name, _, _, _ in SUITE:
+        rs = [r for r in rows if r["workload"] == name and "measured_profitable" in r]
+
+        def nstar(key):
+            ok = [r["N"] for i, r in enumerate(rs) if all(x[key] for x in rs[i:])]
+            return min(ok) if ok else None
+
+        cross[name] = {"measured": nstar("measured_profitable"), "model": nstar("predicted_profitable"),
+                       "peak_model": nstar("predicted_profitable_peak")}
+    return {"rows": rows, "profitability_pairs": n, "model_correct": acc, "peak_model_correct": acc_peak,
+            "crossover_N": cross}
+
+
 def traffic_for(kernel_key: str):
     """Counter-measured HBM bytes per launch for the dominant kernel, if the
     committed profile was taken from the current kernel sources."""
@@ -151,6 +222,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-regret", action="store_true", help="skip exhaustive timing of all plans")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / backward workloads")
+    ap.add_argument("--no-suite", action="store_true", help="skip the evaluation-suite workloads")
     ap.add_argument("--selector", default="auto", choices=["auto", "learned", "analytic", "fixed", "exhaustive"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -287,6 +359,9 @@ def main():
     copy_gbps = h.copy_bandwidth(1 << 30, 15)
     log(f"copy kernel: {copy_gbps:.1f} GB/s")
     extra = None if args.no_forms else forms(C, h)
+    suite_res = None if args.no_suite else suite(C, h, copy_gbps)
+    prims = h.probe_primitives(15)
+    log(f"primitives: {prims}")
 
     cpu = None
     if not args.no_cpu:
@@ -319,6 +394,8 @@ def main():
         "copy_kernel_bytes": 1 << 30,
         "per_shape": per_shape,
         "forms": extra,
+        "paper_suite": suite_res,
+        "primitives": prims,
         "source_hash": source_hash(),
     }
     print(json.dumps(out), flush=True)

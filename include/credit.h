@@ -304,6 +304,30 @@ typedef struct {
 credit_status_t credit_workload_info(credit_op_t op, credit_dir_t dir, credit_dtype_t dt,
                                      int recompute_stats, credit_workload_t *out);
 
+/* MI355X primitive costs (the analogue of the paper's primitive table,
+ * Sec. III-A, Table II), each the median of `reps` launches (0: 15) of a
+ * microbenchmark kernel.  Latencies in nanoseconds (from the 100 MHz
+ * real-time counter); rates in bytes per shader-clock cycle for one
+ * workgroup of 256 threads on one CU; clock_mhz is the s_memtime rate seen
+ * over the probes.  A handoff is one agent-scope store by one workgroup seen
+ * by a polling agent-scope load in another (the exchange's access path); the
+ * workgroup pairs are hardware ids (0, 8) and (0, 1), whose XCDs are
+ * reported.  exchange_ns[i] is one exchange round (q = 1) of a row group of
+ * k = 2, 4, 8, 16, 32 workgroups.  Allocates its own buffers. */
+typedef struct {
+    float clock_mhz;
+    float lds_load_ns;          /* dependent LDS load                             */
+    float l2_load_ns;           /* dependent agent-scope load, L2 hit             */
+    float handoff_same_xcd_ns;  /* one-way handoff between two workgroups, 1 XCD  */
+    float handoff_cross_xcd_ns; /* ... on two XCDs                                */
+    float barrier_ns;           /* one 256-thread workgroup barrier               */
+    float exchange_ns[5];
+    float lds_read_bpc, lds_write_bpc, l2_read_bpc, global_write_bpc;
+    int32_t xcd_same[2], xcd_cross[2];
+    int32_t errors;             /* bounded waits that gave up (0 expected)        */
+} credit_primitives_t;
+credit_status_t credit_probe_primitives(credit_handle_t h, int reps, credit_primitives_t *out);
+
 /* ------------------------------------------------------------ learned model
  * A 12 -> 64 -> 64 -> CREDIT_NUM_PLANS ReLU network over standardized shape
  * features predicts the fastest plan; trained on the GPU by the library's

@@ -54,6 +54,24 @@ class Workload(ctypes.Structure):
                 ("b_keep", ctypes.c_float), ("stages", ctypes.c_int32), ("q", ctypes.c_int32 * 4)]
 
 
+class Primitives(ctypes.Structure):
+    _fields_ = [("clock_mhz", ctypes.c_float), ("lds_load_ns", ctypes.c_float), ("l2_load_ns", ctypes.c_float),
+                ("handoff_same_xcd_ns", ctypes.c_float), ("handoff_cross_xcd_ns", ctypes.c_float),
+                ("barrier_ns", ctypes.c_float), ("exchange_ns", ctypes.c_float * 5),
+                ("lds_read_bpc", ctypes.c_float), ("lds_write_bpc", ctypes.c_float),
+                ("l2_read_bpc", ctypes.c_float), ("global_write_bpc", ctypes.c_float),
+                ("xcd_same", ctypes.c_int32 * 2), ("xcd_cross", ctypes.c_int32 * 2), ("errors", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {}
+        for name, typ in self._fields_:
+            v = getattr(self, name)
+            conv = (lambda x: int(x)) if "int" in str(typ) else (lambda x: round(float(x), 3))
+            d[name] = [conv(x) for x in v] if hasattr(v, "__len__") else conv(v)
+        d["exchange_ns"] = dict(zip(["k2", "k4", "k8", "k16", "k32"], d["exchange_ns"]))
+        return d
+
+
 def plan(variant, k: int = 1) -> Plan:
     if isinstance(variant, str):
         variant = {"two_pass": TWO_PASS, "resident": ROW_RESIDENT, "split": SPLIT_ROW}[variant]
@@ -113,6 +131,7 @@ _SIGS = {
     "credit_load_model": ([_P, ctypes.c_char_p], _S),
     "credit_set_option": ([_P, _S, _I64], _S),
     "credit_set_epoch": ([ctypes.c_uint32], _S),
+    "credit_probe_primitives": ([_P, _S, ctypes.POINTER(Primitives)], _S),
     "credit_plan_geometry": ([_P, _S, _S, _S, _I64, _I64, _PP, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                               ctypes.POINTER(_I32), ctypes.POINTER(_I32)], _S),
 }
@@ -302,6 +321,13 @@ class Handle:
         check(lib().credit_time_control(self.ptr, op, direction, dtype, M, N, k, reps, ctypes.byref(t)),
               "credit_time_control")
         return t.value
+
+    def probe_primitives(self, reps: int = 15) -> dict:
+        """MI355X primitive costs (LDS, L2, workgroup handoffs, barrier,
+        exchange rounds, per-CU rates); see credit_probe_primitives."""
+        out = Primitives()
+        check(lib().credit_probe_primitives(self.ptr, int(reps), ctypes.byref(out)), "credit_probe_primitives")
+        return out.as_dict()
 
     def copy_bandwidth(self, nbytes: int = 1 << 30, reps: int = 15) -> float:
         g = _F()

@@ -42,6 +42,7 @@ const void *twopass_kernel_quant_f8(int, int);
 const void *twopass_kernel_pearson_bwd(int, int);
 const void *twopass_kernel_wvar_bwd(int, int);
 const void *colreduce_kernel();
+const void *colreduce1_kernel();
 const void *colstats_kernel(int, bool);
 const void *control_kernel();
 const void *zero_kernel();
@@ -51,6 +52,7 @@ const void *copy_kernel();
 const void *encode_kernel(int);
 const void *decode_kernel(int);
 const void *mlp_kernel(int);
+const void *probe_kernel(int);
 }  // namespace credit
 
 using namespace credit;
@@ -160,7 +162,8 @@ struct Launch {
     int64_t chunk = 0;
     bool xcd = false;
     int parts = 0, rowblocks = 0;  // dgamma/dbeta partial rows
-    size_t off_slots = 0, off_colpart = 0, off_stats = 0, ws_bytes = 0;
+    int slices = 0;                // first-level column-reduction slices (0: one level)
+    size_t off_slots = 0, off_colpart = 0, off_stats = 0, off_colsum = 0, ws_bytes = 0;
 };
 
 }  // namespace
@@ -205,6 +208,17 @@ int occupancy(credit_handle_t h, const void *fn, int block, size_t shmem) {
     return n;
 }
 
+// The dgamma / dbeta partial rows are summed in two levels when there are
+// many: slices of kColPer partial rows each in parallel, then the slices, so
+// the reduction has parallelism over rows as well as columns (fixed order).
+constexpr int kColPer = 16;
+size_t colsum_layout(Launch &L, int ncp, int64_t N, size_t off) {
+    L.slices = L.parts > 2 * kColPer ? (L.parts + kColPer - 1) / kColPer : 0;
+    if (!L.slices) return off;
+    L.off_colsum = off;
+    return align256(off + (size_t)L.slices * ncp * N * 4);
+}
+
 // Resolves a plan into launch geometry and workspace layout.  Returns
 // CREDIT_ERR_UNSUPPORTED when the plan is illegal for the shape.
 credit_status_t resolve(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t plan,
@@ -233,6 +247,7 @@ credit_status_t resolve(credit_handle_t h, int k_op, int dt, int64_t M, int64_t 
             L.parts = L.rowblocks;
             L.off_colpart = off;
             off = align256(off + (size_t)L.rowblocks * ncp * N * 4);
+            off = colsum_layout(L, ncp, N, off);
             L.off_stats = off;
             off = align256(off + (size_t)2 * M * 4);
         }
@@ -284,6 +299,7 @@ credit_status_t resolve(credit_handle_t h, int k_op, int dt, int64_t M, int64_t 
         L.parts = L.groups;
         L.off_colpart = off;
         off = align256(off + (size_t)L.groups * ncp * N * 4);
+        off = colsum_layout(L, ncp, N, off);
     }
     L.ws_bytes = off;
     (void)recompute;
@@ -399,6 +415,16 @@ credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void 
         int parts = L.parts;
         int n_cp = ncp;
         int64_t N = c.N;
+        if (L.slices) {
+            float *tmp = (float *)(w + L.off_colsum);
+            int per = kColPer;
+            void *a1[] = {&part, &parts, &n_cp, &N, &per, &tmp};
+            e = hipLaunchKernel(colreduce1_kernel(), dim3((unsigned)((N + 255) / 256), (unsigned)L.slices), dim3(256),
+                                a1, 0, stream);
+            if (e != hipSuccess) return CREDIT_ERR_HIP;
+            part = tmp;
+            parts = L.slices;
+        }
         float *o0 = c.dgamma, *o1 = c.dbeta;
         void *args[] = {&part, &parts, &n_cp, &N, &o0, &o1};
         e = launch(colreduce_kernel(), (int)((N + 255) / 256), 256, 0, stream, args);
@@ -1254,6 +1280,120 @@ credit_status_t credit_wvar_bwd(credit_handle_t h, int64_t M, int64_t N, credit_
     c.out = dx; c.ldo = lddx;
     c.out1 = dw; c.ldo1 = lddw;
     try { return run_op(h, c, plan, ws, ws_bytes, stream, false); } catch (...) { return CREDIT_ERR_HIP; }
+}
+
+// ------------------------------------------------------- primitive probes
+namespace {
+struct ProbeOutH {
+    unsigned long long cycles, ticks;
+    unsigned err, xcc[2], sink;
+};
+
+credit_status_t probe_run(credit_handle_t h, int which, dim3 grid, dim3 block, void **args, ProbeOutH *dev,
+                          ProbeOutH *res) {
+    // the result block and the ping-pong word (the first 512 bytes) start at zero
+    if (zero_words(dev, 128, h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+    if (hipLaunchKernel(probe_kernel(which), grid, block, args, 0, h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+    if (hipMemcpyAsync(res, dev, sizeof(ProbeOutH), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+        return CREDIT_ERR_HIP;
+    return hipStreamSynchronize(h->stream) == hipSuccess ? CREDIT_OK : CREDIT_ERR_HIP;
+}
+
+credit_status_t probe_all(credit_handle_t h, int reps, credit_primitives_t *out) {
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    const int rounds = 2000, steps = 4000, xrows = 256;
+    const size_t o_out = 0, o_word = 256, o_chain = 512, o_rate = o_chain + 65536,
+                 o_slots = o_rate + (256 << 10);
+    const size_t slot_bytes = (size_t)xrows * kMaxStages * kMaxK * 8;
+    credit_status_t st = ensure_arena(h, o_slots + slot_bytes);
+    if (st != CREDIT_OK) return st;
+    h->prepared = std::make_tuple(-1, -1, (int64_t)-1, (int64_t)-1);
+    char *base = h->arena;
+    ProbeOutH *dev = (ProbeOutH *)(base + o_out);
+    unsigned *word = (unsigned *)(base + o_word);
+    unsigned *chain = (unsigned *)(base + o_chain);
+    void *rate = base + o_rate;
+    std::vector<unsigned> hc(16384);
+    for (unsigned i = 0; i < 16384; ++i) hc[i] = (i + 4099u) & 16383u;  // one cycle, 16 KiB strides
+    if (hipMemcpyAsync(chain, hc.data(), 65536, hipMemcpyHostToDevice, h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+    std::memset(out, 0, sizeof(*out));
+    const int R = reps > 0 ? reps : 15;
+    double mhz_c = 0, mhz_t = 0;
+    auto med = [&](int which, dim3 grid, dim3 block, std::vector<void *> args, double per, float *ns,
+                   float *cyc_out) -> credit_status_t {
+        std::vector<float> tn, tc;
+        for (int r = 0; r < R; ++r) {
+            ProbeOutH res;
+            credit_status_t s2 = probe_run(h, which, grid, block, args.data(), dev, &res);
+            if (s2 != CREDIT_OK) return s2;
+            out->errors += (int32_t)res.err;
+            tn.push_back((float)(res.ticks * 10.0 / per));
+            tc.push_back((float)(res.cycles / per));
+            mhz_c += (double)res.cycles;
+            mhz_t += (double)res.ticks;
+            if (which == 2) {
+                int32_t *dst = (((int *)args[2])[0] == 0 && ((int *)args[3])[0] == 8) ? out->xcd_same : out->xcd_cross;
+                dst[0] = (int32_t)res.xcc[0];
+                dst[1] = (int32_t)res.xcc[1];
+            }
+        }
+        if (ns) *ns = median(tn);
+        if (cyc_out) *cyc_out = median(tc);
+        return CREDIT_OK;
+    };
+    int isteps = steps, irounds = rounds;
+    unsigned spin = (unsigned)std::min<int64_t>(h->spin_limit, 0xffffffffLL);
+    if ((st = med(0, dim3(1), dim3(64), {&dev, &isteps}, steps, &out->lds_load_ns, nullptr)) != CREDIT_OK) return st;
+    const unsigned *cchain = chain;
+    if ((st = med(1, dim3(1), dim3(64), {&dev, &cchain, &isteps}, steps, &out->l2_load_ns, nullptr)) != CREDIT_OK)
+        return st;
+    int a0 = 0, b8 = 8, b1 = 1;
+    // a round trip is two handoffs
+    if ((st = med(2, dim3(9), dim3(64), {&dev, &word, &a0, &b8, &irounds, &spin}, 2.0 * rounds,
+                  &out->handoff_same_xcd_ns, nullptr)) != CREDIT_OK)
+        return st;
+    if ((st = med(2, dim3(9), dim3(64), {&dev, &word, &a0, &b1, &irounds, &spin}, 2.0 * rounds,
+                  &out->handoff_cross_xcd_ns, nullptr)) != CREDIT_OK)
+        return st;
+    if ((st = med(3, dim3(1), dim3(256), {&dev, &isteps}, steps, &out->barrier_ns, nullptr)) != CREDIT_OK) return st;
+    if (zero_words(base + o_slots, (int64_t)(slot_bytes / 4), h->stream) != hipSuccess) return CREDIT_ERR_HIP;
+    for (int i = 0; i < 5; ++i) {
+        RowArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.k = kSplitKs[i];
+        a.qs = 1;
+        a.M = xrows;
+        a.slots = (unsigned long long *)(base + o_slots);
+        a.errflag = h->errflag;
+        a.spin_limit = spin;
+        int rows = xrows;
+        std::vector<float> tn;
+        for (int r = 0; r < R; ++r) {
+            a.epoch = next_epoch();
+            void *args[] = {&dev, &a, &rows};
+            ProbeOutH res;
+            if ((st = probe_run(h, 4, dim3(a.k), dim3(kBlockThreads), args, dev, &res)) != CREDIT_OK) return st;
+            tn.push_back((float)(res.ticks * 10.0 / rows));
+        }
+        out->exchange_ns[i] = median(tn);
+    }
+    float *rates[4] = {&out->lds_read_bpc, &out->lds_write_bpc, &out->l2_read_bpc, &out->global_write_bpc};
+    const double bytes_per_rep[4] = {32768.0, 32768.0, 262144.0, 262144.0};
+    for (int kind = 0; kind < 4; ++kind) {
+        int k2 = kind, rp = kind < 2 ? 2000 : 200;
+        float cpr = 0.f;
+        if ((st = med(5, dim3(1), dim3(256), {&dev, &rate, &k2, &rp}, rp, nullptr, &cpr)) != CREDIT_OK) return st;
+        *rates[kind] = (float)(bytes_per_rep[kind] / cpr);
+    }
+    out->clock_mhz = mhz_t > 0 ? (float)(mhz_c / mhz_t * 100.0) : 0.f;
+    if (credit_check_errors(h, h->stream) != CREDIT_OK) out->errors += 1;
+    return CREDIT_OK;
+}
+}  // namespace
+
+credit_status_t credit_probe_primitives(credit_handle_t h, int reps, credit_primitives_t *out) {
+    if (!h || !out || reps < 0) return CREDIT_ERR_INVALID_ARG;
+    try { return probe_all(h, reps, out); } catch (...) { return CREDIT_ERR_HIP; }
 }
 
 credit_status_t credit_encode(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const float *x,

@@ -23,6 +23,24 @@ __global__ __launch_bounds__(256) void k_colreduce(const float *part, int parts,
 
 const void *colreduce_kernel() { return (const void *)&k_colreduce; }
 
+// First level of a two-level column reduction: block (bx, s) sums partial
+// rows [s * per, min(parts, (s + 1) * per)) of 256 columns, in increasing g,
+// into tmp[s][p][j].
+__global__ __launch_bounds__(256) void k_colreduce1(const float *part, int parts, int ncp, int64_t N, int per,
+                                                    float *tmp) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= N) return;
+    const int s = blockIdx.y;
+    const int g0 = s * per, g1 = g0 + per < parts ? g0 + per : parts;
+    for (int p = 0; p < ncp; ++p) {
+        float acc = 0.f;
+        for (int g = g0; g < g1; ++g) acc += part[((int64_t)g * ncp + p) * N + j];
+        tmp[((int64_t)s * ncp + p) * N + j] = acc;
+    }
+}
+
+const void *colreduce1_kernel() { return (const void *)&k_colreduce1; }
+
 const void *colstats_kernel(int dt, bool ln) {
     if (dt == DT_F32) return ln ? (const void *)&k_colstats<DT_F32, true> : (const void *)&k_colstats<DT_F32, false>;
     if (dt == DT_BF16) return ln ? (const void *)&k_colstats<DT_BF16, true> : (const void *)&k_colstats<DT_BF16, false>;

@@ -75,3 +75,19 @@ def test_determinism_across_runs_and_plans_agree(gpu_handle):
     ref = case.reference()
     for k, y in outs.items():
         check_case(case, {"y": y}, ref)
+
+
+def test_primitive_probes(gpu_handle):
+    # the primitive table: every bounded wait completed, latencies ordered as
+    # the memory hierarchy (LDS < L2 hit < a handoff through device memory),
+    # exchange rounds grow with the row group, rates are positive
+    p = gpu_handle.probe_primitives(reps=5)
+    print(p, flush=True)
+    assert p["errors"] == 0
+    assert 0 < p["lds_load_ns"] < p["l2_load_ns"] < p["handoff_cross_xcd_ns"]
+    assert 0 < p["handoff_same_xcd_ns"] and 0 < p["barrier_ns"]
+    ex = p["exchange_ns"]
+    assert 0 < ex["k2"] <= ex["k32"]
+    assert min(p["lds_read_bpc"], p["lds_write_bpc"], p["l2_read_bpc"], p["global_write_bpc"]) > 0
+    assert p["clock_mhz"] > 50
+    assert gpu_handle.check_errors() == C.OK
