@@ -69,7 +69,8 @@ typedef enum { CREDIT_F32 = 0, CREDIT_BF16 = 1, CREDIT_FP8_E4M3 = 2 } credit_dty
 /* Operators.  The first three exist in both directions; the others are the
  * remaining reduction-reuse workloads of the paper's evaluation suite
  * (Sec. IV-A) and exist in one direction each: SOFTMAX_LOGITS, PEARSON and
- * WVAR backward only, the two QUANT operators forward only.  Where a call
+ * WVAR backward only, the two QUANT operators and LAYERNORM_FP8_OUT forward
+ * only.  Where a call
  * names an (operator, direction) pair, any other pair is CREDIT_ERR_INVALID_ARG. */
 typedef enum {
     CREDIT_SOFTMAX = 0,
@@ -79,7 +80,8 @@ typedef enum {
     CREDIT_QUANT_INT8 = 4,     /* row-wise int8 quantisation (codes + per-row scale)             */
     CREDIT_QUANT_FP8 = 5,      /* row-wise e4m3 quantisation (codes + per-row scale)             */
     CREDIT_PEARSON = 6,        /* Pearson correlation of two rows                                */
-    CREDIT_WVAR = 7            /* weighted variance of a row                                     */
+    CREDIT_WVAR = 7,           /* weighted variance of a row                                     */
+    CREDIT_LAYERNORM_FP8_OUT = 8 /* LayerNorm forward fused with row-wise e4m3 quantisation      */
 } credit_op_t;
 typedef enum { CREDIT_FWD = 0, CREDIT_BWD = 1 } credit_dir_t;
 typedef enum { CREDIT_TWO_PASS = 0, CREDIT_ROW_RESIDENT = 1, CREDIT_SPLIT_ROW = 2 } credit_variant_t;
@@ -218,6 +220,19 @@ credit_status_t credit_quantize_rows(credit_handle_t h, credit_op_t op, int64_t 
                                      credit_dtype_t dt, const void *x, int64_t ldx, void *q,
                                      int64_t ldq, float *q_scale, const credit_plan_t *plan,
                                      void *ws, size_t ws_bytes, void *stream);
+
+/* LayerNorm forward fused with row-wise e4m3 quantisation of its output (the
+ * quantisation workload of Sec. IV-A fed by a LayerNorm): y as in
+ * credit_layernorm_fwd is computed in FP32 from an FP32 / BF16 row (`dt`),
+ * then one more statistics stage takes amax |y|, q_scale[row] = amax / 448
+ * (1 for an all-zero row) and the codes are e4m3 RNE of y * (448 / amax)
+ * saturated to +-448, stored as uint8 in q [M, ldq].  mean / rstd nullable. */
+credit_status_t credit_layernorm_fwd_fp8_out(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                                             const void *x, int64_t ldx, const float *gamma,
+                                             const float *beta, float eps, void *q, int64_t ldq,
+                                             float *q_scale, float *mean, float *rstd,
+                                             const credit_plan_t *plan, void *ws, size_t ws_bytes,
+                                             void *stream);
 
 /* Pearson-correlation backward (Sec. IV-A): per row, with xc = x - mean(x),
  * yc = y - mean(y), Sxx = sum xc^2, Syy = sum yc^2, Sxy = sum xc yc and

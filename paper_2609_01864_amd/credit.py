@@ -23,7 +23,7 @@ MODEL_PATH = os.path.join(_HERE, "models", "selector_gfx950.txt")
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_TIMEOUT, ERR_MODEL = range(7)
 F32, BF16, FP8 = 0, 1, 2
 SOFTMAX, LAYERNORM, RMSNORM = 0, 1, 2
-SOFTMAX_LOGITS, QUANT_INT8, QUANT_FP8, PEARSON, WVAR = 3, 4, 5, 6, 7
+SOFTMAX_LOGITS, QUANT_INT8, QUANT_FP8, PEARSON, WVAR, LAYERNORM_FP8_OUT = 3, 4, 5, 6, 7, 8
 FWD, BWD = 0, 1
 TWO_PASS, ROW_RESIDENT, SPLIT_ROW = 0, 1, 2
 SEL_LEARNED, SEL_ANALYTIC, SEL_EXHAUSTIVE, SEL_FIXED, SEL_PEAK = range(5)
@@ -111,6 +111,8 @@ _SIGS = {
     "credit_quantize_rows": ([_P, _S, _I64, _I64, _S, _P, _I64, _P, _I64, _P, _PP, _P, _SZ, _P], _S),
     "credit_pearson_bwd": ([_P, _I64, _I64, _S, _P, _I64, _P, _I64, _P, _P, _I64, _P, _I64, _PP, _P, _SZ, _P], _S),
     "credit_wvar_bwd": ([_P, _I64, _I64, _S, _P, _I64, _P, _I64, _P, _P, _I64, _P, _I64, _PP, _P, _SZ, _P], _S),
+    "credit_layernorm_fwd_fp8_out": ([_P, _I64, _I64, _S, _P, _I64, _P, _P, _F, _P, _I64, _P, _P, _P, _PP, _P, _SZ,
+                                      _P], _S),
     "credit_encode": ([_P, _I64, _I64, _S, _P, _P, _P, _P], _S),
     "credit_decode": ([_P, _I64, _I64, _S, _P, _P, _P, _P], _S),
     "credit_check_errors": ([_P, _P], _S),
@@ -575,6 +577,26 @@ def quantize_rows(x, fmt: str = "int8", p: Optional[Plan] = None, out=None, out_
     _launch(h, "credit_quantize_rows", op, FWD, dt, M, N, p, s,
             lambda w, wn: (h.ptr, op, M, N, dt, _ptr(x), _ld(x), _ptr(q), _ld(q), _ptr(qs), pp, w, wn, s))
     return q, qs
+
+
+def layernorm_fwd_fp8_out(x, gamma, beta, eps: float = 1e-5, p: Optional[Plan] = None, save_stats: bool = True,
+                          h: Optional[Handle] = None):
+    """LayerNorm forward of an FP32 / BF16 matrix fused with row-wise e4m3
+    quantisation of y.  Returns (codes uint8, scale, mean, rstd)."""
+    torch = _torch()
+    h = h or handle(x.device.index)
+    dt = io_dtype(x)
+    M, N = x.shape
+    q = torch.empty((M, N), dtype=torch.uint8, device=x.device)
+    qs = _scale_out(x, M)
+    mean = torch.empty(M, dtype=torch.float32, device=x.device) if save_stats else None
+    rstd = torch.empty(M, dtype=torch.float32, device=x.device) if save_stats else None
+    s = h._stream()
+    pp = None if p is None else ctypes.byref(p)
+    _launch(h, "credit_layernorm_fwd_fp8_out", LAYERNORM_FP8_OUT, FWD, dt, M, N, p, s,
+            lambda w, wn: (h.ptr, M, N, dt, _ptr(x), _ld(x), _ptr(gamma), _ptr(beta), float(eps), _ptr(q), _ld(q),
+                           _ptr(qs), _ptr(mean), _ptr(rstd), pp, w, wn, s))
+    return q, qs, mean, rstd
 
 
 def pearson_bwd(x, y, dr, p: Optional[Plan] = None, h: Optional[Handle] = None):

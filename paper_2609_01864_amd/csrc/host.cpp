@@ -41,6 +41,8 @@ const void *twopass_kernel_quant_i8(int, int);
 const void *twopass_kernel_quant_f8(int, int);
 const void *twopass_kernel_pearson_bwd(int, int);
 const void *twopass_kernel_wvar_bwd(int, int);
+const void *resident_kernel_lnq_fwd(int, int);
+const void *twopass_kernel_lnq_fwd(int, int);
 const void *colreduce_kernel();
 const void *colreduce1_kernel();
 const void *colstats_kernel(int, bool);
@@ -87,13 +89,15 @@ int kop(int op, int dir) {
     if (op == CREDIT_QUANT_FP8 && dir == CREDIT_FWD) return OP_QUANT_F8;
     if (op == CREDIT_PEARSON && dir == CREDIT_BWD) return OP_PEARSON_BWD;
     if (op == CREDIT_WVAR && dir == CREDIT_BWD) return OP_WVAR_BWD;
+    if (op == CREDIT_LAYERNORM_FP8_OUT && dir == CREDIT_FWD) return OP_LNQ_FWD;
     return -1;
 }
 // I/O dtypes an operator is built for: quantisation reads FP32 / BF16 and
 // writes codes; Pearson and weighted variance take FP32 / BF16.
 bool dt_ok(int k_op, int dt) {
     if (dt < CREDIT_F32 || dt > CREDIT_FP8_E4M3) return false;
-    if (is_quant(k_op) || k_op == OP_PEARSON_BWD || k_op == OP_WVAR_BWD) return dt != CREDIT_FP8_E4M3;
+    if (is_quant(k_op) || k_op == OP_PEARSON_BWD || k_op == OP_WVAR_BWD || k_op == OP_LNQ_FWD)
+        return dt != CREDIT_FP8_E4M3;
     return k_op >= 0 && k_op < OP_COUNT;
 }
 bool core_op(int k_op) { return k_op >= OP_SOFTMAX_FWD && k_op <= OP_RMS_BWD; }
@@ -101,7 +105,7 @@ int dt_bytes(int dt) { return dt == CREDIT_F32 ? 4 : dt == CREDIT_BF16 ? 2 : 1; 
 int dt_epv(int dt) { return 16 / dt_bytes(dt); }
 int ncp_of(int k_op) { return k_op == OP_LN_BWD ? 2 : k_op == OP_RMS_BWD ? 1 : 0; }
 bool two_inputs(int k_op) { return two_in(k_op); }
-int out_bytes(int k_op, int dt) { return is_quant(k_op) ? 1 : dt_bytes(dt); }
+int out_bytes(int k_op, int dt) { return byte_out(k_op) ? 1 : dt_bytes(dt); }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 const void *resident_fn(int k_op, int dt, int vpt) {
@@ -117,6 +121,7 @@ const void *resident_fn(int k_op, int dt, int vpt) {
     case OP_QUANT_F8: return resident_kernel_quant_f8(dt, vpt);
     case OP_PEARSON_BWD: return resident_kernel_pearson_bwd(dt, vpt);
     case OP_WVAR_BWD: return resident_kernel_wvar_bwd(dt, vpt);
+    case OP_LNQ_FWD: return resident_kernel_lnq_fwd(dt, vpt);
     }
     return nullptr;
 }
@@ -133,6 +138,7 @@ const void *twopass_fn(int k_op, int dt, int block) {
     case OP_QUANT_F8: return twopass_kernel_quant_f8(dt, block);
     case OP_PEARSON_BWD: return twopass_kernel_pearson_bwd(dt, block);
     case OP_WVAR_BWD: return twopass_kernel_wvar_bwd(dt, block);
+    case OP_LNQ_FWD: return twopass_kernel_lnq_fwd(dt, block);
     }
     return nullptr;
 }
@@ -141,7 +147,8 @@ const void *twopass_fn(int k_op, int dt, int block) {
 // is compiled for (used when no device is available to ask).
 int model_waves(int k_op, int dt, int vpt) {
     int data = vpt * 4 * (two_inputs(k_op) ? 2 : 1) + ncp_of(k_op) * vpt * dt_epv(dt);
-    int work = 64 + (dt == CREDIT_FP8_E4M3 ? 32 : 0) + (k_op == OP_SOFTMAX_FWD || k_op == OP_SOFTMAX_BWD ? 0 : 16);
+    int work = 64 + (dt == CREDIT_FP8_E4M3 || k_op == OP_LNQ_FWD ? 32 : 0) +
+               (k_op == OP_SOFTMAX_FWD || k_op == OP_SOFTMAX_BWD ? 0 : 16);
     int w = 512 / (data + work);
     return std::max(1, std::min(8, w));
 }
@@ -149,7 +156,7 @@ int model_waves(int k_op, int dt, int vpt) {
 // Number of exchange stages of a row (for the control kernel and the model).
 int stages_of(int k_op, int dt, bool recompute) {
     int L = 1;
-    if (dt == CREDIT_FP8_E4M3 && k_op != OP_SOFTMAX_FWD && !is_quant(k_op)) L += 1;
+    if ((dt == CREDIT_FP8_E4M3 && k_op != OP_SOFTMAX_FWD && !is_quant(k_op)) || k_op == OP_LNQ_FWD) L += 1;
     if (recompute && (k_op == OP_LN_BWD || k_op == OP_RMS_BWD)) L += 1;
     return L;
 }
@@ -452,9 +459,11 @@ credit_status_t run_op(credit_handle_t h, const OpCall &c, const credit_plan_t *
         if (!c.s0 || !c.so || (two_inputs(c.k_op) && !c.s1)) return CREDIT_ERR_INVALID_ARG;
     }
     if (is_quant(c.k_op) && !c.so) return CREDIT_ERR_INVALID_ARG;
-    const bool norm = c.k_op == OP_LN_FWD || c.k_op == OP_RMS_FWD || c.k_op == OP_LN_BWD || c.k_op == OP_RMS_BWD;
+    const bool norm = c.k_op == OP_LN_FWD || c.k_op == OP_RMS_FWD || c.k_op == OP_LN_BWD || c.k_op == OP_RMS_BWD ||
+                      c.k_op == OP_LNQ_FWD;
     if (norm && !c.gamma) return CREDIT_ERR_INVALID_ARG;
-    if (c.k_op == OP_LN_FWD && !c.beta) return CREDIT_ERR_INVALID_ARG;
+    if ((c.k_op == OP_LN_FWD || c.k_op == OP_LNQ_FWD) && !c.beta) return CREDIT_ERR_INVALID_ARG;
+    if (c.k_op == OP_LNQ_FWD && !c.so) return CREDIT_ERR_INVALID_ARG;
     if ((c.k_op == OP_LN_BWD || c.k_op == OP_RMS_BWD) && !recompute && !c.rstd_in) return CREDIT_ERR_INVALID_ARG;
     if (c.k_op == OP_LN_BWD && !recompute && !c.mean_in) return CREDIT_ERR_INVALID_ARG;
     credit_plan_t p;
@@ -487,12 +496,12 @@ credit_workload_t workload(int k_op, int dt, bool recompute) {
         w.q[L++] = k_op == OP_LN_BWD ? 2 : 1;
         stage_bytes += e;  // reads x only
     }
-    int q = (k_op == OP_SOFTMAX_FWD || k_op == OP_LN_FWD || k_op == OP_LN_BWD) ? 2 : 1;
+    int q = (k_op == OP_SOFTMAX_FWD || k_op == OP_LN_FWD || k_op == OP_LN_BWD || k_op == OP_LNQ_FWD) ? 2 : 1;
     if (k_op == OP_SMXL_BWD || k_op == OP_WVAR_BWD) q = 3;
     if (k_op == OP_PEARSON_BWD) q = 5;
     w.q[L++] = q;
     stage_bytes += nin * e;
-    if (dt == CREDIT_FP8_E4M3 && k_op != OP_SOFTMAX_FWD && !is_quant(k_op)) {
+    if ((dt == CREDIT_FP8_E4M3 && k_op != OP_SOFTMAX_FWD && !is_quant(k_op)) || k_op == OP_LNQ_FWD) {
         w.q[L++] = 1;  // amax of the output before it can be scaled
         stage_bytes += nin * e;
     }
@@ -1279,6 +1288,21 @@ credit_status_t credit_wvar_bwd(credit_handle_t h, int64_t M, int64_t N, credit_
     c.rowg = dv;
     c.out = dx; c.ldo = lddx;
     c.out1 = dw; c.ldo1 = lddw;
+    try { return run_op(h, c, plan, ws, ws_bytes, stream, false); } catch (...) { return CREDIT_ERR_HIP; }
+}
+
+credit_status_t credit_layernorm_fwd_fp8_out(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                                             const void *x, int64_t ldx, const float *gamma, const float *beta,
+                                             float eps, void *q, int64_t ldq, float *q_scale, float *mean,
+                                             float *rstd, const credit_plan_t *plan, void *ws, size_t ws_bytes,
+                                             void *stream) {
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = OP_LNQ_FWD; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = x; c.ld0 = ldx;
+    c.gamma = gamma; c.beta = beta; c.eps = eps;
+    c.out = q; c.ldo = ldq; c.so = q_scale;
+    c.mean_out = mean; c.rstd_out = rstd;
     try { return run_op(h, c, plan, ws, ws_bytes, stream, false); } catch (...) { return CREDIT_ERR_HIP; }
 }
 

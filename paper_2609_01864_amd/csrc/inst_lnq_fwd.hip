@@ -1,0 +1,32 @@
+// Kernel instantiations for OP_LNQ_FWD (LayerNorm forward with e4m3 output): the register-resident /
+// split-row kernel for every (dtype, vectors-per-thread) within the register
+// budget, and the two-pass kernel for 256- and 1024-thread workgroups.
+#include "resident.h"
+#include "twopass.h"
+
+namespace credit {
+
+#define CREDIT_R(DT, V) \
+    if (max_vpt(OP_LNQ_FWD, DT) >= V && dt == DT && vpt == V) return (const void *)&k_resident<OP_LNQ_FWD, (max_vpt(OP_LNQ_FWD, DT) >= V ? DT : DT_F32), (max_vpt(OP_LNQ_FWD, DT) >= V ? V : 1)>;
+#define CREDIT_RV(DT) \
+    CREDIT_R(DT, 1) CREDIT_R(DT, 2) CREDIT_R(DT, 4) CREDIT_R(DT, 8) \
+    CREDIT_R(DT, 12) CREDIT_R(DT, 16) CREDIT_R(DT, 24) CREDIT_R(DT, 32)
+
+const void *resident_kernel_lnq_fwd(int dt, int vpt) {
+    CREDIT_RV(DT_F32)
+    CREDIT_RV(DT_BF16)
+    return nullptr;
+}
+
+const void *twopass_kernel_lnq_fwd(int dt, int block) {
+    if (block == 256) {
+        if (dt == DT_F32) return (const void *)&k_twopass<OP_LNQ_FWD, DT_F32, 256, 4>;
+        if (dt == DT_BF16) return (const void *)&k_twopass<OP_LNQ_FWD, DT_BF16, 256, 4>;
+    } else if (block == 1024) {
+        if (dt == DT_F32) return (const void *)&k_twopass<OP_LNQ_FWD, DT_F32, 1024, 4>;
+        if (dt == DT_BF16) return (const void *)&k_twopass<OP_LNQ_FWD, DT_BF16, 1024, 4>;
+    }
+    return nullptr;
+}
+
+}  // namespace credit

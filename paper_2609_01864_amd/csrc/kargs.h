@@ -13,7 +13,8 @@ enum KOp {
     OP_QUANT_F8 = 8,     // row-wise e4m3 quantisation, scale = amax / 448
     OP_PEARSON_BWD = 9,  // Pearson-correlation backward (x, y, dr -> dx, dy)
     OP_WVAR_BWD = 10,    // weighted-variance backward (x, w, dv -> dx, dw)
-    OP_COUNT = 11
+    OP_LNQ_FWD = 11,     // LayerNorm forward writing e4m3 codes + row scales from FP32 / BF16 input
+    OP_COUNT = 12
 };
 enum KDt { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };
 
@@ -38,9 +39,12 @@ constexpr int q_of(int op) {
     return op == OP_PEARSON_BWD ? 5 : (op == OP_SMXL_BWD || op == OP_WVAR_BWD) ? 3 : 2;
 }
 // Operators with two resident input tensors / two output tensors.
-constexpr bool two_in(int op) { return (op >= OP_SOFTMAX_BWD && op <= OP_SMXL_BWD) || op >= OP_PEARSON_BWD; }
-constexpr bool two_out(int op) { return op >= OP_PEARSON_BWD; }
+constexpr bool two_in(int op) {
+    return (op >= OP_SOFTMAX_BWD && op <= OP_SMXL_BWD) || op == OP_PEARSON_BWD || op == OP_WVAR_BWD;
+}
+constexpr bool two_out(int op) { return op == OP_PEARSON_BWD || op == OP_WVAR_BWD; }
 constexpr bool is_quant(int op) { return op == OP_QUANT_I8 || op == OP_QUANT_F8; }
+constexpr bool byte_out(int op) { return is_quant(op) || op == OP_LNQ_FWD; }  // one-byte codes out
 
 // Register-resident slice sizes: vectors (16 bytes) per thread per tensor.
 constexpr int kVpts[] = {1, 2, 4, 8, 12, 16, 24, 32};
@@ -49,7 +53,7 @@ constexpr int kNumVpts = 8;
 // register file (data of one or two tensors, plus FP32 dgamma/dbeta column
 // partials for normalisation backward).
 constexpr int max_vpt(int op, int dt) {
-    return (op <= OP_RMS_FWD || op == OP_QUANT_I8 || op == OP_QUANT_F8) ? (dt == DT_FP8 ? 16 : 32)
+    return (op <= OP_RMS_FWD || op == OP_QUANT_I8 || op == OP_QUANT_F8 || op == OP_LNQ_FWD) ? (dt == DT_FP8 ? 16 : 32)
          : (op == OP_SOFTMAX_BWD || op == OP_SMXL_BWD || op == OP_PEARSON_BWD || op == OP_WVAR_BWD) ? 16
          : op == OP_LN_BWD ? (dt == DT_F32 ? 8 : dt == DT_BF16 ? 4 : 2)
          : (dt == DT_F32 ? 8 : dt == DT_BF16 ? 8 : 4);

@@ -29,7 +29,8 @@ namespace credit {
 template <int OP> struct OpTraits {
     static constexpr bool TWO = two_in(OP);    // two resident input tensors
     static constexpr bool TWOO = two_out(OP);  // two output tensors
-    static constexpr bool QUANT = is_quant(OP);  // one-byte codes out
+    static constexpr bool QUANT = is_quant(OP);  // row quantisation
+    static constexpr bool BOUT = byte_out(OP);   // one-byte codes out
     static constexpr int NCP = OP == OP_LN_BWD ? 2 : (OP == OP_RMS_BWD ? 1 : 0);  // column partials
 };
 
@@ -38,7 +39,8 @@ template <int OP> struct OpTraits {
 // the FP32 column partials and the working registers within 512 / W VGPRs.
 template <int OP, int DT, int VPT> constexpr int resident_waves() {
     constexpr int data = VPT * 4 * (OpTraits<OP>::TWO ? 2 : 1) + OpTraits<OP>::NCP * VPT * Io<DT>::EPV;
-    constexpr int work = 64 + (DT == DT_FP8 ? 32 : 0) + (OP == OP_SOFTMAX_FWD || OP == OP_SOFTMAX_BWD ? 0 : 16);
+    constexpr int work = 64 + (DT == DT_FP8 || OP == OP_LNQ_FWD ? 32 : 0) +
+                         (OP == OP_SOFTMAX_FWD || OP == OP_SOFTMAX_BWD ? 0 : 16);
     static_assert(OP < OP_COUNT, "operator");
     constexpr int w = 512 / (data + work);
     return w < 1 ? 1 : (w > 8 ? 8 : w);
@@ -183,10 +185,10 @@ template <int OP, int DT, int VPT, bool AL, bool FULLS>
 __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const Slice &sl, float *red, float *xb) {
     using T = OpTraits<OP>;
     constexpr int EPV = Io<DT>::EPV, B = Io<DT>::BYTES, NCP = T::NCP;
-    constexpr int OB = T::QUANT ? 1 : B;  // output element bytes
+    constexpr int OB = T::BOUT ? 1 : B;  // output element bytes
     constexpr bool FP8 = DT == DT_FP8;
     // slots per batch of parameter loads: 16 FP32 parameter registers in flight
-    constexpr int GBW = 16 / EPV / (OP == OP_LN_FWD ? 2 : 1);
+    constexpr int GBW = 16 / EPV / (OP == OP_LN_FWD || OP == OP_LNQ_FWD ? 2 : 1);
     constexpr int GB = GBW < 1 ? 1 : (VPT < GBW ? VPT : GBW);
     int parity = 0;
     const int tid = threadIdx.x;
@@ -234,7 +236,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
         asm volatile("" : "+v"(toff));
         asm volatile("" : "+v"(poff));
         uint32_t qoff = (uint32_t)tid * (uint32_t)EPV;  // codes: EPV bytes per slot
-        if constexpr (T::QUANT) asm volatile("" : "+v"(qoff));
+        if constexpr (T::BOUT) asm volatile("" : "+v"(qoff));
         // masked slots re-read the slice's first vector (only when nfv >= 1);
         // their data is zeroed before use and their stores are skipped
         auto doff = [&](int j) -> uint32_t {
@@ -349,8 +351,10 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, -cmax)) * omul;
                 store_vec<DT>(orow, tcol, tn, false, encode<DT>(y, 1.f));
             }
-        } else if constexpr (OP == OP_LN_FWD || OP == OP_RMS_FWD) {
-            constexpr bool LN = OP == OP_LN_FWD;
+        } else if constexpr (OP == OP_LN_FWD || OP == OP_RMS_FWD || OP == OP_LNQ_FWD) {
+            constexpr bool LN = OP != OP_RMS_FWD;
+            constexpr bool QO = OP == OP_LNQ_FWD;  // e4m3 codes out from an FP32 / BF16 row
+            constexpr bool F8O = FP8 || QO;        // FP8 output: one more (amax) stage
             // Statistics on the decoded codes q (x = xs * q for FP8, q = x
             // otherwise), so the per-row scale is applied once per row, not per
             // element: mean_x = xs mean_q, var_x = xs^2 var_q, y uses xs * rstd.
@@ -439,8 +443,18 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             };
             // FP8 output with a small slice keeps y in registers between the
             // amax stage and the quantize pass: gamma / beta are read once
-            constexpr bool YC = FP8 && VPT * EPV <= 32;
+            constexpr bool YC = F8O && VPT * EPV <= 32;
             float yc[YC ? VPT * EPV : 1], yct[YC ? EPV : 1];
+            // the trailing partial vector of the output
+            auto store_out_tail = [&](const float *y, float oinv) {
+                if constexpr (QO) {
+                    unsigned w[EPV / 4];
+                    quant_codes<false, EPV>(y, oinv, w);
+                    for (int i = 0; i < tn; ++i) orow[tcol + i] = (char)((w[i / 4] >> (8 * (i % 4))) & 0xffu);
+                } else {
+                    store_vec<DT>(orow, tcol, tn, false, encode<DT>(y, oinv));
+                }
+            };
             // output pass over the slots in batches of GB: the parameter loads of
             // a batch are issued together; store == false only measures amax
             auto out_pass = [&](bool store, float oinv, float &amax) {
@@ -463,7 +477,13 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                         decode<DT>(d0[j], q, 1.f);
                         h(q, g[u], LN ? bb[u] : g[u], y);
                         if (store) {
-                            ST(j, encode<DT>(y, oinv));
+                            if constexpr (QO) {
+                                unsigned w[EPV / 4];
+                                quant_codes<false, EPV>(y, oinv, w);
+                                QST(j, w);
+                            } else {
+                                ST(j, encode<DT>(y, oinv));
+                            }
                         } else {
                             const bool ok = ok_of(j);
 #pragma unroll
@@ -481,7 +501,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     if constexpr (LN) load_params_tail<DT>(a.beta, tcol, tn, bb);
                     h(q, g, bb, y);
                     if (store) {
-                        store_vec<DT>(orow, tcol, tn, false, encode<DT>(y, oinv));
+                        store_out_tail(y, oinv);
                     } else {
                         for (int i = 0; i < tn; ++i) amax = fmaxf(amax, fabsf(y[i]));
                         if constexpr (YC) {
@@ -492,7 +512,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 }
             };
             float oinv = 1.f;
-            if constexpr (FP8) {
+            if constexpr (F8O) {
                 float am[1] = {0.f};
                 out_pass(false, 1.f, am[0]);
                 row_reduce<1>(am, MergeMax(), a, row, 1, c, red, xb, parity);
@@ -501,8 +521,16 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             }
             if constexpr (YC) {
 #pragma unroll
-                for (int j = 0; j < VPT; ++j) ST(j, encode<DT>(&yc[j * EPV], oinv));
-                if (tail) store_vec<DT>(orow, tcol, tn, false, encode<DT>(yct, oinv));
+                for (int j = 0; j < VPT; ++j) {
+                    if constexpr (QO) {
+                        unsigned w[EPV / 4];
+                        quant_codes<false, EPV>(&yc[j * EPV], oinv, w);
+                        QST(j, w);
+                    } else {
+                        ST(j, encode<DT>(&yc[j * EPV], oinv));
+                    }
+                }
+                if (tail) store_out_tail(yct, oinv);
             } else {
                 float unused = 0.f;
                 out_pass(true, oinv, unused);

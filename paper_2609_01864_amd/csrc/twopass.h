@@ -109,7 +109,7 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
     for (int64_t row = blockIdx.x; row < a.M; row += gridDim.x) {
         const char *r0 = (const char *)a.in0 + row * a.ld0 * B;
         const char *r1 = TWO ? (const char *)a.in1 + row * a.ld1 * B : nullptr;
-        char *orow = (char *)a.out + row * a.ldo * (is_quant(OP) ? 1 : B);
+        char *orow = (char *)a.out + row * a.ldo * (byte_out(OP) ? 1 : B);
         char *orow1 = two_out(OP) ? (char *)a.out1 + row * a.ldo1 * B : nullptr;
         const bool writer = threadIdx.x == 0;
 
@@ -145,8 +145,10 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
                 for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, -cmax)) * omul;
                 row_store<DT>(orow, v, nv, encode<DT>(y, 1.f));
             });
-        } else if constexpr (OP == OP_LN_FWD || OP == OP_RMS_FWD || OP == OP_LN_BWD || OP == OP_RMS_BWD) {
-            constexpr bool LN = OP == OP_LN_FWD || OP == OP_LN_BWD;
+        } else if constexpr (OP == OP_LN_FWD || OP == OP_RMS_FWD || OP == OP_LN_BWD || OP == OP_RMS_BWD ||
+                             OP == OP_LNQ_FWD) {
+            constexpr bool LN = OP == OP_LN_FWD || OP == OP_LN_BWD || OP == OP_LNQ_FWD;
+            constexpr bool QO = OP == OP_LNQ_FWD;  // e4m3 codes out from an FP32 / BF16 row
             constexpr bool BWD = OP == OP_LN_BWD || OP == OP_RMS_BWD;
             const float xs = FP8 ? a.s0[row] : 1.f;
             const float gs = (FP8 && BWD) ? a.s1[row] : 1.f;
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
                 }
             };
             float oinv = 1.f;
-            if constexpr (FP8) {
+            if constexpr (FP8 || QO) {
                 float am[1] = {0.f};
                 stream_row<DT, BLOCK, U, false>(r0, r1, N, al0, al1, [&](int64_t v, u32x4 d0v, u32x4 d1v, int nv) {
                     float y[EPV];
@@ -253,7 +255,13 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
                 if (nv == 0) return;
                 float y[EPV];
                 apply(v, d0v, d1v, nv, y);
-                row_store<DT>(orow, v, nv, encode<DT>(y, oinv));
+                if constexpr (QO) {
+                    unsigned w[EPV / 4];
+                    quant_codes<false, EPV>(y, oinv, w);
+                    code_store<EPV>(orow, v, nv, w);
+                } else {
+                    row_store<DT>(orow, v, nv, encode<DT>(y, oinv));
+                }
             });
         } else if constexpr (OP == OP_SOFTMAX_BWD) {
             const float ys = FP8 ? a.s0[row] : 1.f, gs = FP8 ? a.s1[row] : 1.f;

@@ -22,7 +22,7 @@ import oracle
 from paper_2609_01864_amd import credit as C
 from paper_2609_01864_amd import inputs as I
 
-from _cases import ALL_PLANS, check_tensor, from_device, scale_dev, to_device, ulp_bf16
+from _cases import ALL_PLANS, EPS, check_tensor, from_device, scale_dev, to_device, ulp_bf16
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +31,8 @@ OPS = {"smxl": (C.SOFTMAX_LOGITS, C.BWD, ["f32", "bf16", "fp8"]),
        "quant_int8": (C.QUANT_INT8, C.FWD, ["f32", "bf16"]),
        "quant_fp8": (C.QUANT_FP8, C.FWD, ["f32", "bf16"]),
        "pearson": (C.PEARSON, C.BWD, ["f32", "bf16"]),
-       "wvar": (C.WVAR, C.BWD, ["f32", "bf16"])}
+       "wvar": (C.WVAR, C.BWD, ["f32", "bf16"]),
+       "lnq": (C.LAYERNORM_FP8_OUT, C.FWD, ["f32", "bf16"])}
 DTN = {"f32": C.F32, "bf16": C.BF16, "fp8": C.FP8}
 
 
@@ -45,6 +46,9 @@ class WCase:
             self.raw = {"x": I.store(x, dtype), "dy": I.store(I.normal_rows(M, N, seed, 1, rows=rows), dtype)}
         elif op.startswith("quant"):
             self.raw = {"x": I.store(I.outlier_rows(M, N, seed, 0, rows), dtype)}
+        elif op == "lnq":
+            self.raw = {"x": I.store(I.norm_rows(M, N, seed, 0, rows), dtype)}
+            self.gamma, self.beta = I.norm_params(N, seed)
         elif op == "pearson":
             x, y = I.correlated_rows(M, N, seed, rows=rows)
             self.raw = {"x": I.store(x, dtype), "y": I.store(y, dtype)}
@@ -68,6 +72,10 @@ class WCase:
             codes, scale = oracle.quantize_rows(v["x"].astype(np.float32), fmt)
             return {"codes": codes, "scale": scale}
         x = v["x"]
+        if self.op == "lnq":
+            gm, bt = self.gamma.astype(np.float64), self.beta.astype(np.float64)
+            y, mu, rs = oracle.layernorm_fwd(x, gm, bt, EPS)
+            return {"y": y, "mag_y": np.abs(x) * rs[:, None] * gm + np.abs(bt), "mean": mu, "rstd": rs}
         if self.op == "pearson":
             with np.errstate(divide="ignore", invalid="ignore"):  # N = 1: r undefined
                 return self._pearson_reference(x, v["y"], g)
@@ -101,6 +109,11 @@ class WCase:
         if self.op == "smxl":
             dx, dxs = C.softmax_logits_bwd(dev["x"], dev["dy"], sc["x"], sc["dy"], p=plan, h=h)
             out = {"dx": from_device(dx, dt, dxs), "dx_scale": dxs}
+        elif self.op == "lnq":
+            q, qs, mu, rs = C.layernorm_fwd_fp8_out(dev["x"], torch.from_numpy(self.gamma).cuda(),
+                                                    torch.from_numpy(self.beta).cuda(), EPS, p=plan, h=h)
+            out = {"y": oracle.decode(q.cpu().numpy(), "fp8", qs.cpu().numpy()), "y_scale": qs,
+                   "mean": mu.double().cpu().numpy(), "rstd": rs.double().cpu().numpy()}
         elif self.op.startswith("quant"):
             fmt = "int8" if self.op == "quant_int8" else "fp8"
             qbuf = torch.zeros(self.M * ld + offset + 64, dtype=torch.int8 if fmt == "int8" else torch.uint8,
@@ -122,6 +135,11 @@ class WCase:
 
 
 def check(case, got, ref):
+    if case.op == "lnq":
+        check_tensor("y", "layernorm_fwd", "fp8", got["y"], ref["y"], ref["mag_y"], got["y_scale"])
+        assert np.max(np.abs(got["rstd"] - ref["rstd"])) <= 1e-6 * np.max(ref["rstd"])
+        assert np.max(np.abs(got["mean"] - ref["mean"])) <= 1e-5 * max(1.0, np.max(np.abs(ref["mean"])))
+        return
     if case.op.startswith("quant"):
         assert np.array_equal(got["scale"].view(np.uint32), ref["scale"].view(np.uint32)), "scale"
         bad = np.flatnonzero(got["codes"].ravel().view(np.uint8) != ref["codes"].ravel().view(np.uint8))
@@ -212,6 +230,14 @@ def test_workload_zero_rows_and_illegal_args(gpu_handle, op):
         z = torch.zeros((4, 16), dtype=torch.uint8, device="cuda")
         with pytest.raises(C.CreditError):
             C.quantize_rows(z, "int8", p=C.plan("two_pass"), h=h)
+    elif op == "lnq":
+        gm = torch.ones(10, device="cuda")
+        q, qs, _, _ = C.layernorm_fwd_fp8_out(x, gm, gm, EPS, p=C.plan("two_pass"), h=h)
+        assert q.shape == (0, 10)
+        z = torch.zeros((4, 16), dtype=torch.uint8, device="cuda")
+        with pytest.raises(C.CreditError):  # the input is FP32 or BF16
+            C.layernorm_fwd_fp8_out(z, torch.ones(16, device="cuda"), torch.ones(16, device="cuda"), EPS,
+                                    p=C.plan("two_pass"), h=h)
     else:
         g = torch.zeros(0, device="cuda")
         fn = C.pearson_bwd if op == "pearson" else C.wvar_bwd
@@ -263,6 +289,11 @@ def test_workload_full_size_sampled_rows(gpu_handle, op, N):
         elif op.startswith("quant"):
             q, qs = C.quantize_rows(dev["x"], "int8" if op == "quant_int8" else "fp8", p=p, h=h)
             got = {"codes": q[ri].cpu().numpy(), "scale": qs[ri].cpu().numpy()}
+        elif op == "lnq":
+            q, qs, mu, rs = C.layernorm_fwd_fp8_out(dev["x"], torch.from_numpy(sub.gamma).cuda(),
+                                                    torch.from_numpy(sub.beta).cuda(), EPS, p=p, h=h)
+            got = {"y": oracle.decode(q[ri].cpu().numpy(), "fp8", qs[ri].cpu().numpy()), "y_scale": qs[ri],
+                   "mean": mu[ri].double().cpu().numpy(), "rstd": rs[ri].double().cpu().numpy()}
         elif op == "pearson":
             a, b = C.pearson_bwd(dev["x"], dev["y"], g, p=p, h=h)
             got = {"dx": a[ri].double().cpu().numpy(), "dy": b[ri].double().cpu().numpy()}
