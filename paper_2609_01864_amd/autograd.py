@@ -1,7 +1,10 @@
 """torch.autograd.Function wrappers over the library's forward and backward
-kernels (FP32 and BF16 I/O).  The forward saves y (softmax) or x with the FP32
-row statistics (normalisations); the backward is itself a reduction-reuse pass
-computed by the library (dx; dgamma / dbeta by column reduction)."""
+kernels (FP32 and BF16 I/O).  The forward saves y (softmax), or the logits x
+when asked to (the backward then rebuilds y inside the row: the
+softmax-logits backward of the evaluation suite, Sec. IV-A), or x with the
+FP32 row statistics (normalisations); the backward is itself a
+reduction-reuse pass computed by the library (dx; dgamma / dbeta by column
+reduction)."""
 from __future__ import annotations
 
 import torch
@@ -26,6 +29,24 @@ class SoftmaxFn(torch.autograd.Function):
     def backward(ctx, dy):
         (y,) = ctx.saved_tensors
         dx, _ = C.softmax_bwd(y, _rows(dy.contiguous().to(y.dtype)), p=ctx.plan_bwd)
+        return dx.view(dy.shape), None
+
+
+class SoftmaxLogitsFn(torch.autograd.Function):
+    """Softmax that saves its input instead of its output; the backward
+    recomputes y = softmax(x) in the same pass that forms dx."""
+
+    @staticmethod
+    def forward(ctx, x, plan=None):
+        x2 = _rows(x.contiguous())
+        y, _ = C.softmax_fwd(x2, p=plan)
+        ctx.save_for_backward(x2)
+        return y.view_as(x)
+
+    @staticmethod
+    def backward(ctx, dy):
+        (x2,) = ctx.saved_tensors
+        dx, _ = C.softmax_logits_bwd(x2, _rows(dy.contiguous().to(x2.dtype)))
         return dx.view(dy.shape), None
 
 
@@ -64,8 +85,13 @@ class RMSNormFn(torch.autograd.Function):
         return dx.view(dy.shape), dg, None, None
 
 
-def softmax(x, plan=None):
-    """Softmax over the last dimension."""
+def softmax(x, plan=None, save: str = "output"):
+    """Softmax over the last dimension.  save="logits" keeps x for the
+    backward instead of y (same memory, and x is often kept anyway)."""
+    if save == "logits":
+        return SoftmaxLogitsFn.apply(x, plan)
+    if save != "output":
+        raise ValueError(f"save must be 'output' or 'logits', not {save!r}")
     return SoftmaxFn.apply(x, plan)
 
 
