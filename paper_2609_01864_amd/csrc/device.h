@@ -174,6 +174,16 @@ template <int V> __device__ __forceinline__ void opaque(u32x4 (&d)[V]) {
     for (int j = 0; j < V; ++j) asm volatile("" : "+v"(d[j]));
 }
 
+// Orders a pass over the retained slots: the accumulators are made opaque
+// after each slot, so the scheduler cannot decode later slots ahead of earlier
+// ones and keep all of their decoded values live at once (which spilled the
+// two-input kernels).  Emits no instruction.
+__device__ __forceinline__ void keep1(float &v) { asm volatile("" : "+v"(v)); }
+template <class... T> __device__ __forceinline__ void keep_order(T &...v) {
+    int unused[] = {(keep1(v), 0)...};
+    (void)unused;
+}
+
 // -------------------------------------------------------- wave64 reduction
 // Partner value across lanes (lane ^ m) inside each 32-lane half: DPP quad
 // permutes for m = 1, 2 and ds_swizzle bit-mode xor for m = 4, 8, 16.

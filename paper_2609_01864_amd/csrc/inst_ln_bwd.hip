@@ -1,6 +1,8 @@
 // Kernel instantiations for OP_LN_BWD: the register-resident / split-row kernel
 // for every (dtype, vectors-per-thread) within the register budget, and the
-// two-pass kernel for 256- and 1024-thread workgroups.
+// two-pass kernel for 256- and 1024-thread workgroups (FP8 at 1024 threads
+// keeps 2 vectors in flight per thread: its decoded values then fit the 128
+// registers a 1024-thread workgroup allows, without spilling).
 #include "resident.h"
 #include "twopass.h"
 
@@ -27,7 +29,7 @@ const void *twopass_kernel_ln_bwd(int dt, int block) {
     } else if (block == 1024) {
         if (dt == DT_F32) return (const void *)&k_twopass<OP_LN_BWD, DT_F32, 1024, 4>;
         if (dt == DT_BF16) return (const void *)&k_twopass<OP_LN_BWD, DT_BF16, 1024, 4>;
-        if (dt == DT_FP8) return (const void *)&k_twopass<OP_LN_BWD, DT_FP8, 1024, 4>;
+        if (dt == DT_FP8) return (const void *)&k_twopass<OP_LN_BWD, DT_FP8, 1024, 2>;
     }
     return nullptr;
 }

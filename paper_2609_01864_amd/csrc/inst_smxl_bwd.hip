@@ -27,7 +27,7 @@ const void *twopass_kernel_smxl_bwd(int dt, int block) {
     } else if (block == 1024) {
         if (dt == DT_F32) return (const void *)&k_twopass<OP_SMXL_BWD, DT_F32, 1024, 4>;
         if (dt == DT_BF16) return (const void *)&k_twopass<OP_SMXL_BWD, DT_BF16, 1024, 4>;
-        if (dt == DT_FP8) return (const void *)&k_twopass<OP_SMXL_BWD, DT_FP8, 1024, 4>;
+        if (dt == DT_FP8) return (const void *)&k_twopass<OP_SMXL_BWD, DT_FP8, 1024, 2>;
     }
     return nullptr;
 }

@@ -303,6 +303,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 const bool ok = ok_of(j);
 #pragma unroll
                 for (int i = 0; i < EPV; ++i) qmax = fmaxf(qmax, ok ? q[i] : -INFINITY);
+                keep_order(qmax);
             }
             if (tail) {
                 float q[EPV];
@@ -322,6 +323,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     float e = fast_exp2(fmaf(q[i], K, -ct));
                     st[1] += ok ? e : 0.f;
                 }
+                keep_order(st[1]);
             }
             if (tail) {
                 float q[EPV];
@@ -384,6 +386,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                         s1 += d;
                         s2 = fmaf(d, d, s2);
                     }
+                    keep_order(s1, s2);
                 }
                 if (tail) {
                     float q[EPV];
@@ -417,6 +420,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     decode<DT>(d0[j], q, 1.f);
 #pragma unroll
                     for (int i = 0; i < EPV; ++i) st[0] = fmaf(q[i], q[i], st[0]);
+                    keep_order(st[0]);
                 }
                 if (tail) {
                     float q[EPV];
@@ -491,6 +495,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                                 amax = fmaxf(amax, ok ? fabsf(y[i]) : 0.f);
                                 if constexpr (YC) yc[j * EPV + i] = y[i];
                             }
+                            keep_order(amax);
                         }
                     }
                 }
@@ -546,6 +551,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 decode<DT>(d1[j], g, gs);
 #pragma unroll
                 for (int i = 0; i < EPV; ++i) st[0] = fmaf(g[i], y[i], st[0]);
+                keep_order(st[0]);
             }
             if (tail) {
                 float y[EPV], g[EPV];
@@ -623,6 +629,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                             s1 += d;
                             s2 = fmaf(d, d, s2);
                         }
+                        keep_order(s1, s2);
                     }
                     if (tail) {
                         float x[EPV];
@@ -651,6 +658,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                         decode<DT>(d0[j], x, xs);
 #pragma unroll
                         for (int i = 0; i < EPV; ++i) st[0] = fmaf(x[i], x[i], st[0]);
+                        keep_order(st[0]);
                     }
                     if (tail) {
                         float x[EPV];
@@ -697,6 +705,8 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     decode<DT>(d0[jb + u], x, xs);
                     decode<DT>(d1[jb + u], dy, gs);
                     acc(x, dy, gm[u]);
+                    if constexpr (LN) keep_order(st[0], st[LN ? 1 : 0]);
+                    else keep_order(st[0]);
                 }
             }
             if (tail) {
@@ -812,6 +822,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     st[1] += e;
                     st[2] = fmaf(e, g[i], st[2]);
                 }
+                keep_order(st[1], st[2]);
             }
             if (tail) {
                 float q[EPV], g[EPV];
@@ -878,6 +889,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 decode<DT>(d0[j], q, 1.f);
 #pragma unroll
                 for (int i = 0; i < EPV; ++i) am[0] = fmaxf(am[0], fabsf(q[i]));  // masked slots are 0
+                keep_order(am[0]);
             }
             if (tail) {
                 float q[EPV];
@@ -939,6 +951,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 decode<DT>(d0[j], x, 1.f);
                 decode<DT>(d1[j], y, 1.f);
                 acc(x, y, EPV, ok_of(j));
+                keep_order(sx, sy, sxx, syy, sxy);
             }
             if (tail) {
                 float x[EPV], y[EPV];
@@ -1016,6 +1029,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 decode<DT>(d0[j], x, 1.f);
                 decode<DT>(d1[j], w, 1.f);
                 acc(x, w, EPV);
+                keep_order(sw, swd, swdd);
             }
             if (tail) {
                 float x[EPV], w[EPV];
