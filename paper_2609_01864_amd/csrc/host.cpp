@@ -150,6 +150,7 @@ int model_waves(int k_op, int dt, int vpt) {
     int work = 64 + (dt == CREDIT_FP8_E4M3 || k_op == OP_LNQ_FWD ? 32 : 0) +
                (k_op == OP_SOFTMAX_FWD || k_op == OP_SOFTMAX_BWD ? 0 : 16);
     int w = 512 / (data + work);
+    if (int ov = wave_override(k_op, dt, vpt)) return ov;
     return std::max(1, std::min(8, w));
 }
 

@@ -59,6 +59,20 @@ constexpr int max_vpt(int op, int dt) {
          : (dt == DT_F32 ? 8 : dt == DT_BF16 ? 8 : 4);
 }
 
+// Measured exceptions to the register model below: LayerNorm backward
+// instances that run faster on MI355X with one more co-resident workgroup per
+// CU than fit their registers (the compiler spills a little): BF16 with 4
+// vectors per thread 14% faster at 3, FP8 with 2 vectors 17% faster at 3, FP32
+// with 4 vectors 6% faster at 4 (M = 2048, N = 131072).  For every other
+// instance measured, more workgroups with heavier spilling, or fewer without
+// spilling, was slower.
+constexpr int wave_override(int op, int dt, int vpt) {
+    return op != OP_LN_BWD ? 0
+         : (dt == DT_BF16 && vpt == 4) ? 3
+         : (dt == DT_FP8 && vpt == 2) ? 3
+         : (dt == DT_F32 && vpt == 4) ? 4 : 0;
+}
+
 struct RowArgs {
     const void *in0;   // x (forward, norm backward) or y (softmax backward)
     const void *in1;   // dy (backward); y (Pearson); w (weighted variance)

@@ -43,7 +43,8 @@ template <int OP, int DT, int VPT> constexpr int resident_waves() {
                          (OP == OP_SOFTMAX_FWD || OP == OP_SOFTMAX_BWD ? 0 : 16);
     static_assert(OP < OP_COUNT, "operator");
     constexpr int w = 512 / (data + work);
-    return w < 1 ? 1 : (w > 8 ? 8 : w);
+    constexpr int ov = wave_override(OP, DT, VPT);
+    return ov ? ov : (w < 1 ? 1 : (w > 8 ? 8 : w));
 }
 
 // Slots are addressed as (uniform base pointer, 32-bit per-thread byte
