@@ -158,7 +158,7 @@ def amd_delta_t(*, M: int, N: int, k: int, S: int, o: int, f: float, b_B: float,
 
 # ------------------------------------------------------------------ workloads
 def paper_workloads() -> Dict[str, Workload]:
-    """Stage structures of four of the paper's FP32 workloads (Sec. IV-A),
+    """Stage structures of five of the paper's FP32 workloads (Sec. IV-A),
     as read from their definitions.  Used to reproduce the printed traffic."""
     f = 4.0
     return {
@@ -175,6 +175,9 @@ def paper_workloads() -> Dict[str, Workload]:
         "pearson_bwd": Workload({"x": f, "y": f}, [(("x", "y"), 5)], ("x", "y"), 2 * f),
         # Row-wise int8 quantization: amax, then the int8 codes.
         "quant_int8": Workload({"x": f}, [(("x",), 1)], ("x",), 1.0),
+        # Weighted-variance backward: (W, sum w x), then sum w (x - mu)^2, then
+        # dx and dw each written by its own pass over (x, w).
+        "wvar_bwd": Workload({"x": f, "w": f}, [(("x", "w"), 2), (("x", "w"), 1)], ("x", "w", "x", "w"), 2 * f),
     }
 
 

@@ -143,3 +143,29 @@ def test_library_model_delta_matches_oracle(lib_built, op, d, M, N):
         ref = cm.delta_t(tb * w.b_reread / w.b_base, ctrl[i], 0.0, 0.0,
                          8.0 * W * (k - 1) * sum(list(w.q)[: w.stages]) / (2.4e9 * 64.0) * 1e6)
         assert math.isclose(got[i], ref, rel_tol=1e-5, abs_tol=1e-4), (k, got[i], ref)
+
+
+def test_library_workload_info_of_the_suite_workloads(lib_built):
+    # the library's byte accounting of its two-pass schedules: quantisation and
+    # Pearson reproduce the paper's printed pairs (Sec. IV-D); softmax-logits
+    # and weighted variance read their inputs once per (single) statistics
+    # stage, so their two-pass moves 20 and 24 B/elem (the paper's baselines,
+    # with three and four passes, move 28 and 40)
+    from paper_2609_01864_amd import credit as C
+
+    gold = _load("paper_traffic.json")["bytes_per_element"]
+    cases = {(C.QUANT_INT8, C.FWD): (tuple(gold["quant_int8"]), [1]),
+             (C.PEARSON, C.BWD): (tuple(gold["pearson_bwd"]), [5]),
+             (C.SOFTMAX_LOGITS, C.BWD): ((20, 12), [3]),
+             (C.WVAR, C.BWD): ((24, 16), [3]),
+             (C.LAYERNORM_FP8_OUT, C.FWD): ((13, 5), [2, 1]),
+             (C.QUANT_FP8, C.FWD): ((9, 5), [1])}
+    for (op, d), ((base, staged), q) in cases.items():
+        w = C.workload_info(op, d, C.F32)
+        assert (w.b_base, w.b_staged) == (base, staged), (op, d)
+        assert list(w.q)[:w.stages] == q, (op, d)
+    # pairs that do not exist are rejected
+    with pytest.raises(C.CreditError):
+        C.workload_info(C.PEARSON, C.FWD, C.F32)
+    with pytest.raises(C.CreditError):
+        C.workload_info(C.QUANT_INT8, C.FWD, C.FP8)
