@@ -110,7 +110,12 @@ const char *credit_version(void);
 
 /* Creates a handle bound to HIP device `device`: reads its properties, sizes
  * the persistent grids, allocates the handle's small device-side error flag.
- * The handle owns the plan cache, the selector model and timing buffers. */
+ * The handle owns the plan cache, the selector model and timing buffers.
+ * Environment read here: CREDIT_SELECTOR (learned | analytic | exhaustive |
+ * fixed | peak) sets the selector; CREDIT_FORCE_PLAN (two_pass | resident |
+ * split:<k>) is used by calls with plan == NULL wherever it is legal for the
+ * shape (elsewhere the selector decides); CREDIT_SPIN_LIMIT sets the split-row
+ * wait bound.  Unrecognised values are ignored. */
 credit_status_t credit_create(int device, credit_handle_t *h);
 credit_status_t credit_destroy(credit_handle_t h);
 

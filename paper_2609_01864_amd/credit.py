@@ -17,7 +17,8 @@ from typing import Optional, Tuple
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcredit.so")
-MODEL_PATH = os.path.join(_HERE, "models", "selector_gfx950.txt")
+# the learned selector's weights; CREDIT_MODEL_PATH overrides the installed file
+MODEL_PATH = os.environ.get("CREDIT_MODEL_PATH") or os.path.join(_HERE, "models", "selector_gfx950.txt")
 
 # enums (include/credit.h)
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_TIMEOUT, ERR_MODEL = range(7)

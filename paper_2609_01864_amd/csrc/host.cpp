@@ -184,6 +184,8 @@ struct credit_handle_s {
     unsigned *errflag = nullptr;
     credit_selector_t selector = CREDIT_SEL_FIXED;
     bool selector_set = false;
+    bool force_set = false;  // CREDIT_FORCE_PLAN: used for plan == NULL where legal
+    credit_plan_t force_plan{CREDIT_TWO_PASS, 1};
     int64_t spin_limit = 1 << 22;
     bool drop_publish = false;
     int64_t max_groups = 0;
@@ -866,6 +868,11 @@ credit_status_t learned_pick(credit_handle_t h, int k_op, int dt, int64_t M, int
 credit_status_t pick_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t *out,
                           float *pred) {
     std::lock_guard<std::recursive_mutex> g(h->lock);
+    if (h->force_set && plan_ok(h, k_op, dt, M, N, h->force_plan)) {
+        *out = h->force_plan;
+        if (pred) *pred = -1.f;
+        return CREDIT_OK;
+    }
     credit_selector_t sel = h->selector;
     if (!h->selector_set) sel = h->has_model ? CREDIT_SEL_LEARNED : CREDIT_SEL_FIXED;
     auto key = std::make_tuple(k_op, dt, (int)sel, M, N, 0);
@@ -1030,6 +1037,45 @@ const char *credit_status_string(credit_status_t s) {
 
 const char *credit_version(void) { return "credit-mi355x 0.1.0 (gfx950)"; }
 
+// Environment configuration, read once when a handle is created:
+//   CREDIT_SELECTOR    learned | analytic | exhaustive | fixed | peak
+//   CREDIT_FORCE_PLAN  two_pass | resident | split:<k>   (calls with plan == NULL
+//                      use it where it is legal for the shape)
+//   CREDIT_SPIN_LIMIT  polls before a split-row wait gives up
+// Unrecognised values are ignored.
+static void read_env(credit_handle_t h) {
+    if (const char *v = std::getenv("CREDIT_SELECTOR")) {
+        const std::string s(v);
+        const char *names[] = {"learned", "analytic", "exhaustive", "fixed", "peak"};
+        for (int i = 0; i < 5; ++i)
+            if (s == names[i]) {
+                h->selector = (credit_selector_t)i;
+                h->selector_set = true;
+            }
+    }
+    if (const char *v = std::getenv("CREDIT_FORCE_PLAN")) {
+        const std::string s(v);
+        if (s == "two_pass") {
+            h->force_plan = {CREDIT_TWO_PASS, 1};
+            h->force_set = true;
+        } else if (s == "resident") {
+            h->force_plan = {CREDIT_ROW_RESIDENT, 1};
+            h->force_set = true;
+        } else if (s.rfind("split:", 0) == 0) {
+            const int k = std::atoi(s.c_str() + 6);
+            for (int kk : kSplitKs)
+                if (kk == k) {
+                    h->force_plan = {CREDIT_SPLIT_ROW, k};
+                    h->force_set = true;
+                }
+        }
+    }
+    if (const char *v = std::getenv("CREDIT_SPIN_LIMIT")) {
+        const long long n = std::atoll(v);
+        if (n > 0) h->spin_limit = n;
+    }
+}
+
 credit_status_t credit_create(int device, credit_handle_t *out) {
     if (!out) return CREDIT_ERR_INVALID_ARG;
     *out = nullptr;
@@ -1047,6 +1093,7 @@ credit_status_t credit_create(int device, credit_handle_t *out) {
             credit_destroy(h);
             return CREDIT_ERR_HIP;
         }
+        read_env(h);
         *out = h;
         return CREDIT_OK;
     } catch (...) {
