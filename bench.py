@@ -95,9 +95,9 @@ def kernel_symbol(C, h, op_num, dt_num, M, N, p):
 def forms(C, h):
     """Cold-cache times (flush, median of 15) of the precision workload
     (softmax and LayerNorm forward, M = 4096, N in {65536, 262144}, BF16 and
-    FP8 I/O vs the FP32 two-pass kernel) and of the backward workload
-    (softmax and LayerNorm backward, M = 2048, N = 131072, FP32 and BF16)
-    with the selector's plans."""
+    FP8 I/O vs the FP32 two-pass kernel), of the backward workload (softmax
+    and LayerNorm backward, M = 2048, N = 131072, FP32 and BF16) and of the
+    LayerNorm -> e4m3 fusion, with the selector's plans."""
     out = {"precision": [], "backward": []}
     e = {C.F32: 4, C.BF16: 2, C.FP8: 1}
     for op, name in ((C.SOFTMAX, "softmax_fwd"), (C.LAYERNORM, "layernorm_fwd")):
@@ -123,6 +123,21 @@ def forms(C, h):
                                     "us": round(t, 1), "gbps": round(M * N * e[dt] * 3 / (t * 1e3), 1),
                                     "two_pass_us": round(t2, 1)})
             log(f"backward {name} {dn}: {out['backward'][-1]}")
+    # LayerNorm -> e4m3 fusion: the fused operator against LayerNorm (FP32
+    # out) followed by the row quantisation op, FP32 input, M = 4096
+    out["fusion"] = []
+    for N in (65536, 262144):
+        M = 4096
+        pf, _ = h.select(C.LAYERNORM_FP8_OUT, C.FWD, C.F32, M, N)
+        tf = h.time_plan(C.LAYERNORM_FP8_OUT, C.FWD, C.F32, M, N, pf, 15, True)
+        pl, _ = h.select(C.LAYERNORM, C.FWD, C.F32, M, N)
+        tl = h.time_plan(C.LAYERNORM, C.FWD, C.F32, M, N, pl, 15, True)
+        pq, _ = h.select(C.QUANT_FP8, C.FWD, C.F32, M, N)
+        tq = h.time_plan(C.QUANT_FP8, C.FWD, C.F32, M, N, pq, 15, True)
+        out["fusion"].append({"M": M, "N": N, "fused_plan": list(pf.as_tuple()), "fused_us": round(tf, 1),
+                              "fused_gbps": round(M * N * 5 / (tf * 1e3), 1),
+                              "unfused_us": round(tl + tq, 1), "speedup": round((tl + tq) / tf, 3)})
+        log(f"fusion N={N}: {out['fusion'][-1]}")
     return out
 
 
