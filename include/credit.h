@@ -43,6 +43,12 @@
  *   - The workspace must be zero-filled before its first use; the library
  *     keeps it valid across calls.  Two calls that may run concurrently must
  *     not share a workspace.
+ *   - Operator calls may be recorded into a HIP graph (stream capture) and
+ *     replayed: a recorded split-row launch is preceded by a one-thread kernel
+ *     that advances a device-side exchange epoch, so every replay is a new
+ *     epoch.  Make one eager call per shape first when the selector would
+ *     time kernels or run its network (plan == NULL), so that capture finds
+ *     the plan cached; operator calls record no memset nodes.
  *   - No C++ exception crosses this interface and nothing aborts.
  */
 #ifndef CREDIT_H

@@ -48,6 +48,7 @@ const void *colreduce1_kernel();
 const void *colstats_kernel(int, bool);
 const void *control_kernel();
 const void *zero_kernel();
+const void *epoch_bump_kernel();
 const void *flush_kernel();
 const void *fill_kernel();
 const void *copy_kernel();
@@ -73,9 +74,11 @@ constexpr int kMlpParams = CREDIT_NUM_FEATURES * CREDIT_MLP_HIDDEN + CREDIT_MLP_
                            CREDIT_NUM_PLANS * CREDIT_MLP_HIDDEN + CREDIT_NUM_PLANS;
 
 std::atomic<uint32_t> g_epoch{1};
+// Host-chosen exchange epochs keep the top bit clear (graph-recorded launches
+// use device-side epochs with it set) and are never 0.
 uint32_t next_epoch() {
-    uint32_t e = g_epoch.fetch_add(1);
-    while (e == 0) e = g_epoch.fetch_add(1);
+    uint32_t e = g_epoch.fetch_add(1) & 0x7fffffffu;
+    while (e == 0) e = g_epoch.fetch_add(1) & 0x7fffffffu;
     return e;
 }
 
@@ -412,6 +415,18 @@ credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void 
         if (L.k > 1) {
             a.slots = (unsigned long long *)(w + L.off_slots);
             a.epoch = next_epoch();
+            // a launch being recorded into a graph would replay with this same
+            // epoch and could then accept the previous replay's slot words:
+            // record a bump of the device-side epoch before it instead
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return CREDIT_ERR_HIP;
+            if (cs == hipStreamCaptureStatusActive) {
+                unsigned *ctr = h->errflag + 64;  // the device epoch word of the handle
+                void *bargs[] = {&ctr};
+                if (launch(epoch_bump_kernel(), 1, 64, 0, stream, bargs) != hipSuccess) return CREDIT_ERR_HIP;
+                a.epoch = 0;
+                a.epoch_ptr = ctr;
+            }
         }
         if (L.xcd) flags |= F_XCD;
         if (ncp) a.colpart = (float *)(w + L.off_colpart);

@@ -93,7 +93,8 @@ struct RowArgs {
     int k;             // split factor
     int qs;            // slot stride: statistics per stage of this operator
     int groups;        // concurrent row groups = grid / k
-    unsigned epoch;    // exchange epoch of this launch (never 0)
+    unsigned epoch;    // exchange epoch of this launch (never 0); 0: read it from epoch_ptr
+    const unsigned *epoch_ptr;  // device-side epoch (launches captured into a graph)
     unsigned spin_limit;
     float eps;
     int flags;

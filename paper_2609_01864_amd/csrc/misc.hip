@@ -78,6 +78,18 @@ __global__ __launch_bounds__(256) void k_zero(unsigned *p, int64_t n) {
 }
 const void *zero_kernel() { return (const void *)&k_zero; }
 
+// Advances the device-side exchange epoch of graph-recorded launches.  These
+// epochs have the top bit set and host-chosen epochs have it clear, so the two
+// never coincide; the 31-bit count wraps and never yields 0.
+__global__ void k_epoch_bump(unsigned *ctr) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const unsigned e = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned n = ((e + 1u) & 0x7fffffffu) | 0x80000000u;
+        __hip_atomic_store(ctr, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+const void *epoch_bump_kernel() { return (const void *)&k_epoch_bump; }
+
 // Cache flush by reading: streams n 16-byte vectors so the L2s and the
 // Infinity Cache hold clean lines of this buffer, not the operator's data
 // (a write sweep would leave dirty lines to be written back during the

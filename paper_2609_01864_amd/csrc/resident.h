@@ -1095,6 +1095,10 @@ template <int OP, int DT, int VPT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(resident_waves<OP, DT, VPT>())))
 void k_resident(RowArgs a) {
     constexpr int EPV = Io<DT>::EPV;
+    // a launch recorded in a graph takes its epoch from device memory, bumped
+    // by the kernel launched before it on every replay
+    if (a.epoch == 0u && a.epoch_ptr)
+        a.epoch = __hip_atomic_load(a.epoch_ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __shared__ float red[2 * 4 * 6];  // up to six statistics per reduction
     __shared__ float xb[kMaxK * kMaxQ];
     int c, grp;
