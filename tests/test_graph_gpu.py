@@ -56,3 +56,41 @@ def test_graph_replay_with_new_inputs(lib_built):
         assert h.check_errors() == C.OK
     finally:
         h.close()
+
+
+def test_graph_replay_backward_with_column_reduction(lib_built):
+    # LayerNorm backward recorded with its dgamma / dbeta reduction kernels
+    h = C.Handle(0, load_default_model=False)
+    M, N = 600, 4096
+    g32, _ = I.norm_params(N, seed=41)
+    gamma = torch.from_numpy(g32).cuda()
+    sx = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    sdy = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    side = torch.cuda.Stream()
+    try:
+        sx.copy_(torch.from_numpy(I.norm_rows(M, N, seed=40).astype(np.float32)))
+        sdy.normal_()
+        with torch.cuda.stream(side):
+            C.layernorm_bwd(sx, sdy, gamma, None, None, EPS, p=C.plan("split", 4), h=h)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            dx, _, dg, db = C.layernorm_bwd(sx, sdy, gamma, None, None, EPS, p=C.plan("split", 4), h=h)
+        for rep in range(3):
+            x32 = I.norm_rows(M, N, seed=200 + rep).astype(np.float32)
+            dy32 = I.normal_rows(M, N, seed=200 + rep, tensor=1).astype(np.float32)
+            sx.copy_(torch.from_numpy(x32))
+            sdy.copy_(torch.from_numpy(dy32))
+            print(f"[graph] backward replay {rep}", flush=True)
+            graph.replay()
+            torch.cuda.synchronize()
+            x64, dy64 = x32.astype(np.float64), dy32.astype(np.float64)
+            dxr, dgr, dbr = oracle.layernorm_bwd(x64, dy64, g32.astype(np.float64), EPS)
+            assert np.max(np.abs(dx.double().cpu().numpy() - dxr)) <= 1e-5 * max(1.0, np.abs(dxr).max())
+            _, mu, rs = oracle.layernorm_fwd(x64, g32.astype(np.float64), np.zeros(N), EPS)
+            xh = (x64 - mu[:, None]) * rs[:, None]
+            assert np.all(np.abs(dg.double().cpu().numpy() - dgr) <= 1e-5 * np.abs(dy64 * xh).sum(0) + 1e-6)
+            assert np.all(np.abs(db.double().cpu().numpy() - dbr) <= 1e-5 * np.abs(dy64).sum(0) + 1e-6)
+        assert h.check_errors() == C.OK
+    finally:
+        h.close()

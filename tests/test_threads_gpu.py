@@ -1,0 +1,49 @@
+"""One handle used from several host threads at once, each on its own HIP
+stream (and so its own workspace): results match the oracle and no exchange
+wait times out."""
+import threading
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2609_01864_amd import credit as C
+from paper_2609_01864_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def test_concurrent_calls_from_threads(lib_built):
+    h = C.Handle(0, load_default_model=False)
+    M, N = 40, 25000
+    errors = []
+
+    def work(tid):
+        try:
+            s = torch.cuda.Stream()
+            x32 = I.softmax_rows(M, N, seed=300 + tid).astype(np.float32)
+            ref = oracle.softmax_fwd(x32.astype(np.float64))
+            with torch.cuda.stream(s):
+                x = torch.from_numpy(x32).cuda()
+                for it in range(6):
+                    plan = C.plan("split", 2 if (it + tid) % 2 else 4)
+                    y, _ = C.softmax_fwd(x, p=plan, h=h)
+                    s.synchronize()
+                    err = np.max(np.abs(y.double().cpu().numpy() - ref))
+                    if err > 2e-6:
+                        errors.append((tid, it, err))
+        except Exception as e:  # reported below
+            errors.append((tid, repr(e)))
+
+    threads = [threading.Thread(target=work, args=(t,)) for t in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    try:
+        assert not any(t.is_alive() for t in threads)
+        assert not errors, errors
+        assert h.check_errors() == C.OK
+    finally:
+        h.close()
