@@ -103,8 +103,7 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
     int parity = 0;
     const int64_t N = a.N;
     const float invN = 1.f / (float)N;
-    const bool al0 = a.flags & F_ALIGN0, al1 = a.flags & F_ALIGN1, alo = a.flags & F_ALIGNO,
-               alp = a.flags & F_ALIGNP;
+    const bool al0 = a.flags & F_ALIGN0, al1 = a.flags & F_ALIGN1, alp = a.flags & F_ALIGNP;
 
     for (int64_t row = blockIdx.x; row < a.M; row += gridDim.x) {
         const char *r0 = (const char *)a.in0 + row * a.ld0 * B;
