@@ -34,11 +34,21 @@ template <int OP> struct OpTraits {
     static constexpr int NCP = OP == OP_LN_BWD ? 2 : (OP == OP_RMS_BWD ? 1 : 0);  // column partials
 };
 
+// FP32 registers per thread that hold the normalised row y of a norm forward
+// with FP8 output between its amax stage and its quantize pass (0: y is
+// recomputed from x, gamma and beta instead).
+template <int OP, int DT, int VPT> constexpr int yc_regs() {
+    constexpr bool f8o = (DT == DT_FP8 && (OP == OP_LN_FWD || OP == OP_RMS_FWD)) || OP == OP_LNQ_FWD;
+    return f8o && VPT * Io<DT>::EPV <= kYcMax ? VPT * Io<DT>::EPV : 0;
+}
+
 // Waves per SIMD the register allocation must allow (each workgroup is one
 // wave per SIMD, so this is also the workgroups per CU): the retained data,
-// the FP32 column partials and the working registers within 512 / W VGPRs.
+// the FP32 column partials, a kept y and the working registers within
+// 512 / W VGPRs.
 template <int OP, int DT, int VPT> constexpr int resident_waves() {
-    constexpr int data = VPT * 4 * (OpTraits<OP>::TWO ? 2 : 1) + OpTraits<OP>::NCP * VPT * Io<DT>::EPV;
+    constexpr int data = VPT * 4 * (OpTraits<OP>::TWO ? 2 : 1) + OpTraits<OP>::NCP * VPT * Io<DT>::EPV +
+                         yc_regs<OP, DT, VPT>();
     constexpr int work = 64 + (DT == DT_FP8 || OP == OP_LNQ_FWD ? 32 : 0) +
                          (OP == OP_SOFTMAX_FWD || OP == OP_SOFTMAX_BWD ? 0 : 16);
     static_assert(OP < OP_COUNT, "operator");
@@ -446,9 +456,10 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                         y[i] = q[i] * amul * g[i];
                 }
             };
-            // FP8 output with a small slice keeps y in registers between the
-            // amax stage and the quantize pass: gamma / beta are read once
-            constexpr bool YC = F8O && VPT * EPV <= 32;
+            // FP8 output keeps y in registers between the amax stage and the
+            // quantize pass when the slice holds at most kYcMax values per
+            // thread: gamma / beta are then read once instead of twice
+            constexpr bool YC = yc_regs<OP, DT, VPT>() > 0;
             float yc[YC ? VPT * EPV : 1], yct[YC ? EPV : 1];
             // the trailing partial vector of the output
             auto store_out_tail = [&](const float *y, float oinv) {
