@@ -208,8 +208,13 @@ def suite(C, h, copy_gbps):
 
         cross[name] = {"measured": nstar("measured_profitable"), "model": nstar("predicted_profitable"),
                        "peak_model": nstar("predicted_profitable_peak")}
+    # the headline of Sec. IV-B: geometric-mean speedup of the best split-row
+    # plan over the best single-workgroup plan at the widest swept N
+    nmax = max(SUITE_N)
+    sp = [r["speedup_vs_best_single"] for r in rows if r["N"] == nmax and "speedup_vs_best_single" in r]
+    gm = round(math.exp(sum(math.log(x) for x in sp) / len(sp)), 3) if sp else None
     return {"rows": rows, "profitability_pairs": n, "model_correct": acc, "peak_model_correct": acc_peak,
-            "crossover_N": cross}
+            "crossover_N": cross, "geomean_speedup_at_widest_N": {"N": nmax, "workloads": len(sp), "speedup": gm}}
 
 
 def traffic_for(kernel_key: str):

@@ -23,6 +23,7 @@ constexpr int kMaxQ = 5;       // statistics per stage (Pearson co-moments)
 constexpr int kMaxK = 32;      // largest split factor
 constexpr int kBlockThreads = 256;  // threads per row-resident / split-row workgroup
 constexpr int kYcMax = 128;   // most FP32 y values per thread kept across an FP8-output amax stage
+constexpr int kEcMax = 64;    // most FP32 exponentials per thread kept by the FP8 softmax forward
 
 enum KFlags {
     F_ALIGN0 = 1,              // rows of in0 start 16-byte aligned

@@ -42,13 +42,22 @@ template <int OP, int DT, int VPT> constexpr int yc_regs() {
     return f8o && VPT * Io<DT>::EPV <= kYcMax ? VPT * Io<DT>::EPV : 0;
 }
 
+// FP32 registers per thread that hold an FP8 softmax row's decoded values,
+// then their exponentials, across the three passes of the forward (0: the
+// packed row is decoded and exponentiated again in the output pass).  Up to
+// kEcMax values: beyond that the registers cost more occupancy than the
+// saved decode and exponential gain.
+template <int OP, int DT, int VPT> constexpr int ec_regs() {
+    return OP == OP_SOFTMAX_FWD && DT == DT_FP8 && VPT * Io<DT>::EPV <= kEcMax ? VPT * Io<DT>::EPV : 0;
+}
+
 // Waves per SIMD the register allocation must allow (each workgroup is one
 // wave per SIMD, so this is also the workgroups per CU): the retained data,
 // the FP32 column partials, a kept y and the working registers within
 // 512 / W VGPRs.
 template <int OP, int DT, int VPT> constexpr int resident_waves() {
     constexpr int data = VPT * 4 * (OpTraits<OP>::TWO ? 2 : 1) + OpTraits<OP>::NCP * VPT * Io<DT>::EPV +
-                         yc_regs<OP, DT, VPT>();
+                         yc_regs<OP, DT, VPT>() + ec_regs<OP, DT, VPT>();
     constexpr int work = 64 + (DT == DT_FP8 || OP == OP_LNQ_FWD ? 32 : 0) +
                          (OP == OP_SOFTMAX_FWD || OP == OP_SOFTMAX_BWD ? 0 : 16);
     static_assert(OP < OP_COUNT, "operator");
@@ -305,6 +314,12 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
         if constexpr (OP == OP_SOFTMAX_FWD) {
             // Base-2 statistics: K = scale * log2(e); c = max(q * K); s = sum 2^(q*K - c).
             const float K = (FP8 ? a.s0[row] : 1.f) * kLog2e;
+            // EC: the slice is decoded once into ec, which then holds
+            // e = 2^(q*K - ct) about the thread's own maximum ct; the output is
+            // e * 2^(ct - c) * omul, one multiply per element instead of a
+            // second decode and exponential.
+            constexpr bool EC = ec_regs<OP, DT, VPT>() > 0;
+            float ec[EC ? VPT * EPV : 1];
             float qmax = -INFINITY;
             fresh();
 #pragma unroll
@@ -313,7 +328,10 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 decode<DT>(d0[j], q, 1.f);
                 const bool ok = ok_of(j);
 #pragma unroll
-                for (int i = 0; i < EPV; ++i) qmax = fmaxf(qmax, ok ? q[i] : -INFINITY);
+                for (int i = 0; i < EPV; ++i) {
+                    qmax = fmaxf(qmax, ok ? q[i] : -INFINITY);
+                    if constexpr (EC) ec[j * EPV + i] = q[i];
+                }
                 keep_order(qmax);
             }
             if (tail) {
@@ -327,11 +345,12 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
 #pragma unroll
             for (int j = 0; j < VPT; ++j) {
                 float q[EPV];
-                decode<DT>(d0[j], q, 1.f);
+                if constexpr (!EC) decode<DT>(d0[j], q, 1.f);
                 const bool ok = ok_of(j);
 #pragma unroll
                 for (int i = 0; i < EPV; ++i) {
-                    float e = fast_exp2(fmaf(q[i], K, -ct));
+                    float e = fast_exp2(fmaf(EC ? ec[j * EPV + i] : q[i], K, -ct));
+                    if constexpr (EC) ec[j * EPV + i] = e;
                     st[1] += ok ? e : 0.f;
                 }
                 keep_order(st[1]);
@@ -348,14 +367,26 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             // code of element i is 448 * 2^(q*K - c) (no second statistics stage).
             const float omul = FP8 ? kFp8Max : inv_s;
             if (FP8 && writer) a.so[row] = inv_s / kFp8Max;
-            fresh();
+            if constexpr (EC) {
+                // a thread without data (ct = 0) stores nothing: its factor is unused
+                const float f = fast_exp2(ct - cmax) * omul;
 #pragma unroll
-            for (int j = 0; j < VPT; ++j) {
-                float q[EPV], y[EPV];
-                decode<DT>(d0[j], q, 1.f);
+                for (int j = 0; j < VPT; ++j) {
+                    float y[EPV];
 #pragma unroll
-                for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, -cmax)) * omul;
-                ST(j, encode<DT>(y, 1.f));
+                    for (int i = 0; i < EPV; ++i) y[i] = ec[j * EPV + i] * f;
+                    ST(j, encode<DT>(y, 1.f));
+                }
+            } else {
+                fresh();
+#pragma unroll
+                for (int j = 0; j < VPT; ++j) {
+                    float q[EPV], y[EPV];
+                    decode<DT>(d0[j], q, 1.f);
+#pragma unroll
+                    for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, -cmax)) * omul;
+                    ST(j, encode<DT>(y, 1.f));
+                }
             }
             if (tail) {
                 float q[EPV], y[EPV];
