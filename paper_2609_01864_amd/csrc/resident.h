@@ -317,8 +317,10 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             // EC: the slice is decoded once into ec, which then holds
             // e = 2^(q*K - ct) about the thread's own maximum ct; the output is
             // e * 2^(ct - c) * omul, one multiply per element instead of a
-            // second decode and exponential.
+            // second decode and exponential.  ECI: an FP32 slice is its own
+            // decoded form, so e overwrites it in place (no extra registers).
             constexpr bool EC = ec_regs<OP, DT, VPT>() > 0;
+            constexpr bool ECI = DT == DT_F32;
             float ec[EC ? VPT * EPV : 1];
             float qmax = -INFINITY;
             fresh();
@@ -344,15 +346,18 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             fresh();
 #pragma unroll
             for (int j = 0; j < VPT; ++j) {
-                float q[EPV];
+                float q[EPV], ev[EPV];
                 if constexpr (!EC) decode<DT>(d0[j], q, 1.f);
                 const bool ok = ok_of(j);
 #pragma unroll
                 for (int i = 0; i < EPV; ++i) {
-                    float e = fast_exp2(fmaf(EC ? ec[j * EPV + i] : q[i], K, -ct));
-                    if constexpr (EC) ec[j * EPV + i] = e;
-                    st[1] += ok ? e : 0.f;
+                    ev[i] = fast_exp2(fmaf(EC ? ec[j * EPV + i] : q[i], K, -ct));
+                    if constexpr (EC) ec[j * EPV + i] = ev[i];
+                    st[1] += ok ? ev[i] : 0.f;
                 }
+                if constexpr (ECI)
+                    d0[j] = u32x4{__float_as_uint(ev[0]), __float_as_uint(ev[1]), __float_as_uint(ev[2]),
+                                  __float_as_uint(ev[3])};
                 keep_order(st[1]);
             }
             if (tail) {
@@ -367,14 +372,19 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             // code of element i is 448 * 2^(q*K - c) (no second statistics stage).
             const float omul = FP8 ? kFp8Max : inv_s;
             if (FP8 && writer) a.so[row] = inv_s / kFp8Max;
-            if constexpr (EC) {
+            if constexpr (EC || ECI) {
                 // a thread without data (ct = 0) stores nothing: its factor is unused
                 const float f = fast_exp2(ct - cmax) * omul;
 #pragma unroll
                 for (int j = 0; j < VPT; ++j) {
                     float y[EPV];
+                    if constexpr (EC) {
 #pragma unroll
-                    for (int i = 0; i < EPV; ++i) y[i] = ec[j * EPV + i] * f;
+                        for (int i = 0; i < EPV; ++i) y[i] = ec[j * EPV + i] * f;
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) y[i] = __uint_as_float(d0[j][i]) * f;
+                    }
                     ST(j, encode<DT>(y, 1.f));
                 }
             } else {
