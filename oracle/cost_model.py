@@ -12,6 +12,9 @@ no fitting and no shortcuts:
 * ``t_deposit``           the non-overlapped deposit residual [T_w - T_input]^+
 * ``delta_t``             Eq. (9)
 * ``crossover_width``     N*, the smallest tested width with a profitable legal P
+* ``structural_screen``   the rules that reject a pattern before any timing
+                          (elementwise and scalar-output reductions, scans,
+                          selection / stencil kernels)
 
 ``Workload`` is the static description the model consumes (b_B, b_keep,
 b_reread, q_l, L), derived here from a stage structure: which input tensors each
@@ -132,6 +135,36 @@ def crossover_width(widths: Sequence[int], legal_and_profitable) -> int | None:
         if legal_and_profitable(N):
             return N
     return None
+
+
+def structural_screen(w: Workload, barriers_per_row=None, remote_state_per_row=None,
+                      widths: Sequence[int] = (4096, 65536)) -> List[str]:
+    """The model's structural rejection rules (end of Sec. III-D, and the
+    negative controls of Sec. IV-D): a pattern is outside the reduction-reuse
+    class, whatever its width, when
+
+    * it rereads nothing (b_reread = 0: elementwise maps, reductions with a
+      scalar output), so there is no source time to recover;
+    * its synchronisation count per row K grows with N (scans: an ordered
+      carry crosses every slice), so widening adds cost faster than it can
+      be amortised;
+    * the state exchanged per row grows with N (selection, stencils: halos or
+      candidate lists instead of sum q_l compact scalars).
+
+    barriers_per_row(N) and remote_state_per_row(N) default to the paper's
+    protocol, K = 2L and sum q_l, which do not depend on N.  Returns the
+    reasons for rejection; an empty list means the pattern is in the class."""
+    K = barriers_per_row or (lambda N: 2 * w.L)
+    R = remote_state_per_row or (lambda N: sum(w.q))
+    lo, hi = min(widths), max(widths)
+    reasons = []
+    if w.b_reread() <= 0.0:
+        reasons.append("no reread to recover")
+    if K(hi) > K(lo):
+        reasons.append("synchronisation grows with N")
+    if R(hi) > R(lo):
+        reasons.append("exchanged state grows with N")
+    return reasons
 
 
 # ------------------------------------------------------------------ MI355X form

@@ -169,3 +169,45 @@ def test_library_workload_info_of_the_suite_workloads(lib_built):
         C.workload_info(C.PEARSON, C.FWD, C.F32)
     with pytest.raises(C.CreditError):
         C.workload_info(C.QUANT_INT8, C.FWD, C.FP8)
+
+
+def test_structural_screen_accepts_the_suite_and_rejects_negative_controls():
+    # every workload of the paper's suite is in the reduction-reuse class:
+    # a reread to recover, K = 2L and sum q_l compact scalars per row
+    for name, w in cm.paper_workloads().items():
+        assert cm.structural_screen(w) == [], name
+    for name, w in cm.credit_workloads(4.0).items():
+        assert cm.structural_screen(w) == [], name
+    # negative controls (Sec. IV-D): an elementwise map and a scalar-output
+    # row reduction read every input once in either schedule
+    ew = cm.Workload({"x": 4.0}, [], ("x",), 4.0)
+    rowsum = cm.Workload({"x": 4.0}, [(("x",), 1)], (), 0.0)
+    assert ew.b_reread() == 0.0 and rowsum.b_reread() == 0.0
+    assert cm.structural_screen(ew) == ["no reread to recover"]
+    assert cm.structural_screen(rowsum) == ["no reread to recover"]
+    # a row scan with a sliced layout: one ordered carry hand-off per slice of
+    # a fixed 4096 elements, so its synchronisation count grows with N
+    scan = cm.Workload({"x": 4.0}, [(("x",), 1)], ("x",), 4.0)
+    assert cm.structural_screen(scan, barriers_per_row=lambda N: 2 * (N // 4096)) == \
+        ["synchronisation grows with N"]
+    # a top-k selection exchanging k candidates per slice, k proportional to N
+    topk = cm.Workload({"x": 4.0}, [(("x",), 1)], ("x",), 4.0)
+    assert cm.structural_screen(topk, remote_state_per_row=lambda N: N // 64) == \
+        ["exchanged state grows with N"]
+
+
+def test_library_operators_are_all_in_the_class(lib_built):
+    # every operator the library splits has a reread to recover, so Eq. (7)
+    # gives T_save > 0 for it; a zero would make the analytic model reject it
+    from paper_2609_01864_amd import credit as C
+
+    pairs = [(C.SOFTMAX, C.FWD), (C.LAYERNORM, C.FWD), (C.RMSNORM, C.FWD), (C.SOFTMAX, C.BWD),
+             (C.LAYERNORM, C.BWD), (C.RMSNORM, C.BWD), (C.SOFTMAX_LOGITS, C.BWD), (C.QUANT_INT8, C.FWD),
+             (C.QUANT_FP8, C.FWD), (C.PEARSON, C.BWD), (C.WVAR, C.BWD), (C.LAYERNORM_FP8_OUT, C.FWD)]
+    for op, d in pairs:
+        for dt in (C.F32, C.BF16, C.FP8):
+            try:
+                w = C.workload_info(op, d, dt)
+            except C.CreditError:
+                continue  # (op, dtype) pair that does not exist
+            assert w.b_base > w.b_staged > 0, (op, d, dt)
