@@ -147,6 +147,46 @@ SUITE = (("layernorm_bwd", "LAYERNORM", "BWD", 2048), ("wvar_bwd", "WVAR", "BWD"
 SUITE_N = (4096, 8192, 16384, 32768, 65536)
 
 
+TRAFFIC_REPS = 3
+TRAFFIC_CALIB_BYTES = 1 << 30
+
+
+def traffic_suite(C, h):
+    """Launch sequence for the traffic validation of Sec. IV-E (the paper's
+    DRAM-traffic figure at N = 65536): for every suite workload, the two-pass
+    baseline and the fastest split-row plan, each launched 3 + TRAFFIC_REPS
+    times with a cache flush before each launch, behind a marker (a small
+    copy-kernel launch whose size names the block).  Meant to run under
+    `rocprofv3 --pmc FETCH_SIZE` (then WRITE_SIZE); the JSON it prints tells
+    the summary which block is which.  A 1 GiB copy first calibrates the
+    counters."""
+    N = max(SUITE_N)
+    best = {}
+    for name, opn, dirn, M in SUITE:  # pick the split plan before any marker
+        op, d = getattr(C, opn), getattr(C, dirn)
+        ts = {}
+        for k in (2, 4, 8, 16, 32):
+            p = C.plan("split", k)
+            if h.plan_legal(op, d, C.F32, M, N, p):
+                ts[k] = h.time_plan(op, d, C.F32, M, N, p, 7, True)
+        best[name] = min(ts, key=ts.get)
+        log(f"traffic: {name} fastest split k={best[name]}")
+    h.copy_bandwidth(TRAFFIC_CALIB_BYTES, 1)
+    blocks = []
+    for name, opn, dirn, M in SUITE:
+        op, d = getattr(C, opn), getattr(C, dirn)
+        w = C.workload_info(op, d, C.F32)
+        for variant, k in (("two_pass", 1), ("split", best[name])):
+            marker = 4096 * (1 + len(blocks))
+            h.copy_bandwidth(marker, 1)
+            h.time_plan(op, d, C.F32, M, N, C.plan(variant, k), TRAFFIC_REPS, True)
+            blocks.append({"workload": name, "M": M, "N": N, "variant": variant, "k": k,
+                           "marker_threads": marker // 16, "launches": 3 + TRAFFIC_REPS,
+                           "algorithmic_bytes": M * N * (w.b_base if variant == "two_pass" else w.b_staged)})
+    return {"mode": "traffic_suite", "source_hash": source_hash(), "copy_kernel_bytes": TRAFFIC_CALIB_BYTES,
+            "copy_threads": TRAFFIC_CALIB_BYTES // 16, "blocks": blocks}
+
+
 def suite(C, h, copy_gbps):
     """The paper's evaluation suite on this GPU (Sec. IV-A: FP32 input, M =
     2048 for LayerNorm and 4096 otherwise, N in 4K..64K; LayerNorm backward
@@ -244,6 +284,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / backward workloads")
     ap.add_argument("--no-suite", action="store_true", help="skip the evaluation-suite workloads")
     ap.add_argument("--selector", default="auto", choices=["auto", "learned", "analytic", "fixed", "exhaustive"])
+    ap.add_argument("--traffic-suite", action="store_true",
+                    help="only the launch sequence of the suite traffic validation (run under rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the row kernels shard over rows with no communication, "
@@ -263,6 +305,9 @@ def main():
            "exhaustive": C.SEL_EXHAUSTIVE}[sel_name]
     h.set_selector(sel)
     log(f"selector={sel_name} model_loaded={h.model_loaded}")
+    if args.traffic_suite:
+        print(json.dumps(traffic_suite(C, h)), flush=True)
+        return
 
     # ---------------------------------------------------------------- inputs
     gen = torch.Generator(device=dev)

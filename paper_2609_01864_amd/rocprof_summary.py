@@ -12,6 +12,14 @@ traffic  HBM bytes per launch of the dominant kernel from two `--pmc` runs
          (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each divided by the
          counter-per-byte factor the same counter reads on the plain copy
          kernel (k_copy moves a known number of bytes each way).
+suite    the same two counters over the launch sequence of
+         `bench.py --traffic-suite` (two-pass and fastest split-row plan of
+         every evaluation-suite workload at N = 65536, each block behind a
+         marker copy launch): bytes per operator call, summed over every
+         kernel the call launches, and the reduction of the split-row plan.
+
+    python -m paper_2609_01864_amd.rocprof_summary suite --fetch DIR --write DIR --bench META.json \
+        --json profiles/suite_traffic.json --out profiles/Z.md
 """
 from __future__ import annotations
 
@@ -20,6 +28,7 @@ import csv
 import glob
 import json
 import os
+import re
 import statistics
 import sys
 
@@ -152,9 +161,81 @@ def traffic(args):
     print("\n".join(lines))
 
 
+_OP_KERNEL = re.compile(r"credit::k_(twopass|resident|colreduce1|colreduce|colstats)\b")
+_MAIN_KERNEL = re.compile(r"credit::k_(twopass|resident)\b")
+
+
+def _counter_seq(d: str, counter: str):
+    """(kernel name, grid, value) of every dispatch, in dispatch order."""
+    rows = _rows(_find(d, "counter_collection.csv"))
+    out = []
+    for r in rows:
+        if (r.get("Counter_Name") or r.get("counter_name")) != counter:
+            continue
+        out.append((int(r.get("Dispatch_Id") or 0), r.get("Kernel_Name") or "", _grid(r),
+                    float(r.get("Counter_Value") or r.get("value"))))
+    out.sort()
+    return [(n, g, v) for _, n, g, v in out]
+
+
+def suite(args):
+    meta = json.loads(open(args.bench).read().strip().splitlines()[-1])
+    assert meta.get("mode") == "traffic_suite", "not a --traffic-suite run"
+    blocks = meta["blocks"]
+    by_marker = {b["marker_threads"]: i for i, b in enumerate(blocks)}
+    per = {}
+    for counter, d in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
+        seq = _counter_seq(d, counter)
+        cp = [v for n, g, v in seq if "credit::k_copy" in n and g == meta["copy_threads"]]
+        if not cp:
+            raise SystemExit(f"{counter}: no calibration copy dispatch")
+        factor = statistics.median(cp) * 1024.0 / meta["copy_kernel_bytes"]
+        sums = [0.0] * len(blocks)
+        mains = [0] * len(blocks)
+        cur = None
+        for n, g, v in seq:
+            if "credit::k_copy" in n:
+                cur = by_marker.get(g, cur if g != meta["copy_threads"] else None)
+                continue
+            if cur is None or not _OP_KERNEL.search(n):
+                continue
+            sums[cur] += v
+            mains[cur] += 1 if _MAIN_KERNEL.search(n) else 0
+        for i, b in enumerate(blocks):
+            if mains[i] != b["launches"]:
+                raise SystemExit(f"{counter}: block {i} ({b['workload']} {b['variant']}) has {mains[i]} main "
+                                 f"dispatches, expected {b['launches']}")
+            per.setdefault(i, {})[counter] = sums[i] / mains[i] * 1024.0 / factor
+        per.setdefault("factor", {})[counter] = factor
+    rows = []
+    for i, b in enumerate(blocks):
+        tot = per[i]["FETCH_SIZE"] + per[i]["WRITE_SIZE"]
+        rows.append(dict(b, fetch_bytes=round(per[i]["FETCH_SIZE"]), write_bytes=round(per[i]["WRITE_SIZE"]),
+                         bytes_per_call=round(tot), ratio_to_algorithmic=round(tot / b["algorithmic_bytes"], 4)))
+    out = {"source_hash": meta.get("source_hash"), "factors": per["factor"], "rows": rows}
+    json.dump(out, open(args.json, "w"), indent=1)
+    lines = [f"# HBM traffic of the evaluation-suite workloads: {args.title}", "",
+             f"Commands: `{args.command}` with `--pmc FETCH_SIZE` and, separately, `--pmc WRITE_SIZE`", "",
+             "Bytes per operator call, summed over every kernel the call launches (row kernel and, for",
+             "LayerNorm backward, the column reductions), averaged over the calls of its block; counters",
+             f"divided by what they read per byte on a 1 GiB copy (FETCH {per['factor']['FETCH_SIZE']:.4f}, "
+             f"WRITE {per['factor']['WRITE_SIZE']:.4f}).", "",
+             "| workload | M x N | plan | HBM bytes/call | algorithmic | ratio | reduction vs two-pass |",
+             "|---|---|---|---:|---:|---:|---:|"]
+    for i in range(0, len(rows), 2):
+        tp, sp = rows[i], rows[i + 1]
+        red = 1.0 - sp["bytes_per_call"] / tp["bytes_per_call"]
+        for r, rr in ((tp, ""), (sp, f"{100 * red:.1f}%")):
+            plan = "two-pass" if r["variant"] == "two_pass" else f"split k={r['k']}"
+            lines.append(f"| {r['workload']} | {r['M']} x {r['N']} | {plan} | {r['bytes_per_call']:.4e} | "
+                         f"{r['algorithmic_bytes']:.4e} | {r['ratio_to_algorithmic']:.3f} | {rr} |")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "traffic"])
+    ap.add_argument("mode", choices=["trace", "traffic", "suite"])
     ap.add_argument("--trace")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
@@ -164,7 +245,7 @@ def main(argv=None):
     ap.add_argument("--title", default="")
     ap.add_argument("--command", default="python3 bench.py")
     args = ap.parse_args(argv)
-    trace(args) if args.mode == "trace" else traffic(args)
+    {"trace": trace, "traffic": traffic, "suite": suite}[args.mode](args)
 
 
 if __name__ == "__main__":

@@ -1,0 +1,76 @@
+"""The rocprofv3 summaries on synthetic counter files: calibration against the
+copy kernel, the dominant launch's bytes, and the block bookkeeping of the
+evaluation-suite traffic run (markers, every kernel of a call, call counts)."""
+import csv
+import json
+import os
+
+import pytest
+
+from paper_2609_01864_amd import rocprof_summary as R
+
+HDR = ["Dispatch_Id", "Grid_Size", "Kernel_Name", "Counter_Name", "Counter_Value"]
+
+
+def _write(d, counter, rows):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "x_counter_collection.csv"), "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(HDR)
+        for i, (name, grid, kib) in enumerate(rows):
+            w.writerow([i + 1, grid, name, counter, kib])
+
+
+def test_suite_traffic_blocks(tmp_path):
+    calib = 1 << 30
+    meta = {"mode": "traffic_suite", "source_hash": "abc", "copy_kernel_bytes": calib, "copy_threads": calib // 16,
+            "blocks": [{"workload": "w", "M": 4, "N": 8, "variant": "two_pass", "k": 1, "marker_threads": 256,
+                        "launches": 2, "algorithmic_bytes": 3000.0},
+                       {"workload": "w", "M": 4, "N": 8, "variant": "split", "k": 4, "marker_threads": 512,
+                        "launches": 2, "algorithmic_bytes": 2000.0}]}
+    mp = tmp_path / "meta.json"
+    mp.write_text(json.dumps(meta) + "\n")
+    copy = "credit::k_copy(u32x4 const*, u32x4*, long)"
+    tp = "void credit::k_twopass<9, 0, 256>(credit::RowArgs)"
+    rs = "void credit::k_resident<9, 0, 4>(credit::RowArgs)"
+    cr = "credit::k_colreduce(float const*, float*, int, long)"
+    fl = "credit::k_flush_read(u32x4 const*, long, unsigned int*)"
+
+    def seq(f):  # FETCH counts 0.5 KiB per KiB moved, WRITE 1.0
+        kib = lambda b: f * b / 1024.0
+        return [(copy, calib // 16, kib(calib)),                     # calibration
+                (rs, 1024, 999.0),                                  # before any marker: ignored
+                (copy, 256, 1.0), (copy, 256, 1.0),                 # marker of block 0
+                (fl, 99, 5000.0), (tp, 4096, kib(2900)), (fl, 99, 5000.0), (tp, 4096, kib(3100)),
+                (copy, 512, 1.0),                                   # marker of block 1
+                (fl, 99, 5000.0), (rs, 1024, kib(1800)), (cr, 64, kib(200)),
+                (fl, 99, 5000.0), (rs, 1024, kib(1800)), (cr, 64, kib(200))]
+
+    _write(tmp_path / "f", "FETCH_SIZE", seq(0.5))
+    _write(tmp_path / "w", "WRITE_SIZE", seq(1.0))
+    out = tmp_path / "s.json"
+    R.main(["suite", "--fetch", str(tmp_path / "f"), "--write", str(tmp_path / "w"), "--bench", str(mp),
+            "--json", str(out), "--out", str(tmp_path / "s.md")])
+    rows = json.load(open(out))["rows"]
+    # each counter recovers the bytes of one call: 3000 (two-pass), 2000 (split
+    # row kernel 1800 + column reduction 200), once per counter
+    assert rows[0]["fetch_bytes"] == 3000 and rows[0]["write_bytes"] == 3000
+    assert rows[1]["fetch_bytes"] == 2000 and rows[1]["write_bytes"] == 2000
+    assert rows[1]["ratio_to_algorithmic"] == pytest.approx(2.0)
+    assert "33.3%" in (tmp_path / "s.md").read_text()
+
+
+def test_suite_traffic_rejects_a_missing_call(tmp_path):
+    calib = 1 << 30
+    meta = {"mode": "traffic_suite", "copy_kernel_bytes": calib, "copy_threads": calib // 16,
+            "blocks": [{"workload": "w", "M": 1, "N": 1, "variant": "two_pass", "k": 1, "marker_threads": 256,
+                        "launches": 3, "algorithmic_bytes": 1.0}]}
+    mp = tmp_path / "meta.json"
+    mp.write_text(json.dumps(meta) + "\n")
+    rows = [("credit::k_copy(x)", calib // 16, 512.0), ("credit::k_copy(x)", 256, 1.0),
+            ("void credit::k_twopass<0, 0, 256>(credit::RowArgs)", 8, 1.0)]
+    _write(tmp_path / "f", "FETCH_SIZE", rows)
+    _write(tmp_path / "w", "WRITE_SIZE", rows)
+    with pytest.raises(SystemExit):
+        R.main(["suite", "--fetch", str(tmp_path / "f"), "--write", str(tmp_path / "w"), "--bench", str(mp),
+                "--json", str(tmp_path / "s.json"), "--out", str(tmp_path / "s.md")])
