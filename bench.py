@@ -283,7 +283,7 @@ def main():
     ap.add_argument("--no-regret", action="store_true", help="skip exhaustive timing of all plans")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / backward workloads")
     ap.add_argument("--no-suite", action="store_true", help="skip the evaluation-suite workloads")
-    ap.add_argument("--selector", default="auto", choices=["auto", "learned", "analytic", "fixed", "exhaustive"])
+    ap.add_argument("--selector", default="auto", choices=["auto", "learned", "learned_timed", "analytic", "fixed", "exhaustive"])
     ap.add_argument("--traffic-suite", action="store_true",
                     help="only the launch sequence of the suite traffic validation (run under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -300,9 +300,9 @@ def main():
     h = C.Handle(0)
     sel_name = args.selector
     if sel_name == "auto":
-        sel_name = "learned" if h.model_loaded else "analytic"
-    sel = {"learned": C.SEL_LEARNED, "analytic": C.SEL_ANALYTIC, "fixed": C.SEL_FIXED,
-           "exhaustive": C.SEL_EXHAUSTIVE}[sel_name]
+        sel_name = "learned_timed" if h.model_loaded else "analytic"
+    sel = {"learned": C.SEL_LEARNED, "learned_timed": C.SEL_LEARNED_TIMED, "analytic": C.SEL_ANALYTIC,
+           "fixed": C.SEL_FIXED, "exhaustive": C.SEL_EXHAUSTIVE}[sel_name]
     h.set_selector(sel)
     log(f"selector={sel_name} model_loaded={h.model_loaded}")
     if args.traffic_suite:
@@ -420,6 +420,12 @@ def main():
             r["best_plan"] = [int(best[0].variant), int(best[0].k)]
             r["regret"] = round(tp / best[1] - 1.0, 4)
             regrets.append(tp / best[1])
+            if h.model_loaded:  # the network's own first choice, before any timing
+                h.set_selector(C.SEL_LEARNED)
+                pu = h.select(o, C.FWD, C.F32, M_ROWS, r["N"])[0]
+                h.set_selector(sel)
+                r["learned_untimed_plan"] = [int(pu.variant), int(pu.k)]
+                r["learned_untimed_regret"] = round(times[f"{pu.variant},{pu.k}"] / best[1] - 1.0, 4)
             log(f"{r['op']} N={r['N']}: times {times} pick {r['plan']} regret {r['regret']:+.3f}")
     copy_gbps = h.copy_bandwidth(1 << 30, 15)
     log(f"copy kernel: {copy_gbps:.1f} GB/s")
@@ -455,6 +461,9 @@ def main():
         "cpu_baseline": cpu,
         "regret_geomean": round(math.exp(sum(math.log(x) for x in regrets) / len(regrets)) - 1.0, 4)
         if regrets else None,
+        "regret_geomean_learned_untimed": round(math.exp(sum(math.log(1.0 + r["learned_untimed_regret"])
+                                                             for r in per_shape) / len(per_shape)) - 1.0, 4)
+        if per_shape and all("learned_untimed_regret" in r for r in per_shape) else None,
         "copy_kernel_gbps": round(copy_gbps, 1),
         "copy_kernel_bytes": 1 << 30,
         "per_shape": per_shape,

@@ -96,7 +96,9 @@ typedef enum {
     CREDIT_SEL_ANALYTIC = 1,   /* Eq. (9) with one timing of the baseline (Eq. (7)) */
     CREDIT_SEL_EXHAUSTIVE = 2, /* time every legal plan, keep the fastest           */
     CREDIT_SEL_FIXED = 3,      /* resident if it fits, else smallest legal k, else two-pass */
-    CREDIT_SEL_PEAK = 4        /* Eq. (9) with the baseline priced at calibrated copy bandwidth */
+    CREDIT_SEL_PEAK = 4,       /* Eq. (9) with the baseline priced at calibrated copy bandwidth */
+    CREDIT_SEL_LEARNED_TIMED = 5 /* the MLP's two best legal plans, each timed once (cold,
+                                    median of 7), the faster kept; falls back to ANALYTIC */
 } credit_selector_t;
 
 /* variant and split factor; k == 1 for CREDIT_TWO_PASS and CREDIT_ROW_RESIDENT,
@@ -365,9 +367,13 @@ credit_status_t credit_probe_primitives(credit_handle_t h, int reps, credit_prim
 /* Plan of class c in [0, CREDIT_NUM_PLANS). */
 credit_status_t credit_plan_of_class(int32_t c, credit_plan_t *out);
 
-/* The 12 raw (unstandardized) features of a shape.  Defined for the softmax,
- * LayerNorm and RMSNorm operators (the learned selector's domain; the other
- * operators are planned by the analytic model): CREDIT_ERR_UNSUPPORTED else. */
+/* The 12 raw (unstandardized) features of a shape: operator one-hot (3),
+ * is-backward, dtype one-hot (3), log2 M, log2 N, aligned rows (1 when N * e
+ * is a multiple of 16 bytes, so rows of ld = N from an aligned base hold
+ * whole aligned vectors, else 0), log2 of the operator's total I/O bytes and
+ * log2(M / CUs) clamped at 0.  Defined for the softmax, LayerNorm and RMSNorm
+ * operators (the learned selector's domain; the other operators are planned
+ * by the analytic model): CREDIT_ERR_UNSUPPORTED else. */
 credit_status_t credit_features(credit_op_t op, credit_dir_t dir, credit_dtype_t dt, int64_t M,
                                 int64_t N, float *feat12);
 

@@ -27,7 +27,7 @@ SOFTMAX, LAYERNORM, RMSNORM = 0, 1, 2
 SOFTMAX_LOGITS, QUANT_INT8, QUANT_FP8, PEARSON, WVAR, LAYERNORM_FP8_OUT = 3, 4, 5, 6, 7, 8
 FWD, BWD = 0, 1
 TWO_PASS, ROW_RESIDENT, SPLIT_ROW = 0, 1, 2
-SEL_LEARNED, SEL_ANALYTIC, SEL_EXHAUSTIVE, SEL_FIXED, SEL_PEAK = range(5)
+SEL_LEARNED, SEL_ANALYTIC, SEL_EXHAUSTIVE, SEL_FIXED, SEL_PEAK, SEL_LEARNED_TIMED = range(6)
 OPT_SPIN_LIMIT, OPT_TEST_DROP_PUBLISH, OPT_MAX_GROUPS = range(3)
 NUM_FEATURES, NUM_PLANS, MLP_HIDDEN = 12, 7, 64
 DTYPE_NAMES = {"f32": F32, "bf16": BF16, "fp8": FP8}

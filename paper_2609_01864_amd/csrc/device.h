@@ -22,6 +22,12 @@ template <> struct Io<DT_BF16> { static constexpr int EPV = 8, BYTES = 2; };
 template <> struct Io<DT_FP8> { static constexpr int EPV = 16, BYTES = 1; };
 
 __device__ __forceinline__ float fast_exp2(float v) { return __builtin_amdgcn_exp2f(v); }
+// The hardware exp2 flushes results below 2^-126 to zero.  Output passes
+// evaluate 2^(v + kExpShift) and fold 2^-kExpShift into their per-row factor,
+// so outputs down to 2^-158 keep their denormal value (v <= 0 there, so the
+// shifted exponential cannot overflow); the factor's product is exact.
+constexpr float kExpShift = 32.f;
+constexpr float kExpUnshift = 0x1p-32f;
 
 // ------------------------------------------------------------------ codecs
 // Decode one 16-byte vector into EPV floats; FP8 codes are multiplied by the

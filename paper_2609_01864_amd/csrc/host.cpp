@@ -783,6 +783,12 @@ credit_plan_t fixed_rule(credit_handle_t h, int k_op, int dt, int64_t M, int64_t
     return class_plan(0);
 }
 
+// Shape features of the learned selector.  f[9] says whether rows of
+// ld = N from an aligned base hold whole, 16-byte aligned vectors (N * e a
+// multiple of 16): such rows take the unmasked, aligned row loop, up to 1.4x
+// faster than ragged rows of the same size, which shifts the best plan.  The
+// pick depends on (op, dtype, M, N) only, so a workspace sized with an
+// automatic plan always fits the launch that follows.
 void features(int k_op, int dt, int64_t M, int64_t N, float *f) {
     const int op = k_op % 3, dir = k_op / 3;
     for (int i = 0; i < CREDIT_NUM_FEATURES; ++i) f[i] = 0.f;
@@ -793,7 +799,7 @@ void features(int k_op, int dt, int64_t M, int64_t N, float *f) {
     const int nin = two_inputs(k_op) ? 2 : 1;
     f[7] = (float)std::log2((double)std::max<int64_t>(M, 1));
     f[8] = (float)std::log2((double)N);
-    f[9] = (float)std::log2((double)N * e * nin);
+    f[9] = ((int64_t)(N * e) % 16 == 0) ? 1.f : 0.f;
     f[10] = (float)std::log2((double)std::max<int64_t>(M, 1) * N * e * (nin + 1));
     f[11] = (float)std::log2(std::max(1.0, (double)M / kDefaultCUs));
 }
@@ -869,18 +875,35 @@ credit_status_t exhaustive_pick(credit_handle_t h, int k_op, int dt, int64_t M, 
     return std::isfinite(best) ? CREDIT_OK : CREDIT_ERR_UNSUPPORTED;
 }
 
-credit_status_t learned_pick(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t *out) {
+// The network's best legal plan, or with `timed` its two best legal plans,
+// each timed (cold cache, median of 7), keeping the faster: the model as a
+// screen that narrows the search, the final choice by measurement.
+credit_status_t learned_pick(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, bool timed,
+                             credit_plan_t *out, float *pred) {
     float f[CREDIT_NUM_FEATURES], logits[CREDIT_NUM_PLANS];
     features(k_op, dt, M, N, f);
     credit_status_t st = mlp_predict_dev(h, f, 1, logits);
     if (st != CREDIT_OK) return st;
-    int best = -1;
+    int best = -1, second = -1;
     for (int c = 0; c < CREDIT_NUM_PLANS; ++c) {
         if (!plan_ok(h, k_op, dt, M, N, class_plan(c))) continue;
-        if (best < 0 || logits[c] > logits[best]) best = c;
+        if (best < 0 || logits[c] > logits[best]) {
+            second = best;
+            best = c;
+        } else if (second < 0 || logits[c] > logits[second]) {
+            second = c;
+        }
     }
     if (best < 0) return CREDIT_ERR_UNSUPPORTED;
     *out = class_plan(best);
+    if (!timed || second < 0) return CREDIT_OK;
+    float t1 = 0.f, t2 = 0.f;
+    st = time_plan(h, k_op, dt, M, N, class_plan(best), 7, 1, &t1);
+    if (st != CREDIT_OK) return st;
+    st = time_plan(h, k_op, dt, M, N, class_plan(second), 7, 1, &t2);
+    if (st != CREDIT_OK) return st;
+    if (t2 < t1) *out = class_plan(second);
+    if (pred) *pred = std::min(t1, t2);
     return CREDIT_OK;
 }
 
@@ -908,8 +931,9 @@ credit_status_t pick_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_
     case CREDIT_SEL_LEARNED:
         // the learned selector's features cover the softmax / LayerNorm /
         // RMSNorm operators; the other workloads use the analytic model
+    case CREDIT_SEL_LEARNED_TIMED:
         if (h->has_model && core_op(k_op)) {
-            st = learned_pick(h, k_op, dt, M, N, out);
+            st = learned_pick(h, k_op, dt, M, N, sel == CREDIT_SEL_LEARNED_TIMED, out, pred);
             if (st == CREDIT_OK) break;
         }
         st = analytic_pick(h, k_op, dt, M, N, false, out, pred);
@@ -1134,7 +1158,7 @@ credit_status_t credit_destroy(credit_handle_t h) {
 }
 
 credit_status_t credit_set_selector(credit_handle_t h, credit_selector_t s) {
-    if (!h || (int)s < 0 || (int)s > 4) return CREDIT_ERR_INVALID_ARG;
+    if (!h || (int)s < 0 || (int)s > (int)CREDIT_SEL_LEARNED_TIMED) return CREDIT_ERR_INVALID_ARG;
     std::lock_guard<std::recursive_mutex> g(h->lock);
     h->selector = s;
     h->selector_set = true;
@@ -1693,7 +1717,7 @@ credit_status_t credit_mlp_predict(credit_handle_t h, const float *feats, int64_
     }
 }
 
-static const char *kSchema = "f12-h64-h64-c7-v1";
+static const char *kSchema = "f12-h64-h64-c7-v2";
 
 credit_status_t credit_save_model(credit_handle_t h, const char *path) {
     if (!h || !path) return CREDIT_ERR_INVALID_ARG;

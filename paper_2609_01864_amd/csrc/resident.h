@@ -371,10 +371,11 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             // FP8 output: the largest output is 2^0 * inv_s, so amax = inv_s and the
             // code of element i is 448 * 2^(q*K - c) (no second statistics stage).
             const float omul = FP8 ? kFp8Max : inv_s;
+            const float csh = kExpShift - cmax, omuls = omul * kExpUnshift;
             if (FP8 && writer) a.so[row] = inv_s / kFp8Max;
             if constexpr (EC || ECI) {
                 // a thread without data (ct = 0) stores nothing: its factor is unused
-                const float f = fast_exp2(ct - cmax) * omul;
+                const float f = fast_exp2(ct + csh) * omuls;
 #pragma unroll
                 for (int j = 0; j < VPT; ++j) {
                     float y[EPV];
@@ -394,7 +395,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     float q[EPV], y[EPV];
                     decode<DT>(d0[j], q, 1.f);
 #pragma unroll
-                    for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, -cmax)) * omul;
+                    for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, csh)) * omuls;
                     ST(j, encode<DT>(y, 1.f));
                 }
             }
@@ -402,7 +403,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 float q[EPV], y[EPV];
                 decode<DT>(t0, q, 1.f);
 #pragma unroll
-                for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, -cmax)) * omul;
+                for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, csh)) * omuls;
                 store_vec<DT>(orow, tcol, tn, false, encode<DT>(y, 1.f));
             }
         } else if constexpr (OP == OP_LN_FWD || OP == OP_RMS_FWD || OP == OP_LNQ_FWD) {
@@ -890,12 +891,13 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             row_reduce<3>(st, MergeSoftmax3(), a, row, 0, c, red, xb, parity);
             const float cmax = st[0], inv_s = 1.f / st[1];
             const float cdot = st[2] * inv_s;
+            const float csh = kExpShift - cmax, invs_s = inv_s * kExpUnshift;
             auto h = [&](u32x4 xv, u32x4 gv, float *dx) {
                 float q[EPV], g[EPV];
                 decode<DT>(xv, q, 1.f);
                 decode<DT>(gv, g, gs);
 #pragma unroll
-                for (int i = 0; i < EPV; ++i) dx[i] = fast_exp2(fmaf(q[i], K, -cmax)) * inv_s * (g[i] - cdot);
+                for (int i = 0; i < EPV; ++i) dx[i] = fast_exp2(fmaf(q[i], K, csh)) * invs_s * (g[i] - cdot);
             };
             float oinv = 1.f;
             if constexpr (FP8) {

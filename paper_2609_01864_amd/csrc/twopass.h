@@ -135,13 +135,14 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
             block_reduce<NW, 2>(st, MergeSoftmax(), red, parity);
             const float cmax = st[0], inv_s = 1.f / st[1];
             const float omul = FP8 ? kFp8Max : inv_s;
+            const float csh = kExpShift - cmax, omuls = omul * kExpUnshift;
             if (FP8 && writer) a.so[row] = inv_s / kFp8Max;
             stream_row<DT, BLOCK, U, true>(r0, nullptr, N, al0, al1, [&](int64_t v, u32x4 d, u32x4, int nv) {
                 if (nv == 0) return;
                 float q[EPV], y[EPV];
                 decode<DT>(d, q, 1.f);
 #pragma unroll
-                for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, -cmax)) * omul;
+                for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, csh)) * omuls;
                 row_store<DT>(orow, v, nv, encode<DT>(y, 1.f));
             });
         } else if constexpr (OP == OP_LN_FWD || OP == OP_RMS_FWD || OP == OP_LN_BWD || OP == OP_RMS_BWD ||
@@ -329,12 +330,13 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
             });
             block_reduce<NW, 3>(st, MergeSoftmax3(), red, parity);
             const float cmax = st[0], inv_s = 1.f / st[1], cdot = st[2] * inv_s;
+            const float csh = kExpShift - cmax, invs_s = inv_s * kExpUnshift;
             auto h = [&](u32x4 xv, u32x4 gv, float *dx) {
                 float q[EPV], g[EPV];
                 decode<DT>(xv, q, 1.f);
                 decode<DT>(gv, g, gs);
 #pragma unroll
-                for (int i = 0; i < EPV; ++i) dx[i] = fast_exp2(fmaf(q[i], K, -cmax)) * inv_s * (g[i] - cdot);
+                for (int i = 0; i < EPV; ++i) dx[i] = fast_exp2(fmaf(q[i], K, csh)) * invs_s * (g[i] - cdot);
             };
             float oinv = 1.f;
             if constexpr (FP8) {

@@ -57,8 +57,11 @@ def test_plan_classes_and_features(lib_built):
     assert plans == [(0, 1), (1, 1), (2, 2), (2, 4), (2, 8), (2, 16), (2, 32)]
     f = C.features(C.LAYERNORM, C.BWD, C.BF16, 2048, 131072)
     assert list(f[:7]) == [0, 1, 0, 1, 0, 1, 0]
-    assert f[7] == 11 and f[8] == 17 and f[9] == np.log2(131072 * 2 * 2)
+    assert f[7] == 11 and f[8] == 17 and f[9] == 1  # 131072 BF16 values: whole 16-byte vectors
     assert np.isclose(f[10], np.log2(2048 * 131072 * 2 * 3)) and f[11] == 3
+    assert C.features(C.LAYERNORM, C.BWD, C.BF16, 2048, 131071)[9] == 0
+    assert C.features(C.SOFTMAX, C.FWD, C.FP8, 3, 4096 + 16)[9] == 1
+    assert C.features(C.SOFTMAX, C.FWD, C.F32, 3, 4096 + 2)[9] == 0
 
 
 def test_host_legality_follows_capacity(lib_built):

@@ -86,3 +86,28 @@ def test_model_file_round_trip_and_rejection(gpu_handle, tmp_path):
     assert gpu_handle.load_model(bad) == C.ERR_MODEL
     assert gpu_handle.load_model(str(tmp_path / "missing.txt")) == C.ERR_MODEL
     # without a model the default selection falls back to the fixed rule
+
+
+def test_timed_learned_selector_keeps_the_faster_of_the_two_best(lib_built):
+    # the shipped model's two highest-scoring legal plans are timed once; the
+    # pick is one of them, and the faster one by the library's own timing
+    h = C.Handle(0)
+    try:
+        assert h.model_loaded
+        M, N = 1024, 524288
+        op = C.LAYERNORM
+        f = C.features(op, C.FWD, C.F32, M, N)
+        lg = h.mlp_predict(f[None, :])[0]
+        legal = [c for c in range(NC) if h.plan_legal(op, C.FWD, C.F32, M, N, C.plan_of_class(c))]
+        top2 = sorted(legal, key=lambda c: -lg[c])[:2]
+        h.set_selector(C.SEL_LEARNED)
+        assert h.select(op, C.FWD, C.F32, M, N)[0].as_tuple() == C.plan_of_class(top2[0]).as_tuple()
+        h.set_selector(C.SEL_LEARNED_TIMED)
+        p, pred = h.select(op, C.FWD, C.F32, M, N)
+        assert p.as_tuple() in [C.plan_of_class(c).as_tuple() for c in top2]
+        assert pred > 0
+        # other operators fall back to the analytic model, which also predicts a time
+        q, _ = h.select(C.QUANT_INT8, C.FWD, C.F32, 4096, 65536)
+        assert h.plan_legal(C.QUANT_INT8, C.FWD, C.F32, 4096, 65536, q)
+    finally:
+        h.close()

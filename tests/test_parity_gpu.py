@@ -124,3 +124,35 @@ def test_illegal_plan_and_bad_arguments_are_rejected(gpu_handle):
     s = L.credit_softmax_fwd(gpu_handle.ptr, 4, 40000, C.F32, x.data_ptr(), 40000, None, y.data_ptr(), 40000, None,
                              None, None, 0, None)
     assert s == C.ERR_WORKSPACE
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("N", [3001, 20011])
+def test_softmax_slices_far_below_the_row_maximum(gpu_handle, dtype, N):
+    # Rows whose slices have maxima far below the row's: a ramp over the row
+    # (each thread's own maximum differs from the row maximum by up to ~170 in
+    # the base-2 exponent), its mirror, a row whose maximum sits in the last
+    # (ragged) vector, a constant row and a row of one spike over a flat floor.
+    # The forward keeps 2^(x K - c_t) about each thread's maximum and rescales
+    # by 2^(c_t - c); outputs that underflow must underflow as in the oracle.
+    from paper_2609_01864_amd import inputs as I
+
+    import oracle
+
+    M = 5
+    t = np.linspace(0.0, 1.0, N)
+    x = np.stack([60.0 - 120.0 * t, -60.0 + 120.0 * t, np.where(np.arange(N) == N - 1, 30.0, -30.0 * t),
+                  np.full(N, 7.0), np.where(np.arange(N) == N // 3, 20.0, 0.0)])
+    if dtype == "fp8":
+        x = x * (40.0 / 60.0)  # e4m3 codes with the per-row scale of the precision workload
+    case = Case("softmax_fwd", dtype, M, N, seed=3)
+    case.raw = {"x": I.store(x, dtype)}
+    case.vals = {k: oracle.decode(r, dtype, s) for k, (r, s) in case.raw.items()}
+    ref = case.reference()
+    print(f"[parity] softmax ramps {dtype} N={N}", flush=True)
+    for p in legal_plans(gpu_handle, "softmax_fwd", dtype, M, N):
+        out = case.run(gpu_handle, p, ref=ref)
+        try:
+            check_case(case, out, ref)
+        except AssertionError as e:
+            raise AssertionError(f"{p}: {e}") from None
