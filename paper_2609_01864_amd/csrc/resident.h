@@ -746,6 +746,10 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     }
                 }
             };
+            // GI (FP32): the statistics pass also adds the column partials and
+            // overwrites the resident dy with g = dy * gamma, so the output pass
+            // reads no gamma and needs no second product
+            constexpr bool GI = DT == DT_F32;
             fresh();
 #pragma unroll
             for (int jb = 0; jb < VPT; jb += GB) {
@@ -755,10 +759,30 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 for (int u = 0; u < GB; ++u) PAR(a.gamma, jb + u, gm[u]);
 #pragma unroll
                 for (int u = 0; u < GB; ++u) {
+                    const int j = jb + u;
                     float x[EPV], dy[EPV];
-                    decode<DT>(d0[jb + u], x, xs);
-                    decode<DT>(d1[jb + u], dy, gs);
-                    acc(x, dy, gm[u]);
+                    decode<DT>(d0[j], x, xs);
+                    decode<DT>(d1[j], dy, gs);
+                    if constexpr (GI) {
+                        float g[EPV];
+#pragma unroll
+                        for (int i = 0; i < EPV; ++i) {  // masked slots: x = dy = 0, adding 0
+                            float xh = (x[i] - mean) * rstd;
+                            g[i] = dy[i] * gm[u][i];
+                            if constexpr (LN) {
+                                st[0] += g[i];
+                                st[1] = fmaf(g[i], xh, st[1]);
+                            } else {
+                                st[0] = fmaf(g[i], xh, st[0]);
+                            }
+                            cp[0][j * EPV + i] = fmaf(dy[i], xh, cp[0][j * EPV + i]);
+                            if constexpr (LN) cp[NCP - 1][j * EPV + i] += dy[i];
+                        }
+                        d1[j] = u32x4{__float_as_uint(g[0]), __float_as_uint(g[1]), __float_as_uint(g[2]),
+                                      __float_as_uint(g[3])};
+                    } else {
+                        acc(x, dy, gm[u]);
+                    }
                     if constexpr (LN) keep_order(st[0], st[LN ? 1 : 0]);
                     else keep_order(st[0]);
                 }
@@ -782,8 +806,21 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             };
             auto out_pass = [&](bool store, float oinv, float &amax) {
                 fresh();
+                if constexpr (GI) {
 #pragma unroll
-                for (int jb = 0; jb < VPT; jb += GB) {
+                    for (int j = 0; j < VPT; ++j) {
+                        float x[EPV], dx[EPV];
+                        decode<DT>(d0[j], x, xs);
+#pragma unroll
+                        for (int i = 0; i < EPV; ++i) {
+                            float xh = (x[i] - mean) * rstd;
+                            dx[i] = rstd * (__uint_as_float(d1[j][i]) - c1 - xh * c2);
+                        }
+                        ST(j, encode<DT>(dx, oinv));
+                    }
+                }
+#pragma unroll
+                for (int jb = 0; jb < (GI ? 0 : VPT); jb += GB) {
                     __builtin_amdgcn_sched_barrier(0);
                     float gm[GB][EPV];
 #pragma unroll
