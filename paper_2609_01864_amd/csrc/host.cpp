@@ -154,6 +154,8 @@ int model_waves(int k_op, int dt, int vpt) {
     if (f8o && vpt * dt_epv(dt) <= kYcMax) data += vpt * dt_epv(dt);  // y kept across the amax stage
     if (k_op == OP_SOFTMAX_FWD && dt == CREDIT_FP8_E4M3 && vpt * dt_epv(dt) <= kEcMax)
         data += vpt * dt_epv(dt);  // decoded values, then exponentials, kept across the passes
+    if ((k_op == OP_LN_BWD || k_op == OP_RMS_BWD) && dt == CREDIT_BF16 && vpt <= 2)
+        data += vpt * dt_epv(dt);  // g = dy * gamma kept between the passes
     int work = 64 + (dt == CREDIT_FP8_E4M3 || k_op == OP_LNQ_FWD ? 32 : 0) +
                (k_op == OP_SOFTMAX_FWD || k_op == OP_SOFTMAX_BWD ? 0 : 16);
     int w = 512 / (data + work);

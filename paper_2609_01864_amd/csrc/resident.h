@@ -51,13 +51,21 @@ template <int OP, int DT, int VPT> constexpr int ec_regs() {
     return OP == OP_SOFTMAX_FWD && DT == DT_FP8 && VPT * Io<DT>::EPV <= kEcMax ? VPT * Io<DT>::EPV : 0;
 }
 
+// FP32 registers per thread that hold g = dy * gamma of a BF16 LayerNorm /
+// RMSNorm backward between its statistics and output passes (slices of up to
+// two vectors; 0 otherwise: FP32 keeps g in place of dy, wider BF16 slices
+// reload gamma).
+template <int OP, int DT, int VPT> constexpr int gk_regs() {
+    return (OP == OP_LN_BWD || OP == OP_RMS_BWD) && DT == DT_BF16 && VPT <= 2 ? VPT * Io<DT>::EPV : 0;
+}
+
 // Waves per SIMD the register allocation must allow (each workgroup is one
 // wave per SIMD, so this is also the workgroups per CU): the retained data,
 // the FP32 column partials, a kept y and the working registers within
 // 512 / W VGPRs.
 template <int OP, int DT, int VPT> constexpr int resident_waves() {
     constexpr int data = VPT * 4 * (OpTraits<OP>::TWO ? 2 : 1) + OpTraits<OP>::NCP * VPT * Io<DT>::EPV +
-                         yc_regs<OP, DT, VPT>() + ec_regs<OP, DT, VPT>();
+                         yc_regs<OP, DT, VPT>() + ec_regs<OP, DT, VPT>() + gk_regs<OP, DT, VPT>();
     constexpr int work = 64 + (DT == DT_FP8 || OP == OP_LNQ_FWD ? 32 : 0) +
                          (OP == OP_SOFTMAX_FWD || OP == OP_SOFTMAX_BWD ? 0 : 16);
     static_assert(OP < OP_COUNT, "operator");
@@ -746,10 +754,14 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     }
                 }
             };
-            // GI (FP32): the statistics pass also adds the column partials and
-            // overwrites the resident dy with g = dy * gamma, so the output pass
-            // reads no gamma and needs no second product
-            constexpr bool GI = DT == DT_F32;
+            // GI: the statistics pass also adds the column partials and keeps
+            // g = dy * gamma, so the output pass reads no gamma and needs no
+            // second product.  FP32 overwrites the resident dy with g; BF16
+            // slices of up to two vectors keep g in registers of their own
+            // (gk_regs; larger slices would lose a workgroup per CU).
+            constexpr bool GK = gk_regs<OP, DT, VPT>() > 0;
+            constexpr bool GI = DT == DT_F32 || GK;
+            float gk[GK ? VPT * EPV : 1];
             fresh();
 #pragma unroll
             for (int jb = 0; jb < VPT; jb += GB) {
@@ -778,8 +790,13 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                             cp[0][j * EPV + i] = fmaf(dy[i], xh, cp[0][j * EPV + i]);
                             if constexpr (LN) cp[NCP - 1][j * EPV + i] += dy[i];
                         }
-                        d1[j] = u32x4{__float_as_uint(g[0]), __float_as_uint(g[1]), __float_as_uint(g[2]),
-                                      __float_as_uint(g[3])};
+                        if constexpr (GK) {
+#pragma unroll
+                            for (int i = 0; i < EPV; ++i) gk[j * EPV + i] = g[i];
+                        } else {
+                            d1[j] = u32x4{__float_as_uint(g[0]), __float_as_uint(g[1]), __float_as_uint(g[2]),
+                                          __float_as_uint(g[3])};
+                        }
                     } else {
                         acc(x, dy, gm[u]);
                     }
@@ -814,7 +831,10 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
 #pragma unroll
                         for (int i = 0; i < EPV; ++i) {
                             float xh = (x[i] - mean) * rstd;
-                            dx[i] = rstd * (__uint_as_float(d1[j][i]) - c1 - xh * c2);
+                            float gv;
+                            if constexpr (GK) gv = gk[j * EPV + i];
+                            else gv = __uint_as_float(d1[j][i]);
+                            dx[i] = rstd * (gv - c1 - xh * c2);
                         }
                         ST(j, encode<DT>(dx, oinv));
                     }
