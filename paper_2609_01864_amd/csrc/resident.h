@@ -11,7 +11,8 @@
 // Eq. (5)).  It then applies h to its own retained slice and writes it.  The
 // workgroup is persistent: row group `grp` processes rows grp, grp + groups, ...
 //
-// Slot j of thread t holds vector j * 256 + t of the slice.  Two row loops
+// Slot j of thread t holds vector j * 256 + t of the slice (rotated by the row
+// group for the operators that read gamma / beta, see sv below).  Two row loops
 // exist, chosen once per workgroup (the choice is uniform, and both contain
 // workgroup barriers):
 //   AL && FULLS   every slot of every thread is a full, 16-byte aligned vector:
@@ -221,8 +222,21 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
     int parity = 0;
     const int tid = threadIdx.x;
     const float invN = 1.f / (float)a.N;
-    auto ok_of = [&](int j) -> bool { return FULLS || (int64_t)(j * kBlock + tid) < sl.nfv; };
-    auto col_of = [&](int j) -> int64_t { return sl.c0 + (int64_t)(j * kBlock + tid) * EPV; };
+    // Slot j holds vector sv(j) * 256 + tid of the slice.  Operators that
+    // read gamma / beta rotate the slot order by the row group (fixed for the
+    // workgroup, so column partials stay per slot across rows): the
+    // workgroups sharing an XCD then stream the same parameter columns at
+    // different moments instead of in lockstep (1.5-2% on FP32 LayerNorm
+    // forward; FP8 rows, whose slices are short, measured 1% slower).
+    constexpr bool ROT = DT != DT_FP8 && (OP == OP_LN_FWD || OP == OP_RMS_FWD || OP == OP_LNQ_FWD ||
+                                          OP == OP_LN_BWD || OP == OP_RMS_BWD);
+    const int rot = ROT ? grp % VPT : 0;
+    auto sv = [&](int j) -> int {
+        const int r = j + rot;
+        return r >= VPT ? r - VPT : r;
+    };
+    auto ok_of = [&](int j) -> bool { return FULLS || (int64_t)(sv(j) * kBlock + tid) < sl.nfv; };
+    auto col_of = [&](int j) -> int64_t { return sl.c0 + (int64_t)(sv(j) * kBlock + tid) * EPV; };
     const bool tail = !FULLS && sl.tail_n > 0 && tid == sl.owner;
     const int tn = sl.tail_n;
     const int64_t tcol = sl.c0 + sl.nfv * EPV;
@@ -268,19 +282,19 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
         // masked slots re-read the slice's first vector (only when nfv >= 1);
         // their data is zeroed before use and their stores are skipped
         auto doff = [&](int j) -> uint32_t {
-            return (FULLS || ok_of(j)) ? toff + (uint32_t)j * (kBlock * 16u) : 0u;
+            return (FULLS || ok_of(j)) ? toff + (uint32_t)sv(j) * (kBlock * 16u) : 0u;
         };
         auto pofs = [&](int j) -> uint32_t {
-            return (FULLS || ok_of(j)) ? poff + (uint32_t)j * (kBlock * EPV * 4u) : 0u;
+            return (FULLS || ok_of(j)) ? poff + (uint32_t)sv(j) * (kBlock * EPV * 4u) : 0u;
         };
         auto ST = [&](int j, u32x4 v) {
-            if (FULLS || ok_of(j)) vstore_nt<AL>(bo, toff + (uint32_t)j * (kBlock * 16u), v);
+            if (FULLS || ok_of(j)) vstore_nt<AL>(bo, toff + (uint32_t)sv(j) * (kBlock * 16u), v);
         };
         auto ST1 = [&](int j, u32x4 v) {
-            if (FULLS || ok_of(j)) vstore_nt<AL>(bo1, toff + (uint32_t)j * (kBlock * 16u), v);
+            if (FULLS || ok_of(j)) vstore_nt<AL>(bo1, toff + (uint32_t)sv(j) * (kBlock * 16u), v);
         };
         auto QST = [&](int j, const unsigned *w) {
-            if (FULLS || ok_of(j)) bstore_nt<EPV, AL>(bo, qoff + (uint32_t)j * (uint32_t)(kBlock * EPV), w);
+            if (FULLS || ok_of(j)) bstore_nt<EPV, AL>(bo, qoff + (uint32_t)sv(j) * (uint32_t)(kBlock * EPV), w);
         };
         auto PAR = [&](const float *p, int j, float *out) { load_params_v<DT, AL>(p + sl.c0, pofs(j), out); };
         u32x4 d0[VPT];
