@@ -1,0 +1,46 @@
+"""Selector dataset plumbing on the CPU: the shape sampler (stratification,
+the aligned set, resumable prefixes), feature recomputation on load, soft
+targets and the stratified split."""
+import json
+import math
+
+import numpy as np
+
+from paper_2609_01864_amd import credit as C
+from paper_2609_01864_amd import tune as T
+
+
+def test_sampler_is_stratified_bounded_and_resumable(lib_built):
+    a = T.sample_shapes(360)
+    assert a[:180] == T.sample_shapes(180)  # a longer run extends a shorter one
+    combos = {(s["op"], s["dir"], s["dt"]) for s in a}
+    assert len(combos) == 18
+    for s in a:
+        assert 1 <= s["M"] <= 16384 and 1024 <= s["N"] <= 4194304
+        assert T.io_bytes(s["op"], s["dir"], s["dt"], s["M"], s["N"]) <= T.MAX_IO_BYTES
+    al = T.sample_shapes(180, seed=5, align=64)
+    assert all(s["N"] % 64 == 0 and s["N"] >= 1024 for s in al)
+    assert {T.key_of(s) for s in al}.isdisjoint({T.key_of(s) for s in a})
+
+
+def test_load_recomputes_features_and_targets(lib_built, tmp_path):
+    rec = {"op": C.LAYERNORM, "dir": C.FWD, "dt": C.F32, "M": 1024, "N": 8192, "legal": [0, 1, 2],
+           "times": {"0": 20.0, "1": 15.0, "2": 21.0}, "ctrl": {"1": 5.0}, "feats": [0.0] * 12}
+    path = tmp_path / "t.jsonl"
+    path.write_text(json.dumps(rec) + "\n")
+    r = T.load(str(path))[0]
+    assert np.allclose(r["feats"], C.features(C.LAYERNORM, C.FWD, C.F32, 1024, 8192))
+    assert r["feats"][9] == 1.0  # whole aligned vectors
+    t, m = T.soft_targets(r)
+    assert list(m[:3]) == [1, 1, 1] and m[3:].sum() == 0
+    assert math.isclose(t.sum(), 1.0) and t.argmax() == 1
+    # tau = 0.02: a plan 5% slower than the best weighs exp(-2.5) of it
+    assert math.isclose(t[0] / t[1], math.exp(-(20.0 / 15.0 - 1.0) / T.TAU))
+
+
+def test_split_is_stratified_and_deterministic(lib_built):
+    recs = [dict(s, times={"0": 1.0}) for s in T.sample_shapes(360)]
+    tr, te = T.split(recs)
+    tr2, te2 = T.split(list(reversed(recs)))
+    assert [T.key_of(r) for r in te] == [T.key_of(r) for r in te2]
+    assert len(tr) + len(te) == len(recs) and len(te) == 18 * 4
