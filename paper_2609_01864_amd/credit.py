@@ -150,6 +150,10 @@ def lib():
             if not os.path.exists(LIB_PATH):
                 raise RuntimeError(
                     f"{LIB_PATH} is missing: build it with `python -m paper_2609_01864_amd.build`")
+            # torch's HIP runtime must be in the process before the library
+            # binds to one: device pointers and streams come from torch
+            import torch  # noqa: F401
+
             L = ctypes.CDLL(LIB_PATH)
             for name, (args, res) in _SIGS.items():
                 f = getattr(L, name)

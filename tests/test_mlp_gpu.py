@@ -88,7 +88,7 @@ def test_model_file_round_trip_and_rejection(gpu_handle, tmp_path):
     # without a model the default selection falls back to the fixed rule
 
 
-def test_timed_learned_selector_keeps_the_faster_of_the_two_best(lib_built):
+def test_timed_learned_selector_keeps_the_faster_of_the_two_best(gpu_handle):
     # the shipped model's two highest-scoring legal plans are timed once; the
     # pick is one of them, and the faster one by the library's own timing
     h = C.Handle(0)

@@ -1,0 +1,55 @@
+"""What the learned selector gains over the method without it: on shapes the
+network never saw (the dataset sampler with another seed, half of them with
+aligned rows, at most 1 GB of operator I/O), every legal plan is timed; the
+installed network's first choice must be within 5% of the best plan in
+geometric mean and closer to it than Eq. (9), the paper's analytic model
+(Sec. III-D), which gets the same baseline and control timings."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2609_01864_amd import credit as C
+from paper_2609_01864_amd import tune as T
+
+pytestmark = pytest.mark.gpu
+
+
+def _shapes():
+    out = []
+    for seed, align in ((11, 1), (12, 64)):
+        sh = [s for s in T.sample_shapes(600, seed=seed, align=align)
+              if T.io_bytes(s["op"], s["dir"], s["dt"], s["M"], s["N"]) <= 1e9]
+        per = {}
+        for s in sh:  # two per (op, direction, dtype) combination
+            key = (s["op"], s["dir"], s["dt"])
+            if len(per.setdefault(key, [])) < 2:
+                per[key].append(s)
+        out += [s for v in per.values() for s in v]
+    return out
+
+
+def test_learned_pick_beats_the_analytic_model(gpu_handle):
+    h = C.Handle(0)  # a second handle, with the installed selector model
+    try:
+        assert h.model_loaded
+        recs = []
+        for s in _shapes():
+            o, d, dt, M, N = s["op"], s["dir"], s["dt"], s["M"], s["N"]
+            times = {str(c): h.time_plan(o, d, dt, M, N, C.plan_of_class(c), 7, True)
+                     for c in T.legal_classes(h, s)}
+            ctrl = {"1": h.time_control(o, d, dt, M, N, 1, 7)}
+            for k in T.SPLIT_KS:
+                if h.plan_legal(o, d, dt, M, N, C.plan("split", k)):
+                    ctrl[str(k)] = h.time_control(o, d, dt, M, N, k, 7)
+            recs.append(dict(s, times=times, ctrl=ctrl, feats=[float(v) for v in C.features(o, d, dt, M, N)]))
+        print(f"[selector gain] {len(recs)} shapes timed", flush=True)
+        learned = T.regret_stats(recs, T.pick_learned(h, recs))
+        analytic = T.regret_stats(recs, [T.pick_analytic(r) for r in recs])
+        print(f"[selector gain] learned {learned} analytic {analytic}", flush=True)
+        assert learned["n"] == analytic["n"] >= 60
+        assert learned["geomean"] <= 1.05
+        assert learned["geomean"] < analytic["geomean"]
+        assert learned["share_within_5pct"] > analytic["share_within_5pct"]
+    finally:
+        h.close()
