@@ -27,7 +27,8 @@
  *   - Device pointers are plain HIP device addresses; the caller owns all
  *     tensors and the workspace.  Nothing in an operator call allocates.
  *   - Matrices are row-major [M, ld] with unit inner stride; ld >= N is given
- *     in ELEMENTS.  Rows whose start is not 16-byte aligned take a scalar path.
+ *     in ELEMENTS.  Rows of any alignment use the same 16-byte accesses;
+ *     aligned rows holding whole vectors take an unmasked row loop.
  *   - I/O dtypes: CREDIT_F32 (float), CREDIT_BF16 (raw 16-bit bfloat16),
  *     CREDIT_FP8_E4M3 (raw uint8 OCP e4m3fn).  FP8 tensors carry one FP32
  *     scale per row: value = decode(code) * scale[row].  FP8 inputs read their
@@ -49,6 +50,13 @@
  *     epoch.  Make one eager call per shape first when the selector would
  *     time kernels or run its network (plan == NULL), so that capture finds
  *     the plan cached; operator calls record no memset nodes.
+ *   - A split-row launch assumes its workgroups can all be resident at once:
+ *     its grid is the occupancy bound times the CU count.  Kernels running at
+ *     the same time on other streams or in other processes can keep members of
+ *     a row group from starting; the bounded exchange wait then ends the
+ *     launch and credit_check_errors() returns CREDIT_ERR_TIMEOUT (the output
+ *     is not valid).  CREDIT_OPT_MAX_GROUPS caps the row groups to leave room
+ *     for such work; two-pass and resident plans have no such requirement.
  *   - No C++ exception crosses this interface and nothing aborts.
  */
 #ifndef CREDIT_H
