@@ -329,6 +329,44 @@ hipError_t launch(const void *fn, int grid, int block, size_t shmem, hipStream_t
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, shmem, s);
 }
 
+// Launches whose workgroups wait for one another (split-row, the control
+// kernel) need all their workgroups resident at once, and their grids fill
+// the GPU.  Two of them running together on different streams could each
+// hold part of the GPU and wait for slots the other holds until their bounded
+// waits give up, so each one is ordered after the previous one on this
+// device, whatever stream it came from: one event per device, waited on when
+// the stream changes.  A launch being captured into a graph keeps the
+// graph's own order (the event belongs to no capture).
+struct WaitFence {
+    std::mutex m;
+    hipEvent_t ev = nullptr;
+    hipStream_t last = nullptr;
+    bool valid = false;
+};
+
+WaitFence &wait_fence(int device) {
+    static WaitFence fences[64];
+    return fences[device & 63];
+}
+
+hipError_t fenced_launch(int device, bool capturing, const void *fn, int grid, int block, size_t shmem,
+                         hipStream_t s, void **args) {
+    if (capturing) return launch(fn, grid, block, shmem, s, args);
+    WaitFence &f = wait_fence(device);
+    std::lock_guard<std::mutex> g(f.m);
+    hipError_t e = hipSuccess;
+    if (!f.ev && (e = hipEventCreateWithFlags(&f.ev, hipEventDisableTiming)) != hipSuccess) {
+        f.ev = nullptr;
+        return e;
+    }
+    if (f.valid && f.last != s && (e = hipStreamWaitEvent(s, f.ev, 0)) != hipSuccess) return e;
+    if ((e = launch(fn, grid, block, shmem, s, args)) != hipSuccess) return e;
+    if ((e = hipEventRecord(f.ev, s)) != hipSuccess) return e;
+    f.last = s;
+    f.valid = true;
+    return hipSuccess;
+}
+
 hipError_t zero_words(void *p, int64_t nwords, hipStream_t s) {
     if (nwords <= 0) return hipSuccess;
     int grid = (int)std::min<int64_t>(4096, (nwords + 255) / 256);
@@ -418,6 +456,7 @@ credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void 
         a.k = L.k;
         a.groups = L.groups;
         a.chunk = L.chunk;
+        bool capturing = false;
         if (L.k > 1) {
             a.slots = (unsigned long long *)(w + L.off_slots);
             a.epoch = next_epoch();
@@ -426,7 +465,8 @@ credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void 
             // record a bump of the device-side epoch before it instead
             hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
             if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return CREDIT_ERR_HIP;
-            if (cs == hipStreamCaptureStatusActive) {
+            capturing = cs == hipStreamCaptureStatusActive;
+            if (capturing) {
                 unsigned *ctr = h->errflag + 64;  // the device epoch word of the handle
                 void *bargs[] = {&ctr};
                 if (launch(epoch_bump_kernel(), 1, 64, 0, stream, bargs) != hipSuccess) return CREDIT_ERR_HIP;
@@ -438,7 +478,8 @@ credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void 
         if (ncp) a.colpart = (float *)(w + L.off_colpart);
         a.flags = flags;
         void *args[] = {&a};
-        e = launch(L.fn, L.grid, L.block, 0, stream, args);
+        e = L.k > 1 ? fenced_launch(h->device, capturing, L.fn, L.grid, L.block, 0, stream, args)
+                    : launch(L.fn, L.grid, L.block, 0, stream, args);
         if (e != hipSuccess) return CREDIT_ERR_HIP;
     }
     if (ncp && (c.dgamma || c.dbeta)) {
@@ -736,7 +777,8 @@ credit_status_t time_control(credit_handle_t h, int k_op, int dt, int64_t M, int
                            a.epoch = next_epoch();
                            a.flags = L.xcd ? F_XCD : 0;
                            void *args[] = {&a, &stages};
-                           return launch(control_kernel(), L.grid, kBlockThreads, shmem, h->stream, args) == hipSuccess
+                           return fenced_launch(h->device, false, control_kernel(), L.grid, kBlockThreads, shmem,
+                                                h->stream, args) == hipSuccess
                                       ? CREDIT_OK
                                       : CREDIT_ERR_HIP;
                        },
