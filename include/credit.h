@@ -51,12 +51,15 @@
  *     time kernels or run its network (plan == NULL), so that capture finds
  *     the plan cached; operator calls record no memset nodes.
  *   - A split-row launch assumes its workgroups can all be resident at once:
- *     its grid is the occupancy bound times the CU count.  Kernels running at
- *     the same time on other streams or in other processes can keep members of
- *     a row group from starting; the bounded exchange wait then ends the
- *     launch and credit_check_errors() returns CREDIT_ERR_TIMEOUT (the output
- *     is not valid).  CREDIT_OPT_MAX_GROUPS caps the row groups to leave room
- *     for such work; two-pass and resident plans have no such requirement.
+ *     its grid is the occupancy bound times the CU count.  The library orders
+ *     its own such launches on a device one after another, whatever their
+ *     streams (outside graph capture).  Other kernels that wait on one another
+ *     (other libraries', other processes') running at the same time can keep
+ *     members of a row group from starting; the bounded exchange wait then
+ *     ends the launch and credit_check_errors() returns CREDIT_ERR_TIMEOUT (the
+ *     output is not valid).  CREDIT_OPT_MAX_GROUPS caps the row groups to
+ *     leave room for such work; two-pass and resident plans have no such
+ *     requirement.
  *   - No C++ exception crosses this interface and nothing aborts.
  */
 #ifndef CREDIT_H
