@@ -198,7 +198,7 @@ def suite(C, h, copy_gbps):
     two-pass)?  Answered by Eq. (9) with the measured baseline time (Eq. (7))
     and, as the ablation, with the baseline priced at copy bandwidth plus a
     serialized deposit."""
-    rows, acc, acc_peak, n = [], 0, 0, 0
+    rows, acc, acc_peak, acc_res, n = [], 0, 0, 0, 0
     for name, opn, dirn, M in SUITE:
         op, d = getattr(C, opn), getattr(C, dirn)
         w = C.workload_info(op, d, C.F32)
@@ -227,13 +227,18 @@ def suite(C, h, copy_gbps):
                 meas = bool(tbest < t[base])
                 pred = bool(max(delta) > 0)
                 pred_peak = bool(max(delta_peak) > 0)
+                # the other reading of b_reread: a row-resident baseline rereads
+                # nothing from HBM, so T_save = 0 and Eq. (9) never favours a split
+                pred_res = pred if base[0] == C.TWO_PASS else False
                 n += 1
                 acc += pred == meas
                 acc_peak += pred_peak == meas
+                acc_res += pred_res == meas
                 row.update(best_split=list(kb), best_split_us=round(tbest, 2),
                            speedup_vs_best_single=round(single / tbest, 3),
                            gbps_best=round(M * N * w.b_staged / (min(tbest, single) * 1e3), 1),
-                           measured_profitable=meas, predicted_profitable=pred, predicted_profitable_peak=pred_peak)
+                           measured_profitable=meas, predicted_profitable=pred, predicted_profitable_peak=pred_peak,
+                           predicted_profitable_resident_no_reread=pred_res)
             rows.append(row)
             log(f"suite {name} N={N}: {row}")
     # crossover width N*: the narrowest swept width from which the split-row
@@ -254,6 +259,7 @@ def suite(C, h, copy_gbps):
     sp = [r["speedup_vs_best_single"] for r in rows if r["N"] == nmax and "speedup_vs_best_single" in r]
     gm = round(math.exp(sum(math.log(x) for x in sp) / len(sp)), 3) if sp else None
     return {"rows": rows, "profitability_pairs": n, "model_correct": acc, "peak_model_correct": acc_peak,
+            "resident_no_reread_model_correct": acc_res,
             "crossover_N": cross, "geomean_speedup_at_widest_N": {"N": nmax, "workloads": len(sp), "speedup": gm}}
 
 
