@@ -610,21 +610,21 @@ struct Bufs {
 
 credit_status_t ensure_arena(credit_handle_t h, size_t bytes) {
     if (h->arena_bytes >= bytes && h->flushbuf) return CREDIT_OK;
-    if (h->arena) hipFree(h->arena);
+    if (h->arena) (void)hipFree(h->arena);
     h->arena = nullptr;
     h->arena_bytes = 0;
     h->prepared = std::make_tuple(-1, -1, (int64_t)-1, (int64_t)-1);
     size_t want = std::max(bytes, (size_t)64 << 20);
     if (hipMalloc(&h->arena, want) != hipSuccess) {
         h->arena = nullptr;
-        hipGetLastError();
+        (void)hipGetLastError();
         return CREDIT_ERR_HIP;
     }
     h->arena_bytes = want;
     if (!h->flushbuf) {
         if (hipMalloc(&h->flushbuf, kFlushBytes) != hipSuccess) {
             h->flushbuf = nullptr;
-            hipGetLastError();
+            (void)hipGetLastError();
             return CREDIT_ERR_HIP;
         }
         if (zero_words(h->flushbuf, (int64_t)(kFlushBytes / 4), h->stream) != hipSuccess) return CREDIT_ERR_HIP;
@@ -1004,7 +1004,7 @@ struct MlpDev {
     int64_t n = 0;
     std::vector<void *> owned;
     ~MlpDev() {
-        for (void *q : owned) hipFree(q);
+        for (void *q : owned) (void)hipFree(q);
     }
     template <class T> bool alloc(T *&q, size_t count) {
         if (hipMalloc((void **)&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return false;
@@ -1190,13 +1190,13 @@ credit_status_t credit_create(int device, credit_handle_t *out) {
 
 credit_status_t credit_destroy(credit_handle_t h) {
     if (!h) return CREDIT_ERR_INVALID_ARG;
-    if (h->stream) hipStreamSynchronize(h->stream);
-    if (h->arena) hipFree(h->arena);
-    if (h->flushbuf) hipFree(h->flushbuf);
-    if (h->errflag) hipFree(h->errflag);
-    if (h->ev0) hipEventDestroy(h->ev0);
-    if (h->ev1) hipEventDestroy(h->ev1);
-    if (h->stream) hipStreamDestroy(h->stream);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->arena) (void)hipFree(h->arena);
+    if (h->flushbuf) (void)hipFree(h->flushbuf);
+    if (h->errflag) (void)hipFree(h->errflag);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
     return CREDIT_OK;
 }
