@@ -12,6 +12,9 @@ traffic  HBM bytes per launch of the dominant kernel from two `--pmc` runs
          (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each divided by the
          counter-per-byte factor the same counter reads on the plain copy
          kernel (k_copy moves a known number of bytes each way).
+counters the SQ counters of one `--pmc` run (occupancy, instruction mix, LDS
+         bank conflicts) for the dominant kernel and grid: the median per
+         dispatch, with per-wave and per-element ratios.
 suite    the same two counters over the launch sequence of
          `bench.py --traffic-suite` (two-pass and fastest split-row plan of
          every evaluation-suite workload at N = 65536, each block behind a
@@ -233,9 +236,45 @@ def suite(args):
     print("\n".join(lines))
 
 
+def counters(args):
+    bench = json.loads(open(args.bench).read().strip().splitlines()[-1])
+    sym, grid = kernel_name(bench)
+    rows = _rows(_find(args.pmc, "counter_collection.csv"))
+    vals = {}
+    for r in rows:
+        if not (r.get("Kernel_Name") or "").startswith(sym) or _grid(r) != grid:
+            continue
+        vals.setdefault(r.get("Counter_Name"), []).append(float(r.get("Counter_Value") or 0.0))
+    if not vals:
+        raise SystemExit(f"no dispatch of {sym} with grid {grid}")
+    med = {c: statistics.median(v) for c, v in vals.items()}
+    n_disp = min(len(v) for v in vals.values())
+    key = bench["roofline"]["kernel"]
+    elems = bench["roofline"]["algorithmic_bytes_per_launch"] / 8.0  # FP32 in + out per element
+    waves = med.get("SQ_WAVES", 0.0)
+    lines = [f"# SQ counters of the dominant kernel: {args.title}", "",
+             f"Command: `{args.command}`", "",
+             f"Kernel `{sym}`, grid {grid} work-items ({key}); median over {n_disp} dispatches", "",
+             "| counter | per dispatch | per wave | per element |", "|---|---:|---:|---:|"]
+    for c in sorted(med):
+        pw = med[c] / waves if waves else float("nan")
+        lines.append(f"| {c} | {med[c]:.4g} | {pw:.4g} | {med[c] / elems:.4g} |")
+    if med.get("SQ_ACTIVE_INST_LDS"):
+        lines += ["", f"LDS bank-conflict cycles per active LDS instruction cycle: "
+                      f"{med.get('SQ_LDS_BANK_CONFLICT', 0.0) / med['SQ_ACTIVE_INST_LDS']:.4f}"]
+    if waves:
+        lines += ["", f"Waves per dispatch {waves:.0f} (grid / 64 = {grid / 64:.0f})."]
+    out = {"kernel": key, "kernel_symbol": sym, "grid_threads": grid, "dispatches": n_disp,
+           "median_per_dispatch": med, "source_hash": bench.get("source_hash")}
+    json.dump(out, open(args.json, "w"), indent=1)
+    open(args.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "traffic", "suite"])
+    ap.add_argument("mode", choices=["trace", "traffic", "suite", "counters"])
+    ap.add_argument("--pmc")
     ap.add_argument("--trace")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
@@ -245,7 +284,7 @@ def main(argv=None):
     ap.add_argument("--title", default="")
     ap.add_argument("--command", default="python3 bench.py")
     args = ap.parse_args(argv)
-    {"trace": trace, "traffic": traffic, "suite": suite}[args.mode](args)
+    {"trace": trace, "traffic": traffic, "suite": suite, "counters": counters}[args.mode](args)
 
 
 if __name__ == "__main__":
