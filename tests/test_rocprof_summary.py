@@ -74,3 +74,30 @@ def test_suite_traffic_rejects_a_missing_call(tmp_path):
     with pytest.raises(SystemExit):
         R.main(["suite", "--fetch", str(tmp_path / "f"), "--write", str(tmp_path / "w"), "--bench", str(mp),
                 "--json", str(tmp_path / "s.json"), "--out", str(tmp_path / "s.md")])
+
+
+def test_counters_median_and_ratios(tmp_path):
+    bench = {"roofline": {"kernel": "layernorm_fwd:N=8:plan=2,2", "kernel_symbol": "void credit::k_resident<1, 0, 1>",
+                          "grid_threads": 128, "algorithmic_bytes_per_launch": 8.0 * 1000}, "source_hash": "h"}
+    bp = tmp_path / "b.json"
+    bp.write_text(json.dumps(bench) + "\n")
+    d = tmp_path / "sq"
+    d.mkdir()
+    with open(d / "x_counter_collection.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(HDR)
+        k = "void credit::k_resident<1, 0, 1>(credit::RowArgs)"
+        rows = [(k, 128, "SQ_WAVES", 2), (k, 128, "SQ_INSTS_VALU", 100), (k, 128, "SQ_INSTS_VALU", 300),
+                (k, 128, "SQ_INSTS_VALU", 200), (k, 128, "SQ_WAVES", 2), (k, 128, "SQ_WAVES", 2),
+                (k, 64, "SQ_INSTS_VALU", 9999),  # another grid: ignored
+                (k, 128, "SQ_ACTIVE_INST_LDS", 50), (k, 128, "SQ_LDS_BANK_CONFLICT", 5)]
+        for i, (n, g, c, v) in enumerate(rows):
+            w.writerow([i + 1, g, n, c, v])
+    out = tmp_path / "c.json"
+    R.main(["counters", "--pmc", str(d), "--bench", str(bp), "--json", str(out), "--out", str(tmp_path / "c.md")])
+    res = json.load(open(out))
+    assert res["median_per_dispatch"]["SQ_INSTS_VALU"] == 200.0
+    assert res["median_per_dispatch"]["SQ_WAVES"] == 2.0
+    md = (tmp_path / "c.md").read_text()
+    assert "| SQ_INSTS_VALU | 200 | 100 | 0.2 |" in md
+    assert "0.1000" in md  # 5 conflict cycles per 50 active LDS cycles
