@@ -183,13 +183,16 @@ def baseline_class(r):
     return 1 if "1" in r["times"] else 0
 
 
-def pick_analytic(r, t_base=None):
-    """Eq. (9) with the measured baseline (Eq. (7)) and control excess."""
+def pick_analytic(r, t_base=None, h=None):
+    """Eq. (9) with the measured baseline (Eq. (7)) and control excess; with a
+    handle the row-group waves W come from the runtime occupancy, as in the
+    library's own analytic selector (without one, from the register model,
+    which is a lower bound)."""
     base = baseline_class(r)
     tb = r["times"][str(base)] if t_base is None else t_base
     c1 = r["ctrl"].get("1", 0.0)
     ctrl = [max(0.0, r["ctrl"].get(str(k), c1) - c1) for k in SPLIT_KS]
-    delta = C.model_delta(None, r["op"], r["dir"], r["dt"], r["M"], r["N"], tb, ctrl)
+    delta = C.model_delta(h, r["op"], r["dir"], r["dt"], r["M"], r["N"], tb, ctrl)
     best = None
     for i, k in enumerate(SPLIT_KS):
         c = 2 + i
@@ -237,7 +240,7 @@ def regret_stats(recs, picks):
 
 def evaluate(h, recs, copy_gbps: float):
     out = {"learned": regret_stats(recs, pick_learned(h, recs)),
-           "analytic": regret_stats(recs, [pick_analytic(r) for r in recs]),
+           "analytic": regret_stats(recs, [pick_analytic(r, h=h) for r in recs]),
            "peak": regret_stats(recs, [pick_peak(r, copy_gbps) for r in recs]),
            "fixed": regret_stats(recs, [pick_fixed(r) for r in recs]),
            "always_two_pass": regret_stats(recs, [0 for _ in recs])}

@@ -66,3 +66,36 @@ def test_spin_limit_from_environment(lib_built, monkeypatch):
         assert h.check_errors() == C.OK
     finally:
         h.close()
+
+
+def test_register_model_is_a_lower_bound_of_runtime_occupancy(lib_built):
+    # The host's register model (used without a handle) sets each instance's
+    # minimum waves per SIMD; the compiled kernel may use fewer registers and
+    # fit more.  Co-residency uses the runtime figure, which must never be
+    # below the model's, for every instantiated (operator, dtype, vectors).
+    import torch  # noqa: F401  (torch's HIP runtime first)
+
+    h = C.Handle(0, load_default_model=False)
+    try:
+        pairs = [(C.SOFTMAX, C.FWD), (C.LAYERNORM, C.FWD), (C.RMSNORM, C.FWD), (C.SOFTMAX, C.BWD),
+                 (C.LAYERNORM, C.BWD), (C.RMSNORM, C.BWD), (C.SOFTMAX_LOGITS, C.BWD), (C.QUANT_INT8, C.FWD),
+                 (C.QUANT_FP8, C.FWD), (C.PEARSON, C.BWD), (C.WVAR, C.BWD), (C.LAYERNORM_FP8_OUT, C.FWD)]
+        epv = {C.F32: 4, C.BF16: 8, C.FP8: 16}
+        seen = 0
+        for op, d in pairs:
+            for dt in (C.F32, C.BF16, C.FP8):
+                for vpt in (1, 2, 4, 8, 12, 16, 24, 32):
+                    N = 2 * vpt * 256 * epv[dt]
+                    p = C.plan("split", 2)
+                    try:
+                        g1 = h.geometry(op, d, dt, 4096, N, p)
+                    except C.CreditError:
+                        continue  # (operator, dtype) pair that does not exist
+                    if g1 is None or g1["vpt"] != vpt:
+                        continue
+                    g0 = C.plan_geometry(None, op, d, dt, 4096, N, p)
+                    assert g0 is not None and g1["per_cu"] >= g0["per_cu"] >= 1, (op, d, dt, vpt, g0, g1)
+                    seen += 1
+        assert seen >= 150
+    finally:
+        h.close()

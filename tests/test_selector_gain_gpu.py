@@ -45,7 +45,7 @@ def test_learned_pick_beats_the_analytic_model(gpu_handle):
             recs.append(dict(s, times=times, ctrl=ctrl, feats=[float(v) for v in C.features(o, d, dt, M, N)]))
         print(f"[selector gain] {len(recs)} shapes timed", flush=True)
         learned = T.regret_stats(recs, T.pick_learned(h, recs))
-        analytic = T.regret_stats(recs, [T.pick_analytic(r) for r in recs])
+        analytic = T.regret_stats(recs, [T.pick_analytic(r, h=h) for r in recs])
         print(f"[selector gain] learned {learned} analytic {analytic}", flush=True)
         assert learned["n"] == analytic["n"] >= 60
         assert learned["geomean"] <= 1.05
