@@ -1,14 +1,16 @@
 """Timing-dataset collection, training and evaluation of the learned plan
 selector, and the regret of every selector against exhaustive timing.
 
-    python -m paper_2609_01864_amd.tune all --out DIR [--shapes 6000] [--aligned-shapes 3000] [--model PATH]
+    python -m paper_2609_01864_amd.tune all --out DIR [--shapes 6000] [--aligned-shapes 3000] [--pow2-shapes 1000]
+        [--model PATH]
 
 collect  For 6000 seeded shapes (op x direction x dtype stratified over the 18
          combinations; M log-uniform in [1, 16384]; N log-uniform in
          [1024, 4194304], so rows are ragged and misaligned; at most 16e9 bytes
-         of operator I/O) and 3000 more drawn the same way with N rounded to a
+         of operator I/O), 3000 more drawn the same way with N rounded to a
          multiple of 64 (rows of whole, aligned vectors, the common case and
-         up to 1.4x faster than ragged rows of the same size) every legal plan is
+         up to 1.4x faster than ragged rows of the same size) and 1000 with N a
+         power of two (where slices meet the capacity boundaries) every legal plan is
          timed with credit_time_plan (cache flush, median of 15), and the
          work-free control kernel (Sec. III-D) for k = 1, 2, ..., 32.  Records
          are appended to a JSONL file keyed by shape, so an interrupted
@@ -52,7 +54,8 @@ def io_bytes(op: int, direction: int, dtype: int, M: int, N: int) -> float:
 
 def sample_shapes(n: int = 6000, seed: int = 4, align: int = 1):
     """n shapes stratified over the 18 (op, direction, dtype) combinations;
-    align > 1 rounds N to a multiple of align."""
+    align > 1 rounds N to a multiple of align, align == 0 to a power of two
+    (the common widths, where slices meet the capacity boundaries exactly)."""
     rng = np.random.default_rng(seed)
     combos = [(o, d, t) for (o, d) in OPS for t in (C.F32, C.BF16, C.FP8)]
     out = []
@@ -65,6 +68,8 @@ def sample_shapes(n: int = 6000, seed: int = 4, align: int = 1):
             N = int(round(math.exp(rng.uniform(math.log(1024), math.log(4194304)))))
             if align > 1:
                 N = max(1024, int(round(N / align)) * align)
+            elif align == 0:
+                N = 1 << int(round(math.log2(N)))
             if io_bytes(o, d, t, M, N) <= MAX_IO_BYTES:
                 break
         out.append({"op": o, "dir": d, "dt": t, "M": max(1, M), "N": N})
@@ -253,6 +258,7 @@ def main(argv=None):
     ap.add_argument("--out", default="tune_out")
     ap.add_argument("--shapes", type=int, default=6000)
     ap.add_argument("--aligned-shapes", type=int, default=3000)
+    ap.add_argument("--pow2-shapes", type=int, default=1000)
     ap.add_argument("--reps", type=int, default=15)
     ap.add_argument("--epochs", type=int, default=4000)
     ap.add_argument("--lr", type=float, default=3e-3)
@@ -263,8 +269,8 @@ def main(argv=None):
     model = args.model or os.path.join(args.out, "selector_gfx950.txt")
     h = C.Handle(0, load_default_model=False)
     if args.cmd in ("collect", "all"):
-        collect(h, sample_shapes(args.shapes) + sample_shapes(args.aligned_shapes, seed=5, align=64), data,
-                args.reps)
+        collect(h, sample_shapes(args.shapes) + sample_shapes(args.aligned_shapes, seed=5, align=64) +
+                sample_shapes(args.pow2_shapes, seed=6, align=0), data, args.reps)
     recs = load(data)
     tr, te = split(recs)
     if args.cmd in ("train", "all"):
