@@ -381,8 +381,9 @@ credit_status_t credit_plan_of_class(int32_t c, credit_plan_t *out);
 /* The 12 raw (unstandardized) features of a shape: operator one-hot (3),
  * is-backward, dtype one-hot (3), log2 M, log2 N, aligned rows (1 when N * e
  * is a multiple of 16 bytes, so rows of ld = N from an aligned base hold
- * whole aligned vectors, else 0), log2 of the operator's total I/O bytes and
- * log2(M / CUs) clamped at 0.  Defined for the softmax, LayerNorm and RMSNorm
+ * whole aligned vectors, else 0), and for a k = 4 and a k = 16 split how
+ * full the slice keeps its register bucket (the slice's 16-byte vectors over
+ * 256 * the smallest vectors-per-thread bucket holding them; 0 if none does).  Defined for the softmax, LayerNorm and RMSNorm
  * operators (the learned selector's domain; the other operators are planned
  * by the analytic model): CREDIT_ERR_UNSUPPORTED else. */
 credit_status_t credit_features(credit_op_t op, credit_dir_t dir, credit_dtype_t dt, int64_t M,

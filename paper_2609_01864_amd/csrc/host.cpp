@@ -840,12 +840,23 @@ void features(int k_op, int dt, int64_t M, int64_t N, float *f) {
     f[3] = (float)dir;
     f[4 + dt] = 1.f;
     const double e = dt_bytes(dt);
-    const int nin = two_inputs(k_op) ? 2 : 1;
     f[7] = (float)std::log2((double)std::max<int64_t>(M, 1));
     f[8] = (float)std::log2((double)N);
     f[9] = ((int64_t)(N * e) % 16 == 0) ? 1.f : 0.f;
-    f[10] = (float)std::log2((double)std::max<int64_t>(M, 1) * N * e * (nin + 1));
-    f[11] = (float)std::log2(std::max(1.0, (double)M / kDefaultCUs));
+    // how full the slice of a k = 4 and a k = 16 split keeps its register
+    // bucket (vectors of the slice / vectors the chosen VPT holds; 0 when no
+    // bucket holds it): the best split factor changes in steps where slices
+    // cross bucket boundaries, which log2 N alone shows only indirectly
+    auto fill = [&](int k) -> float {
+        const int64_t nv = (N * (int64_t)e + 15) / 16;
+        const int64_t per = (nv + k - 1) / k;
+        const int64_t need = (per + kBlockThreads - 1) / kBlockThreads;
+        for (int v : kVpts)
+            if (v >= need) return (float)((double)per / ((double)kBlockThreads * v));
+        return 0.f;
+    };
+    f[10] = fill(4);
+    f[11] = fill(16);
 }
 
 credit_status_t mlp_predict_dev(credit_handle_t h, const float *feats, int64_t n, float *logits);
@@ -1761,7 +1772,7 @@ credit_status_t credit_mlp_predict(credit_handle_t h, const float *feats, int64_
     }
 }
 
-static const char *kSchema = "f12-h64-h64-c7-v2";
+static const char *kSchema = "f12-h64-h64-c7-v3";
 
 credit_status_t credit_save_model(credit_handle_t h, const char *path) {
     if (!h || !path) return CREDIT_ERR_INVALID_ARG;

@@ -58,7 +58,12 @@ def test_plan_classes_and_features(lib_built):
     f = C.features(C.LAYERNORM, C.BWD, C.BF16, 2048, 131072)
     assert list(f[:7]) == [0, 1, 0, 1, 0, 1, 0]
     assert f[7] == 11 and f[8] == 17 and f[9] == 1  # 131072 BF16 values: whole 16-byte vectors
-    assert np.isclose(f[10], np.log2(2048 * 131072 * 2 * 3)) and f[11] == 3
+    # 16384 vectors: k = 4 slices of 4096 = 256 x 16 (full bucket), k = 16 of 1024 = 256 x 4 (full)
+    assert f[10] == 1.0 and f[11] == 1.0
+    g = C.features(C.SOFTMAX, C.FWD, C.F32, 3, 100000)  # 25000 vectors
+    # k = 4: 6250 per slice -> 25 per thread -> bucket 32; k = 16: 1563 -> 7 -> bucket 8
+    assert np.isclose(g[10], 6250 / (256 * 32)) and np.isclose(g[11], 1563 / (256 * 8))
+    assert C.features(C.SOFTMAX, C.FWD, C.F32, 3, 4 << 20)[10] == 0.0  # k = 4 slices exceed 32 vectors
     assert C.features(C.LAYERNORM, C.BWD, C.BF16, 2048, 131071)[9] == 0
     assert C.features(C.SOFTMAX, C.FWD, C.FP8, 3, 4096 + 16)[9] == 1
     assert C.features(C.SOFTMAX, C.FWD, C.F32, 3, 4096 + 2)[9] == 0
