@@ -178,11 +178,16 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
                     rstd = rsqrtf(st[2] * invN + a.eps);
                 } else {
                     float st[1] = {0.f};
+                    // each vector is summed on its own, then added: a thread's
+                    // running sum takes N/(threads*EPV) additions instead of
+                    // N/threads (rows of millions of elements)
                     stream_row<DT, BLOCK, U, false>(r0, nullptr, N, al0, al1, [&](int64_t, u32x4 v, u32x4, int) {
                         float x[EPV];
                         decode<DT>(v, x, xs);
+                        float sv = 0.f;
 #pragma unroll
-                        for (int i = 0; i < EPV; ++i) st[0] = fmaf(x[i], x[i], st[0]);
+                        for (int i = 0; i < EPV; ++i) sv = fmaf(x[i], x[i], sv);
+                        st[0] += sv;
                     });
                     block_reduce<NW, 1>(st, MergeSum(), red, parity);
                     rstd = rsqrtf(st[0] * invN + a.eps);
@@ -203,13 +208,16 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
                     decode<DT>(dxv, x, xs);
                     decode<DT>(dyv, dy, gs);
                     load_params_n<DT>(a.gamma, v * EPV, nv, alp, gm);
+                    float sg = 0.f, sgx = 0.f;  // per vector, then added
 #pragma unroll
                     for (int i = 0; i < EPV; ++i) {
                         float xh = (x[i] - mean) * rstd;
                         float g = dy[i] * gm[i];
-                        st[0] += g;
-                        st[1] = fmaf(g, xh, st[1]);
+                        sg += g;
+                        sgx = fmaf(g, xh, sgx);
                     }
+                    st[0] += sg;
+                    st[1] += sgx;
                 });
                 block_reduce<NW, 2>(st, MergeSum(), red, parity);
                 c1 = LN ? st[0] * invN : 0.f;
@@ -270,8 +278,10 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
                 float y[EPV], g[EPV];
                 decode<DT>(yv, y, ys);
                 decode<DT>(gv, g, gs);
+                float sv = 0.f;  // per vector, then added
 #pragma unroll
-                for (int i = 0; i < EPV; ++i) st[0] = fmaf(g[i], y[i], st[0]);
+                for (int i = 0; i < EPV; ++i) sv = fmaf(g[i], y[i], sv);
+                st[0] += sv;
             });
             block_reduce<NW, 1>(st, MergeSum(), red, parity);
             const float cs = st[0];

@@ -108,7 +108,10 @@ class Case:
             c2 = (gg * xh).mean(1, keepdims=True)
             mag = rs[:, None] * (np.abs(gg) + np.abs(c1) + np.abs(v["x"]) * rs[:, None] * np.abs(c2))
             return {"dx": dx, "dgamma": dg, "dbeta": db, "mean": mu, "rstd": rs, "mag": mag,
-                    "dg_mag": np.abs(v["dy"] * xh).sum(0), "db_mag": np.abs(v["dy"]).sum(0)}
+                    # x_hat = (x - mean) * rstd cancels: its FP32 resolution is set by
+                    # the operands |x| and |mean| (the rule of the BF16 bound)
+                    "dg_mag": (np.abs(v["dy"]) * (np.abs(v["x"]) + np.abs(mu[:, None])) * rs[:, None]).sum(0),
+                    "db_mag": np.abs(v["dy"]).sum(0)}
         dx, dg = oracle.rmsnorm_bwd(v["x"], v["dy"], g, EPS)
         _, rs = oracle.rmsnorm_fwd(v["x"], g, EPS)
         xh = v["x"] * rs[:, None]
