@@ -151,40 +151,64 @@ TRAFFIC_REPS = 3
 TRAFFIC_CALIB_BYTES = 1 << 30
 
 
-def traffic_suite(C, h):
-    """Launch sequence for the traffic validation of Sec. IV-E (the paper's
-    DRAM-traffic figure at N = 65536): for every suite workload, the two-pass
-    baseline and the fastest split-row plan, each launched 3 + TRAFFIC_REPS
-    times with a cache flush before each launch, behind a marker (a small
-    copy-kernel launch whose size names the block).  Meant to run under
-    `rocprofv3 --pmc FETCH_SIZE` (then WRITE_SIZE); the JSON it prints tells
-    the summary which block is which.  A 1 GiB copy first calibrates the
-    counters."""
-    N = max(SUITE_N)
-    best = {}
-    for name, opn, dirn, M in SUITE:  # pick the split plan before any marker
-        op, d = getattr(C, opn), getattr(C, dirn)
-        ts = {}
-        for k in (2, 4, 8, 16, 32):
-            p = C.plan("split", k)
-            if h.plan_legal(op, d, C.F32, M, N, p):
-                ts[k] = h.time_plan(op, d, C.F32, M, N, p, 7, True)
-        best[name] = min(ts, key=ts.get)
-        log(f"traffic: {name} fastest split k={best[name]}")
+def _legal_splits(C, h, op, d, M, N):
+    """Every legal split-row plan, so that the launch sequence (and the
+    block each counter reading belongs to) is the same in every profiled
+    run: timing under the profiler would not pick the same plan twice."""
+    return tuple(("split", k) for k in (2, 4, 8, 16, 32)
+                 if h.plan_legal(op, d, C.F32, M, N, C.plan("split", k)))
+
+
+def _traffic_blocks(C, h, items, mode):
+    """Launches each (workload, op, direction, M, N, plans) item's plans
+    3 + TRAFFIC_REPS times with a cache flush before each launch, every plan
+    behind a marker (a small copy-kernel launch whose size names the block),
+    after a 1 GiB copy that calibrates the counters.  Meant to run under
+    `rocprofv3 --pmc FETCH_SIZE` (then WRITE_SIZE); the JSON it returns tells
+    the summary which block is which."""
     h.copy_bandwidth(TRAFFIC_CALIB_BYTES, 1)
     blocks = []
-    for name, opn, dirn, M in SUITE:
-        op, d = getattr(C, opn), getattr(C, dirn)
+    for name, op, d, M, N, plans in items:
         w = C.workload_info(op, d, C.F32)
-        for variant, k in (("two_pass", 1), ("split", best[name])):
+        for variant, k in plans:
             marker = 4096 * (1 + len(blocks))
             h.copy_bandwidth(marker, 1)
             h.time_plan(op, d, C.F32, M, N, C.plan(variant, k), TRAFFIC_REPS, True)
             blocks.append({"workload": name, "M": M, "N": N, "variant": variant, "k": k,
                            "marker_threads": marker // 16, "launches": 3 + TRAFFIC_REPS,
                            "algorithmic_bytes": M * N * (w.b_base if variant == "two_pass" else w.b_staged)})
-    return {"mode": "traffic_suite", "source_hash": source_hash(), "copy_kernel_bytes": TRAFFIC_CALIB_BYTES,
+    return {"mode": mode, "source_hash": source_hash(), "copy_kernel_bytes": TRAFFIC_CALIB_BYTES,
             "copy_threads": TRAFFIC_CALIB_BYTES // 16, "blocks": blocks}
+
+
+def traffic_suite(C, h):
+    """Launch sequence for the traffic validation of Sec. IV-E (the paper's
+    DRAM-traffic figure at N = 65536): for every suite workload, the two-pass
+    baseline and every legal split-row plan."""
+    N = max(SUITE_N)
+    items = []
+    for name, opn, dirn, M in SUITE:
+        op, d = getattr(C, opn), getattr(C, dirn)
+        items.append((name, op, d, M, N, (("two_pass", 1),) + _legal_splits(C, h, op, d, M, N)))
+    return _traffic_blocks(C, h, items, "traffic_suite")
+
+
+def traffic_plans(C, h):
+    """Launch sequence for the traffic of every variant on the bandwidth
+    workload (FP32 LayerNorm / RMSNorm forward, M = 1024 rows, each width):
+    the two-pass baseline, the row-resident kernel where the row fits one
+    workgroup, and every legal split-row plan, so the counters show where
+    the reread of the two-pass kernel reaches HBM and where a cache serves
+    it."""
+    items = []
+    for name in OPS:
+        op = C.LAYERNORM if name == "layernorm_fwd" else C.RMSNORM
+        for N in WIDTHS:
+            plans = (("two_pass", 1),)
+            if h.plan_legal(op, C.FWD, C.F32, M_ROWS, N, C.plan("resident")):
+                plans += (("resident", 1),)
+            items.append((name, op, C.FWD, M_ROWS, N, plans + _legal_splits(C, h, op, C.FWD, M_ROWS, N)))
+    return _traffic_blocks(C, h, items, "traffic_plans")
 
 
 def suite(C, h, copy_gbps):
@@ -292,6 +316,9 @@ def main():
     ap.add_argument("--selector", default="auto", choices=["auto", "learned", "learned_timed", "analytic", "fixed", "exhaustive"])
     ap.add_argument("--traffic-suite", action="store_true",
                     help="only the launch sequence of the suite traffic validation (run under rocprofv3 --pmc)")
+    ap.add_argument("--traffic-plans", action="store_true",
+                    help="only the launch sequence of every variant's traffic on the bandwidth workload "
+                         "(run under rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the row kernels shard over rows with no communication, "
@@ -313,6 +340,9 @@ def main():
     log(f"selector={sel_name} model_loaded={h.model_loaded}")
     if args.traffic_suite:
         print(json.dumps(traffic_suite(C, h)), flush=True)
+        return
+    if args.traffic_plans:
+        print(json.dumps(traffic_plans(C, h)), flush=True)
         return
 
     # ---------------------------------------------------------------- inputs

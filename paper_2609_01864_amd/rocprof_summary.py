@@ -16,13 +16,16 @@ counters the SQ counters of one `--pmc` run (occupancy, instruction mix, LDS
          bank conflicts) for the dominant kernel and grid: the median per
          dispatch, with per-wave and per-element ratios.
 suite    the same two counters over the launch sequence of
-         `bench.py --traffic-suite` (two-pass and fastest split-row plan of
-         every evaluation-suite workload at N = 65536, each block behind a
-         marker copy launch): bytes per operator call, summed over every
-         kernel the call launches, and the reduction of the split-row plan.
+         `bench.py --traffic-suite` (two-pass and every legal split-row plan
+         of every evaluation-suite workload at N = 65536) or of
+         `bench.py --traffic-plans` (two-pass, row-resident where legal and
+         every legal split-row plan of the bandwidth workload at each width),
+         each block behind a marker copy launch: bytes per operator call,
+         summed over every kernel the call launches, and the reduction of
+         each plan against the two-pass kernel of the same shape.
 
     python -m paper_2609_01864_amd.rocprof_summary suite --fetch DIR --write DIR --bench META.json \
-        --json profiles/suite_traffic.json --out profiles/Z.md
+        --bench-write META_W.json --json profiles/suite_traffic.json --out profiles/Z.md
 """
 from __future__ import annotations
 
@@ -183,8 +186,12 @@ def _counter_seq(d: str, counter: str):
 
 def suite(args):
     meta = json.loads(open(args.bench).read().strip().splitlines()[-1])
-    assert meta.get("mode") == "traffic_suite", "not a --traffic-suite run"
+    assert meta.get("mode") in ("traffic_suite", "traffic_plans"), "not a --traffic-suite / --traffic-plans run"
     blocks = meta["blocks"]
+    if args.bench_write:  # the WRITE_SIZE run must have launched the same blocks
+        other = json.loads(open(args.bench_write).read().strip().splitlines()[-1])["blocks"]
+        if other != blocks:
+            raise SystemExit("the FETCH_SIZE and WRITE_SIZE runs launched different blocks")
     by_marker = {b["marker_threads"]: i for i, b in enumerate(blocks)}
     per = {}
     for counter, d in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
@@ -217,7 +224,8 @@ def suite(args):
                          bytes_per_call=round(tot), ratio_to_algorithmic=round(tot / b["algorithmic_bytes"], 4)))
     out = {"source_hash": meta.get("source_hash"), "factors": per["factor"], "rows": rows}
     json.dump(out, open(args.json, "w"), indent=1)
-    lines = [f"# HBM traffic of the evaluation-suite workloads: {args.title}", "",
+    what = "evaluation-suite workloads" if meta["mode"] == "traffic_suite" else "variants of the bandwidth workload"
+    lines = [f"# HBM traffic of the {what}: {args.title}", "",
              f"Commands: `{args.command}` with `--pmc FETCH_SIZE` and, separately, `--pmc WRITE_SIZE`", "",
              "Bytes per operator call, summed over every kernel the call launches (row kernel and, for",
              "LayerNorm backward, the column reductions), averaged over the calls of its block; counters",
@@ -225,13 +233,16 @@ def suite(args):
              f"WRITE {per['factor']['WRITE_SIZE']:.4f}).", "",
              "| workload | M x N | plan | HBM bytes/call | algorithmic | ratio | reduction vs two-pass |",
              "|---|---|---|---:|---:|---:|---:|"]
-    for i in range(0, len(rows), 2):
-        tp, sp = rows[i], rows[i + 1]
-        red = 1.0 - sp["bytes_per_call"] / tp["bytes_per_call"]
-        for r, rr in ((tp, ""), (sp, f"{100 * red:.1f}%")):
-            plan = "two-pass" if r["variant"] == "two_pass" else f"split k={r['k']}"
-            lines.append(f"| {r['workload']} | {r['M']} x {r['N']} | {plan} | {r['bytes_per_call']:.4e} | "
-                         f"{r['algorithmic_bytes']:.4e} | {r['ratio_to_algorithmic']:.3f} | {rr} |")
+    base = None  # each (workload, M, N) group opens with its two-pass row
+    for r in rows:
+        if r["variant"] == "two_pass":
+            base, rr = r, ""
+        else:
+            same = base is not None and (base["workload"], base["M"], base["N"]) == (r["workload"], r["M"], r["N"])
+            rr = f"{100 * (1.0 - r['bytes_per_call'] / base['bytes_per_call']):.1f}%" if same else ""
+        plan = {"two_pass": "two-pass", "resident": "row-resident"}.get(r["variant"], f"split k={r['k']}")
+        lines.append(f"| {r['workload']} | {r['M']} x {r['N']} | {plan} | {r['bytes_per_call']:.4e} | "
+                     f"{r['algorithmic_bytes']:.4e} | {r['ratio_to_algorithmic']:.3f} | {rr} |")
     open(args.out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -279,6 +290,7 @@ def main(argv=None):
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--bench", required=True)
+    ap.add_argument("--bench-write", help="suite: the JSON of the WRITE_SIZE run, checked against --bench")
     ap.add_argument("--json", default="profiles/traffic.json")
     ap.add_argument("--out", required=True)
     ap.add_argument("--title", default="")

@@ -1,6 +1,7 @@
 """The rocprofv3 summaries on synthetic counter files: calibration against the
 copy kernel, the dominant launch's bytes, and the block bookkeeping of the
-evaluation-suite traffic run (markers, every kernel of a call, call counts)."""
+evaluation-suite traffic run (markers, every kernel of a call, call counts)
+and of the per-variant run of the bandwidth workload (rows grouped by shape)."""
 import csv
 import json
 import os
@@ -60,6 +61,45 @@ def test_suite_traffic_blocks(tmp_path):
     assert "33.3%" in (tmp_path / "s.md").read_text()
 
 
+def test_plans_traffic_groups_by_shape(tmp_path):
+    # --traffic-plans: per width a two-pass row, optionally a row-resident row,
+    # then a split row; every reduction is against the two-pass row of its width
+    calib = 1 << 30
+    blk = lambda N, v, k, m, alg: {"workload": "ln", "M": 2, "N": N, "variant": v, "k": k, "marker_threads": m,
+                                   "launches": 1, "algorithmic_bytes": alg}
+    meta = {"mode": "traffic_plans", "source_hash": "abc", "copy_kernel_bytes": calib, "copy_threads": calib // 16,
+            "blocks": [blk(8, "two_pass", 1, 256, 1200.0), blk(8, "resident", 1, 512, 800.0),
+                       blk(8, "split", 2, 768, 800.0), blk(16, "two_pass", 1, 1024, 2400.0),
+                       blk(16, "split", 4, 1280, 1600.0)]}
+    mp = tmp_path / "meta.json"
+    mp.write_text(json.dumps(meta) + "\n")
+    copy = "credit::k_copy(u32x4 const*, u32x4*, long)"
+    tp = "void credit::k_twopass<1, 0, 256>(credit::RowArgs)"
+    rs = "void credit::k_resident<1, 0, 4>(credit::RowArgs)"
+
+    def seq(f):
+        kib = lambda b: f * b / 1024.0
+        return [(copy, calib // 16, kib(calib)),
+                (copy, 256, 1.0), (tp, 64, kib(1000)),   # width 8: the reread partly cached
+                (copy, 512, 1.0), (rs, 64, kib(800)),
+                (copy, 768, 1.0), (rs, 128, kib(800)),
+                (copy, 1024, 1.0), (tp, 64, kib(2400)),  # width 16: the reread reaches HBM
+                (copy, 1280, 1.0), (rs, 256, kib(1600))]
+
+    _write(tmp_path / "f", "FETCH_SIZE", seq(0.5))
+    _write(tmp_path / "w", "WRITE_SIZE", seq(1.0))
+    R.main(["suite", "--fetch", str(tmp_path / "f"), "--write", str(tmp_path / "w"), "--bench", str(mp),
+            "--json", str(tmp_path / "s.json"), "--out", str(tmp_path / "s.md")])
+    rows = json.load(open(tmp_path / "s.json"))["rows"]
+    assert [r["fetch_bytes"] for r in rows] == [1000, 800, 800, 2400, 1600]
+    md = (tmp_path / "s.md").read_text()
+    assert "variants of the bandwidth workload" in md
+    lines = [ln for ln in md.splitlines() if ln.startswith("| ln |")]
+    assert "row-resident" in lines[1] and lines[1].endswith("| 20.0% |")
+    assert "split k=2" in lines[2] and lines[2].endswith("| 20.0% |")
+    assert lines[3].endswith("|  |") and lines[4].endswith("| 33.3% |")
+
+
 def test_suite_traffic_rejects_a_missing_call(tmp_path):
     calib = 1 << 30
     meta = {"mode": "traffic_suite", "copy_kernel_bytes": calib, "copy_threads": calib // 16,
@@ -73,6 +113,23 @@ def test_suite_traffic_rejects_a_missing_call(tmp_path):
     _write(tmp_path / "w", "WRITE_SIZE", rows)
     with pytest.raises(SystemExit):
         R.main(["suite", "--fetch", str(tmp_path / "f"), "--write", str(tmp_path / "w"), "--bench", str(mp),
+                "--json", str(tmp_path / "s.json"), "--out", str(tmp_path / "s.md")])
+
+
+def test_suite_traffic_rejects_runs_with_different_blocks(tmp_path):
+    calib = 1 << 30
+    blk = {"workload": "w", "M": 1, "N": 1, "variant": "split", "k": 8, "marker_threads": 256, "launches": 1,
+           "algorithmic_bytes": 1.0}
+    meta = {"mode": "traffic_suite", "copy_kernel_bytes": calib, "copy_threads": calib // 16, "blocks": [blk]}
+    (tmp_path / "f.json").write_text(json.dumps(meta) + "\n")
+    (tmp_path / "w.json").write_text(json.dumps(dict(meta, blocks=[dict(blk, k=4)])) + "\n")
+    rows = [("credit::k_copy(x)", calib // 16, 512.0), ("credit::k_copy(x)", 256, 1.0),
+            ("void credit::k_resident<0, 0, 1>(credit::RowArgs)", 8, 1.0)]
+    _write(tmp_path / "f", "FETCH_SIZE", rows)
+    _write(tmp_path / "w", "WRITE_SIZE", rows)
+    with pytest.raises(SystemExit, match="different blocks"):
+        R.main(["suite", "--fetch", str(tmp_path / "f"), "--write", str(tmp_path / "w"),
+                "--bench", str(tmp_path / "f.json"), "--bench-write", str(tmp_path / "w.json"),
                 "--json", str(tmp_path / "s.json"), "--out", str(tmp_path / "s.md")])
 
 
