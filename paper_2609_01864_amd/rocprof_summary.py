@@ -2,7 +2,7 @@
 
     python -m paper_2609_01864_amd.rocprof_summary trace  --trace DIR --bench BENCH.json --out profiles/X.md
     python -m paper_2609_01864_amd.rocprof_summary traffic --fetch DIR --write DIR --bench BENCH.json \
-        --json profiles/traffic.json --out profiles/Y.md
+        --bench-write BENCH_W.json --json profiles/traffic.json --out profiles/Y.md
 
 trace    per-kernel dispatch counts and average durations from a
          `rocprofv3 --kernel-trace --stats --output-format csv` run of the
@@ -117,6 +117,10 @@ def _counter_rows(d: str, counter: str):
 def traffic(args):
     bench = json.loads(open(args.bench).read().strip().splitlines()[-1])
     sym, grid = kernel_name(bench)
+    if args.bench_write:  # the WRITE_SIZE run must have timed the same dominant launch
+        other = json.loads(open(args.bench_write).read().strip().splitlines()[-1])
+        if (other["roofline"]["kernel"], kernel_name(other)) != (bench["roofline"]["kernel"], (sym, grid)):
+            raise SystemExit("the FETCH_SIZE and WRITE_SIZE runs timed different dominant launches")
     copy_bytes = float(bench["copy_kernel_bytes"])  # bytes read (= bytes written) per copy launch
     res = {}
     for counter, d in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
@@ -290,7 +294,7 @@ def main(argv=None):
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--bench", required=True)
-    ap.add_argument("--bench-write", help="suite: the JSON of the WRITE_SIZE run, checked against --bench")
+    ap.add_argument("--bench-write", help="traffic / suite: the JSON of the WRITE_SIZE run, checked against --bench")
     ap.add_argument("--json", default="profiles/traffic.json")
     ap.add_argument("--out", required=True)
     ap.add_argument("--title", default="")

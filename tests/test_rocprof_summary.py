@@ -133,6 +133,44 @@ def test_suite_traffic_rejects_runs_with_different_blocks(tmp_path):
                 "--json", str(tmp_path / "s.json"), "--out", str(tmp_path / "s.md")])
 
 
+def _dominant_bench(kernel="ln:N=8:plan=2,4", grid=4096, alg=4000.0):
+    return {"copy_kernel_bytes": 1 << 30, "source_hash": "abc",
+            "roofline": {"kernel": kernel, "kernel_symbol": "void credit::k_resident<1, 0, 32>",
+                         "grid_threads": grid, "algorithmic_bytes_per_launch": alg}}
+
+
+def test_dominant_traffic_calibrated_per_counter(tmp_path):
+    calib = 1 << 30
+    b = _dominant_bench()
+    (tmp_path / "b.json").write_text(json.dumps(b) + "\n")
+    dom = "void credit::k_resident<1, 0, 32>(credit::RowArgs)"
+    copy = "credit::k_copy(u32x4 const*, u32x4*, long)"
+
+    def seq(f, moved):  # the dominant launch moves `moved` bytes in this direction
+        kib = lambda x: f * x / 1024.0
+        return [(copy, calib // 16, kib(calib)), (dom, 4096, kib(moved)), (dom, 4096, kib(moved)),
+                (dom, 4096, kib(100 * moved))]  # same kernel and grid, another shape: excluded
+
+    _write(tmp_path / "f", "FETCH_SIZE", seq(0.5, 2100))
+    _write(tmp_path / "w", "WRITE_SIZE", seq(1.0, 2000))
+    out = tmp_path / "t.json"
+    R.main(["traffic", "--fetch", str(tmp_path / "f"), "--write", str(tmp_path / "w"), "--bench",
+            str(tmp_path / "b.json"), "--bench-write", str(tmp_path / "b.json"), "--json", str(out),
+            "--out", str(tmp_path / "t.md")])
+    e = json.load(open(out))["kernels"]["ln:N=8:plan=2,4"]
+    assert e["fetch_bytes"] == 2100 and e["write_bytes"] == 2000 and e["bytes_per_launch"] == 4100
+    assert "ratio 1.025" in (tmp_path / "t.md").read_text()
+
+
+def test_dominant_traffic_rejects_runs_with_different_launches(tmp_path):
+    (tmp_path / "f.json").write_text(json.dumps(_dominant_bench()) + "\n")
+    (tmp_path / "w.json").write_text(json.dumps(_dominant_bench(kernel="ln:N=8:plan=2,8", grid=8192)) + "\n")
+    with pytest.raises(SystemExit, match="different dominant launches"):
+        R.main(["traffic", "--fetch", str(tmp_path), "--write", str(tmp_path), "--bench", str(tmp_path / "f.json"),
+                "--bench-write", str(tmp_path / "w.json"), "--json", str(tmp_path / "t.json"),
+                "--out", str(tmp_path / "t.md")])
+
+
 def test_counters_median_and_ratios(tmp_path):
     bench = {"roofline": {"kernel": "layernorm_fwd:N=8:plan=2,2", "kernel_symbol": "void credit::k_resident<1, 0, 1>",
                           "grid_threads": 128, "algorithmic_bytes_per_launch": 8.0 * 1000}, "source_hash": "h"}
