@@ -396,8 +396,12 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             const float csh = kExpShift - cmax, omuls = omul * kExpUnshift;
             if (FP8 && writer) a.so[row] = inv_s / kFp8Max;
             if constexpr (EC || ECI) {
-                // a thread without data (ct = 0) stores nothing: its factor is unused
-                const float f = fast_exp2(ct + csh) * omuls;
+                // ct <= cmax, so the exponent is at most 32 for a thread with a
+                // finite element.  A thread whose elements are all -inf (masked)
+                // has ct = 0 and exponentials of 0; with the row maximum far
+                // below zero its unclamped factor 2^(32 - cmax) would overflow
+                // and 0 * inf would store NaN.  The clamp keeps it finite.
+                const float f = fast_exp2(fminf(ct + csh, 64.f)) * omuls;
 #pragma unroll
                 for (int j = 0; j < VPT; ++j) {
                     float y[EPV];
