@@ -91,3 +91,26 @@ def test_masked_softmax_logits_backward(gpu_handle, dtype, N):
             assert worst <= 1.0, f"{p}: {worst:.3f} bf16 ulp"
         assert np.all(got[np.isneginf(xv)] == 0.0), f"{p}: masked entries have a gradient"
     assert h.check_errors() == C.OK
+
+
+@pytest.mark.parametrize("N", [1000, 65536])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_fully_masked_row_is_nan_like_the_oracle(gpu_handle, dtype, N):
+    # softmax of a row of -inf is 0/0: the oracle (and torch) give NaN; every
+    # plan gives NaN on that row and leaves the neighbouring rows intact
+    h = gpu_handle
+    x64 = I.softmax_rows(3, N, 33)
+    x64[1, :] = -np.inf
+    raw, _ = I.store(x64, dtype)
+    xv = oracle.decode(raw, dtype)
+    with np.errstate(invalid="ignore"):
+        ref = oracle.softmax_fwd(xv)
+    assert np.all(np.isnan(ref[1])) and np.all(np.isfinite(ref[[0, 2]]))
+    x = to_device(raw, dtype)
+    for p in plans(h, "fwd", dtype, 3, N):
+        print(f"[masked] fully masked row {dtype} N={N} {p}", flush=True)
+        y, _ = C.softmax_fwd(x, p=p, h=h)
+        got = from_device(y, dtype)
+        assert np.all(np.isnan(got[1])), f"{p}: fully masked row not NaN"
+        check_tensor("y", "softmax_fwd", dtype, got[[0, 2]], ref[[0, 2]], np.abs(ref[[0, 2]]))
+    assert h.check_errors() == C.OK
