@@ -1,0 +1,63 @@
+"""Row-wise int8 and e4m3 quantisation on rows built to hit exact rounding
+ties, bit-exact against the FP64 oracle on every legal plan: each row's
+amax makes the scale a power of two (int8: amax = 127/8, multiplier 8;
+e4m3: amax = 112, multiplier 4), so value * multiplier lands exactly halfway
+between two codes and round-to-nearest-even decides.  Also an all-zero row
+(scale 1, codes 0) and a row with a single nonzero value."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2609_01864_amd import credit as C
+
+from _cases import ALL_PLANS, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def tie_rows(N: int, fmt: str) -> np.ndarray:
+    rng = np.random.default_rng([51, N, fmt == "int8"])
+    x = np.zeros((4, N))
+    if fmt == "int8":
+        mult = 8.0
+        for r in (1, 2):
+            k = rng.integers(-127, 127, N)           # (k + 0.5) lies in [-126.5, 126.5]
+            x[r] = (k + 0.5) / mult
+            x[r, rng.integers(N)] = (127.0 if r == 1 else -127.0) / mult   # the row's amax
+    else:
+        mult = 4.0
+        for r in (1, 2):
+            e = rng.integers(-6, 8, N)               # normal binades up to 2^8
+            m = rng.integers(0, 8, N)                # halfway above mantissa m (m = 7: below the next power)
+            v = np.ldexp(1.0 + (m + 0.5) / 8.0, e)
+            sub = rng.random(N) < 0.1                # subnormal midpoints (j + 1/2) 2^-9
+            v[sub] = (rng.integers(0, 7, sub.sum()) + 0.5) * 2.0 ** -9
+            x[r] = np.where(rng.random(N) < 0.5, -v, v) / mult
+            x[r, rng.integers(N)] = (448.0 if r == 1 else -448.0) / mult
+    x[3, rng.integers(N)] = -3.0                     # one nonzero value; row 0 stays zero
+    return x.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("N", [3001, 65536])
+@pytest.mark.parametrize("fmt", ["int8", "fp8"])
+def test_quantisation_ties_zero_and_single_value_rows(gpu_handle, fmt, N):
+    h = gpu_handle
+    x = tie_rows(N, fmt)
+    mult = 8.0 if fmt == "int8" else 4.0
+    assert np.all(np.abs(x[1:3]).max(axis=1) * mult == (127.0 if fmt == "int8" else 448.0))
+    codes_ref, scale_ref = oracle.quantize_rows(x.astype(np.float32), fmt)
+    assert scale_ref[0] == 1.0 and np.all(codes_ref[0] == 0)
+    op = C.QUANT_INT8 if fmt == "int8" else C.QUANT_FP8
+    xd = to_device(x.astype(np.float32), "f32")
+    for v, k in ALL_PLANS:
+        p = C.plan(v, k)
+        if not h.plan_legal(op, C.FWD, C.F32, 4, N, p):
+            continue
+        print(f"[quant ties] {fmt} N={N} {p}", flush=True)
+        q, qs = C.quantize_rows(xd, fmt, p=p, h=h)
+        torch.cuda.synchronize()
+        assert np.array_equal(qs.cpu().numpy().view(np.uint32), scale_ref.view(np.uint32)), f"{p}: scale"
+        bad = np.flatnonzero(q.cpu().numpy().view(np.uint8) != codes_ref.view(np.uint8))
+        assert bad.size == 0, f"{p}: {bad.size} codes differ, first at {bad[0]}"
+    assert h.check_errors() == C.OK
