@@ -167,7 +167,9 @@ credit_status_t credit_select(credit_handle_t h, credit_op_t op, credit_dir_t di
 
 /* ---------------------------------------------------------------- operators */
 
-/* Row softmax: y = exp(x - max x) / sum exp(x - max x). */
+/* Row softmax: y = exp(x - max x) / sum exp(x - max x).  Entries of -inf
+ * (masks, FP32 / BF16) give 0; a row with no finite entry is 0/0 and gives
+ * NaN, like the plain definition. */
 credit_status_t credit_softmax_fwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
                                    const void *x, int64_t ldx, const float *x_scale, void *y,
                                    int64_t ldy, float *y_scale, const credit_plan_t *plan,
