@@ -424,8 +424,12 @@ def main():
             us = 1e3 * sum(a.elapsed_time(b) for a, b in events[(op, N)]) / len(events[(op, N)])
             gb = algorithmic_bytes(op, M_ROWS, N) / (us * 1e-6) / 1e9
             p = picks[(op, N)][0]
+            g = h.geometry(opnum[op], C.FWD, C.F32, M_ROWS, N, p)
             per_shape.append({"op": op, "N": N, "plan": [int(p.variant), int(p.k)], "us": round(us, 2),
-                              "gbps": round(gb, 1), "frac": round(gb / PEAK_GBPS, 4)})
+                              "gbps": round(gb, 1), "frac": round(gb / PEAK_GBPS, 4),
+                              # launch shape: workgroups, co-resident workgroups per CU
+                              # (runtime occupancy) and 16-byte vectors per thread
+                              "geometry": {"grid": g["grid"], "per_cu": g["per_cu"], "vpt": g["vpt"]}})
     dom = max(per_shape, key=lambda r: r["us"])
     dom_key = f"{dom['op']}:N={dom['N']}:plan={dom['plan'][0]},{dom['plan'][1]}"
     sym, grid_threads = kernel_symbol(C, h, opnum[dom["op"]], C.F32, M_ROWS, dom["N"], picks[(dom["op"], dom["N"])][0])
