@@ -58,6 +58,30 @@ def test_softmax_special_cases():
     assert oracle.softmax_fwd(np.array([[123.0]]))[0, 0] == 1.0
 
 
+def test_softmax_masked_entries_reduce_to_the_unmasked_subset():
+    # an entry of -inf drops out: the row's softmax equals the softmax of its
+    # finite entries alone, placed back, with 0 where masked; the from-logits
+    # backward likewise gives 0 there and the subset's gradient elsewhere
+    x = RNG.standard_normal((3, 40)) * 4
+    mask = RNG.random((3, 40)) < 0.4
+    mask[2, :39] = True  # a single finite entry: a one-hot row
+    dy = RNG.standard_normal((3, 40))
+    xm = np.where(mask, -np.inf, x)
+    y = oracle.softmax_fwd(xm)
+    dx = oracle.softmax_logits_bwd(xm, dy)
+    for r in range(3):
+        keep = ~mask[r]
+        sub = x[r, keep][None, :]
+        assert np.all(y[r, mask[r]] == 0.0) and np.all(dx[r, mask[r]] == 0.0)
+        np.testing.assert_allclose(y[r, keep], oracle.softmax_fwd(sub)[0], rtol=1e-14, atol=0)
+        np.testing.assert_allclose(dx[r, keep], oracle.softmax_logits_bwd(sub, dy[r, keep][None, :])[0],
+                                   rtol=1e-12, atol=1e-15)
+    assert y[2, 39] == 1.0 and dx[2, 39] == 0.0
+    # no finite entry: 0/0
+    with np.errstate(invalid="ignore"):
+        assert np.all(np.isnan(oracle.softmax_fwd(np.full((1, 8), -np.inf))))
+
+
 def test_softmax_matches_independent_library():
     x = 4.0 * RNG.standard_normal((4, 8))
     ref = torch.softmax(torch.from_numpy(x), dim=1).numpy()
