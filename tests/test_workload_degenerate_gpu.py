@@ -27,7 +27,8 @@ def _set(case, **rows):
 
 
 def _run_all(h, case, tag):
-    ref = case.reference()
+    with np.errstate(divide="ignore", invalid="ignore"):  # undefined rows are 0/0
+        ref = case.reference()
     for p in legal_plans(h, case.op, case.dtype, case.M, case.N):
         print(f"[degenerate] {tag} {case.dtype} N={case.N} {p}", flush=True)
         try:
@@ -69,3 +70,22 @@ def test_layernorm_fp8_out_of_a_zero_output_row(gpu_handle, dtype, N):
     _set(case, x=x)
     case.beta = np.zeros_like(case.beta)
     _run_all(gpu_handle, case, "lnq")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_undefined_statistics_are_non_finite_like_the_oracle(gpu_handle, dtype):
+    # Pearson with a constant x (S_xx = 0) and weighted variance with all
+    # weights 0 (W = 0) are 0/0: the oracle's plain definitions give
+    # non-finite gradients there, and so must every plan, with the other
+    # rows intact (the finiteness rule of the workload checks)
+    N = 5003
+    case = WCase("pearson", dtype, 3, N, seed=64)
+    x, y = I.correlated_rows(3, N, 64)
+    x[1] = 1.5
+    _set(case, x=x, y=y)
+    _run_all(gpu_handle, case, "pearson undefined")
+    case = WCase("wvar", dtype, 3, N, seed=65)
+    w = I.uniform_rows(3, N, 65, 1)
+    w[1] = 0.0
+    _set(case, w=w)
+    _run_all(gpu_handle, case, "wvar undefined")
