@@ -10,6 +10,7 @@ import torch
 
 import oracle
 from paper_2609_01864_amd import credit as C
+from paper_2609_01864_amd import inputs as I
 
 from _cases import ALL_PLANS, to_device
 
@@ -41,20 +42,25 @@ def tie_rows(N: int, fmt: str) -> np.ndarray:
 
 @pytest.mark.parametrize("N", [3001, 65536])
 @pytest.mark.parametrize("fmt", ["int8", "fp8"])
-def test_quantisation_ties_zero_and_single_value_rows(gpu_handle, fmt, N):
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_quantisation_ties_zero_and_single_value_rows(gpu_handle, dtype, fmt, N):
+    # every value of these rows has at most 8 significant bits, so BF16 input
+    # holds them exactly and the expected codes are the same
     h = gpu_handle
     x = tie_rows(N, fmt)
+    raw, _ = I.store(x, dtype)
+    assert np.array_equal(oracle.decode(raw, dtype), x)
     mult = 8.0 if fmt == "int8" else 4.0
     assert np.all(np.abs(x[1:3]).max(axis=1) * mult == (127.0 if fmt == "int8" else 448.0))
     codes_ref, scale_ref = oracle.quantize_rows(x.astype(np.float32), fmt)
     assert scale_ref[0] == 1.0 and np.all(codes_ref[0] == 0)
     op = C.QUANT_INT8 if fmt == "int8" else C.QUANT_FP8
-    xd = to_device(x.astype(np.float32), "f32")
+    xd = to_device(raw, dtype)
     for v, k in ALL_PLANS:
         p = C.plan(v, k)
-        if not h.plan_legal(op, C.FWD, C.F32, 4, N, p):
+        if not h.plan_legal(op, C.FWD, C.DTYPE_NAMES[dtype], 4, N, p):
             continue
-        print(f"[quant ties] {fmt} N={N} {p}", flush=True)
+        print(f"[quant ties] {dtype} -> {fmt} N={N} {p}", flush=True)
         q, qs = C.quantize_rows(xd, fmt, p=p, h=h)
         torch.cuda.synchronize()
         assert np.array_equal(qs.cpu().numpy().view(np.uint32), scale_ref.view(np.uint32)), f"{p}: scale"
