@@ -46,3 +46,34 @@ def test_degenerate_rows(gpu_handle, op, dtype, N):
             check_case(case, case.run(h, p, ref=ref), ref)
         except AssertionError as e:
             raise AssertionError(f"{p}: {e}") from None
+
+
+@pytest.mark.parametrize("N", [3001, 65536])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_softmax_backward_of_one_hot_and_uniform_rows(gpu_handle, dtype, N):
+    # y one-hot: dx = 0 exactly (in FP8 the stored 1 is 448 times the FP32
+    # scale 1/448, a hair off 1, so dx is tiny there instead);
+    # y uniform 1/N: dx = (dy - mean dy) / N; y with two equal halves
+    h = gpu_handle
+    y = np.zeros((3, N))
+    y[0, N // 3] = 1.0
+    y[1] = 1.0 / N
+    y[2, : N // 2] = 1.0 / (2 * (N // 2))
+    case = Case("softmax_bwd", dtype, 3, N, seed=42)
+    case.raw["y"] = I.store(y, dtype)
+    case.vals = {k: oracle.decode(r, dtype, s) for k, (r, s) in case.raw.items()}
+    ref = case.reference()
+    exact = dtype != "fp8"
+    assert np.all(ref["dx"][0] == 0.0) or not exact
+    o, d = OPNUM["softmax_bwd"]
+    for v, kk in ALL_PLANS:
+        p = C.plan(v, kk)
+        if not h.plan_legal(o, d, C.DTYPE_NAMES[dtype], 3, N, p):
+            continue
+        print(f"[degenerate] softmax_bwd {dtype} N={N} {p}", flush=True)
+        out = case.run(h, p, ref=ref)
+        assert np.all(out["dx"][0] == 0.0) or not exact, f"{p}: one-hot row has a gradient"
+        try:
+            check_case(case, out, ref)
+        except AssertionError as e:
+            raise AssertionError(f"{p}: {e}") from None
