@@ -200,7 +200,9 @@ def plan_of_class(c: int) -> Plan:
 def model_delta(handle, op, direction, dtype, M, N, t_base_us, t_ctrl_us):
     import numpy as np
 
-    ctrl = np.ascontiguousarray(t_ctrl_us, np.float32)
+    ctrl = np.ascontiguousarray(t_ctrl_us, np.float32).reshape(-1)
+    if ctrl.size != 5:  # the library reads one value per k = 2, 4, 8, 16, 32
+        raise ValueError(f"t_ctrl_us needs 5 entries (k = 2, 4, 8, 16, 32), got {ctrl.size}")
     out = np.zeros(5, np.float32)
     h = handle.ptr if handle is not None else None
     check(lib().credit_model_delta(h, op, direction, dtype, M, N, float(t_base_us), ctrl.ctypes.data,

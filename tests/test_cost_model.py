@@ -211,3 +211,13 @@ def test_library_operators_are_all_in_the_class(lib_built):
             except C.CreditError:
                 continue  # (op, dtype) pair that does not exist
             assert w.b_base > w.b_staged > 0, (op, d, dt)
+
+
+def test_library_model_delta_rejects_a_short_control_time_list(lib_built):
+    # the library reads one control-kernel time per k = 2, 4, 8, 16, 32; the
+    # binding refuses any other length instead of letting it read past the end
+    from paper_2609_01864_amd import credit as C
+
+    for ctrl in ([1.0, 2.0], [1.0] * 6):
+        with pytest.raises(ValueError):
+            C.model_delta(None, C.LAYERNORM, C.FWD, C.F32, 1024, 131072, 100.0, ctrl)
