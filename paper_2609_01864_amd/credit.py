@@ -226,6 +226,26 @@ def set_epoch(e: int) -> None:
 
 
 # ------------------------------------------------------------------ handle
+def _mlp_arrays(feats, targets=None, mask=None):
+    """Contiguous FP32 features [n, NUM_FEATURES] (and FP32 targets / uint8
+    mask [n, NUM_PLANS]); the library reads exactly those sizes, so any other
+    shape is refused here."""
+    import numpy as np
+
+    f = np.ascontiguousarray(feats, np.float32)
+    if f.ndim != 2 or f.shape[1] != NUM_FEATURES:
+        raise ValueError(f"features must be [n, {NUM_FEATURES}], got {f.shape}")
+    out = [f]
+    for a, dt, name in ((targets, np.float32, "targets"), (mask, np.uint8, "mask")):
+        if a is None:
+            continue
+        a = np.ascontiguousarray(a, dt)
+        if a.shape != (f.shape[0], NUM_PLANS):
+            raise ValueError(f"{name} must be [{f.shape[0]}, {NUM_PLANS}], got {a.shape}")
+        out.append(a)
+    return out
+
+
 def _torch():
     import torch
 
@@ -357,17 +377,17 @@ class Handle:
     def mlp_set(self, params, mu, sd) -> None:
         import numpy as np
 
-        p = np.ascontiguousarray(params, np.float32)
-        m = np.ascontiguousarray(mu, np.float32)
-        s = np.ascontiguousarray(sd, np.float32)
+        p = np.ascontiguousarray(params, np.float32).reshape(-1)
+        m = np.ascontiguousarray(mu, np.float32).reshape(-1)
+        s = np.ascontiguousarray(sd, np.float32).reshape(-1)
+        if p.size != lib().credit_mlp_num_params() or m.size != NUM_FEATURES or s.size != NUM_FEATURES:
+            raise ValueError("mlp_set: wrong number of parameters or standardization entries")
         check(lib().credit_mlp_set(self.ptr, p.ctypes.data, m.ctypes.data, s.ctypes.data), "credit_mlp_set")
 
     def mlp_grad(self, feats, targets, mask):
         import numpy as np
 
-        f = np.ascontiguousarray(feats, np.float32)
-        t = np.ascontiguousarray(targets, np.float32)
-        m = np.ascontiguousarray(mask, np.uint8)
+        f, t, m = _mlp_arrays(feats, targets, mask)
         g = np.zeros(lib().credit_mlp_num_params(), np.float32)
         loss = _F()
         check(lib().credit_mlp_grad(self.ptr, f.ctypes.data, t.ctypes.data, m.ctypes.data, f.shape[0],
@@ -377,9 +397,7 @@ class Handle:
     def mlp_train(self, feats, targets, mask, epochs: int, lr: float = 1e-3, seed: int = 1) -> float:
         import numpy as np
 
-        f = np.ascontiguousarray(feats, np.float32)
-        t = np.ascontiguousarray(targets, np.float32)
-        m = np.ascontiguousarray(mask, np.uint8)
+        f, t, m = _mlp_arrays(feats, targets, mask)
         loss = _F()
         check(lib().credit_mlp_train(self.ptr, f.ctypes.data, t.ctypes.data, m.ctypes.data, f.shape[0], epochs,
                                      lr, seed, ctypes.byref(loss)), "credit_mlp_train")
@@ -389,7 +407,7 @@ class Handle:
     def mlp_predict(self, feats):
         import numpy as np
 
-        f = np.ascontiguousarray(feats, np.float32)
+        (f,) = _mlp_arrays(feats)
         out = np.zeros((f.shape[0], NUM_PLANS), np.float32)
         check(lib().credit_mlp_predict(self.ptr, f.ctypes.data, f.shape[0], out.ctypes.data), "credit_mlp_predict")
         return out

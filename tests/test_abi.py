@@ -107,3 +107,27 @@ def test_null_handle_rejected_by_operators(lib_built):
 
     s = C.lib().credit_softmax_fwd(None, 4, 4, C.F32, None, 4, None, None, 4, None, None, None, 0, None)
     assert s == C.ERR_INVALID_ARG
+
+
+def test_mlp_binding_refuses_wrong_shapes(lib_built):
+    # the library reads [n, 12] features, [n, 7] targets and masks and the
+    # exact parameter count; the binding refuses anything else before the call
+    import numpy as np
+
+    from paper_2609_01864_amd import credit as C
+
+    n = 4
+    good_f = np.zeros((n, C.NUM_FEATURES), np.float32)
+    good_t = np.zeros((n, C.NUM_PLANS), np.float32)
+    good_m = np.ones((n, C.NUM_PLANS), np.uint8)
+    with pytest.raises(ValueError):
+        C.Handle.mlp_predict(None, np.zeros((n, 11), np.float32))
+    with pytest.raises(ValueError):
+        C.Handle.mlp_predict(None, np.zeros(C.NUM_FEATURES, np.float32))
+    with pytest.raises(ValueError):
+        C.Handle.mlp_grad(None, good_f, good_t[:, :6], good_m)
+    with pytest.raises(ValueError):
+        C.Handle.mlp_train(None, good_f, good_t, good_m[:3], epochs=1)
+    params = np.zeros(C.lib().credit_mlp_num_params() - 1, np.float32)
+    with pytest.raises(ValueError):
+        C.Handle.mlp_set(None, params, np.zeros(12, np.float32), np.ones(12, np.float32))
