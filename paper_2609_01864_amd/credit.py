@@ -273,6 +273,30 @@ def _ld(t) -> int:
     return t.stride(0)
 
 
+def _validate(M, N, ref, mats=(), vecs=()):
+    """Checks what the kernels will read and write before the launch: every
+    matrix operand is [M, N] with unit inner stride, on the device of `ref`
+    and in its I/O dtype (None entries skipped); every vector operand is FP32
+    on that device with at least the given number of contiguous elements.
+    The library sees raw pointers only, so a short vector would be read out
+    of bounds on the GPU."""
+    torch = _torch()
+    for t, name in mats:
+        if t is None:
+            continue
+        if tuple(t.shape) != (M, N) or t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError(f"{name}: expected [{M}, {N}] with unit inner stride, got {tuple(t.shape)}")
+        if t.device != ref.device or t.dtype != ref.dtype:
+            raise ValueError(f"{name}: expected {ref.dtype} on {ref.device}, got {t.dtype} on {t.device}")
+    for t, n, name in vecs:
+        if t is None:
+            continue
+        if t.dtype != torch.float32 or t.device != ref.device:
+            raise ValueError(f"{name}: expected float32 on {ref.device}, got {t.dtype} on {t.device}")
+        if t.numel() < n or (t.numel() > 1 and t.dim() == 1 and t.stride(0) != 1) or t.dim() > 1 and not t.is_contiguous():
+            raise ValueError(f"{name}: expected at least {n} contiguous elements, got {tuple(t.shape)}")
+
+
 class Handle:
     """A library handle bound to one HIP device, with per-stream workspaces."""
 
@@ -466,6 +490,7 @@ def softmax_fwd(x, x_scale=None, p: Optional[Plan] = None, out=None, out_scale=N
     h = h or handle(x.device.index)
     dt = io_dtype(x)
     M, N = x.shape
+    _validate(M, N, x, [(out, "out")], [(x_scale, M, "x_scale"), (out_scale, M, "out_scale")])
     y = out if out is not None else _empty_like_out(x, M, N)
     ys = out_scale if out_scale is not None else (_scale_out(x, M) if dt == FP8 else None)
     s = h._stream()
@@ -480,6 +505,7 @@ def softmax_bwd(y, dy, y_scale=None, dy_scale=None, p: Optional[Plan] = None, ou
     h = h or handle(y.device.index)
     dt = io_dtype(y)
     M, N = y.shape
+    _validate(M, N, y, [(dy, "dy"), (out, "out")], [(y_scale, M, "y_scale"), (dy_scale, M, "dy_scale")])
     dx = out if out is not None else _empty_like_out(y, M, N)
     dxs = _scale_out(y, M) if dt == FP8 else None
     s = h._stream()
@@ -497,6 +523,7 @@ def layernorm_fwd(x, gamma, beta, eps: float = 1e-5, x_scale=None, p: Optional[P
     h = h or handle(x.device.index)
     dt = io_dtype(x)
     M, N = x.shape
+    _validate(M, N, x, [(out, "out")], [(gamma, N, "gamma"), (beta, N, "beta"), (x_scale, M, "x_scale")])
     y = out if out is not None else _empty_like_out(x, M, N)
     ys = _scale_out(x, M) if dt == FP8 else None
     mean = torch.empty(M, dtype=torch.float32, device=x.device) if save_stats else None
@@ -517,6 +544,8 @@ def layernorm_bwd(x, dy, gamma, mean=None, rstd=None, eps: float = 1e-5, x_scale
     h = h or handle(x.device.index)
     dt = io_dtype(x)
     M, N = x.shape
+    _validate(M, N, x, [(dy, "dy")], [(gamma, N, "gamma"), (mean, M, "mean"), (rstd, M, "rstd"),
+                                     (x_scale, M, "x_scale"), (dy_scale, M, "dy_scale")])
     dx = _empty_like_out(x, M, N)
     dxs = _scale_out(x, M) if dt == FP8 else None
     dg = torch.empty(N, dtype=torch.float32, device=x.device) if need_dgamma else None
@@ -537,6 +566,7 @@ def rmsnorm_fwd(x, gamma, eps: float = 1e-5, x_scale=None, p: Optional[Plan] = N
     h = h or handle(x.device.index)
     dt = io_dtype(x)
     M, N = x.shape
+    _validate(M, N, x, [(out, "out")], [(gamma, N, "gamma"), (x_scale, M, "x_scale")])
     y = out if out is not None else _empty_like_out(x, M, N)
     ys = _scale_out(x, M) if dt == FP8 else None
     rstd = torch.empty(M, dtype=torch.float32, device=x.device) if save_stats else None
@@ -555,6 +585,8 @@ def rmsnorm_bwd(x, dy, gamma, rstd=None, eps: float = 1e-5, x_scale=None, dy_sca
     h = h or handle(x.device.index)
     dt = io_dtype(x)
     M, N = x.shape
+    _validate(M, N, x, [(dy, "dy")], [(gamma, N, "gamma"), (rstd, M, "rstd"), (x_scale, M, "x_scale"),
+                                     (dy_scale, M, "dy_scale")])
     dx = _empty_like_out(x, M, N)
     dxs = _scale_out(x, M) if dt == FP8 else None
     dg = torch.empty(N, dtype=torch.float32, device=x.device) if need_dgamma else None
@@ -574,6 +606,7 @@ def softmax_logits_bwd(x, dy, x_scale=None, dy_scale=None, p: Optional[Plan] = N
     h = h or handle(x.device.index)
     dt = io_dtype(x)
     M, N = x.shape
+    _validate(M, N, x, [(dy, "dy"), (out, "out")], [(x_scale, M, "x_scale"), (dy_scale, M, "dy_scale")])
     dx = out if out is not None else _empty_like_out(x, M, N)
     dxs = _scale_out(x, M) if dt == FP8 else None
     s = h._stream()
@@ -594,6 +627,9 @@ def quantize_rows(x, fmt: str = "int8", p: Optional[Plan] = None, out=None, out_
     dt = io_dtype(x)
     op = {"int8": QUANT_INT8, "fp8": QUANT_FP8}[fmt]
     M, N = x.shape
+    _validate(M, N, x, [], [(out_scale, M, "out_scale")])
+    if out is not None and (tuple(out.shape) != (M, N) or out.device != x.device):
+        raise ValueError(f"out: expected [{M}, {N}] codes on {x.device}, got {tuple(out.shape)} on {out.device}")
     q = out if out is not None else torch.empty((M, N), dtype=torch.int8 if fmt == "int8" else torch.uint8,
                                                 device=x.device)
     qs = out_scale if out_scale is not None else _scale_out(x, M)
@@ -612,6 +648,7 @@ def layernorm_fwd_fp8_out(x, gamma, beta, eps: float = 1e-5, p: Optional[Plan] =
     h = h or handle(x.device.index)
     dt = io_dtype(x)
     M, N = x.shape
+    _validate(M, N, x, [], [(gamma, N, "gamma"), (beta, N, "beta")])
     q = torch.empty((M, N), dtype=torch.uint8, device=x.device)
     qs = _scale_out(x, M)
     mean = torch.empty(M, dtype=torch.float32, device=x.device) if save_stats else None
@@ -630,6 +667,7 @@ def pearson_bwd(x, y, dr, p: Optional[Plan] = None, h: Optional[Handle] = None):
     h = h or handle(x.device.index)
     dt = io_dtype(x)
     M, N = x.shape
+    _validate(M, N, x, [(y, "y")], [(dr, M, "dr")])
     gx, gy = _empty_like_out(x, M, N), _empty_like_out(x, M, N)
     s = h._stream()
     pp = None if p is None else ctypes.byref(p)
@@ -645,6 +683,7 @@ def wvar_bwd(x, w, dv, p: Optional[Plan] = None, h: Optional[Handle] = None):
     h = h or handle(x.device.index)
     dt = io_dtype(x)
     M, N = x.shape
+    _validate(M, N, x, [(w, "w")], [(dv, M, "dv")])
     gx, gw = _empty_like_out(x, M, N), _empty_like_out(x, M, N)
     s = h._stream()
     pp = None if p is None else ctypes.byref(p)

@@ -131,3 +131,27 @@ def test_mlp_binding_refuses_wrong_shapes(lib_built):
     params = np.zeros(C.lib().credit_mlp_num_params() - 1, np.float32)
     with pytest.raises(ValueError):
         C.Handle.mlp_set(None, params, np.zeros(12, np.float32), np.ones(12, np.float32))
+
+
+def test_operand_validation_before_launch():
+    # the binding checks what the kernels will touch (the library sees raw
+    # pointers): matrix operands [M, N] in the input's dtype and device,
+    # vector operands FP32 with at least the required contiguous length
+    import torch
+
+    from paper_2609_01864_amd import credit as C
+
+    x = torch.zeros((3, 8))
+    C._validate(3, 8, x, [(torch.zeros((3, 8)), "dy"), (None, "out")],
+                [(torch.zeros(8), 8, "gamma"), (None, 3, "mean"), (torch.zeros(0), 0, "dr")])
+    bad = [
+        ([(torch.zeros((3, 7)), "dy")], []),                        # wrong width
+        ([(torch.zeros((8, 3)).t(), "dy")], []),                   # not unit inner stride
+        ([(torch.zeros((3, 8), dtype=torch.bfloat16), "dy")], []),  # dtype differs from x
+        ([], [(torch.zeros(7), 8, "gamma")]),                       # too short
+        ([], [(torch.zeros(8, dtype=torch.float64), 8, "gamma")]),  # not FP32
+        ([], [(torch.zeros(16)[::2], 8, "gamma")]),                 # strided
+    ]
+    for mats, vecs in bad:
+        with pytest.raises(ValueError):
+            C._validate(3, 8, x, mats, vecs)
