@@ -698,6 +698,9 @@ def encode(x, dtype: int, row_scale=None, h: Optional[Handle] = None):
     torch = _torch()
     h = h or handle(x.device.index)
     M, N = x.shape
+    if x.dtype != torch.float32 or not x.is_contiguous():  # the codec reads M * N packed values
+        raise ValueError("encode: x must be a contiguous float32 [M, N] tensor")
+    _validate(M, N, x, [], [(row_scale, M, "row_scale")])
     tdt = {F32: torch.float32, BF16: torch.bfloat16, FP8: torch.uint8}[dtype]
     out = torch.empty((M, N), dtype=tdt, device=x.device)
     check(lib().credit_encode(h.ptr, M, N, dtype, _ptr(x), _ptr(row_scale), _ptr(out), h._stream()),
@@ -711,6 +714,9 @@ def decode(codes, row_scale=None, h: Optional[Handle] = None):
     h = h or handle(codes.device.index)
     dt = io_dtype(codes)
     M, N = codes.shape
+    if not codes.is_contiguous():  # the codec reads M * N packed codes
+        raise ValueError("decode: codes must be a contiguous [M, N] tensor")
+    _validate(M, N, codes, [], [(row_scale, M, "row_scale")])
     out = torch.empty((M, N), dtype=torch.float32, device=codes.device)
     check(lib().credit_decode(h.ptr, M, N, dt, _ptr(codes), _ptr(row_scale), _ptr(out), h._stream()),
           "credit_decode")
