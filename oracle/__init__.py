@@ -70,6 +70,7 @@ def _load():
         "oracle_rmsnorm_bwd": ([_I64, _I64, P, P, P, ctypes.c_double, P, P, P], None),
         "oracle_softmax_logits_bwd": ([_I64, _I64, P, P, P], None),
         "oracle_quantize_rows": ([_I64, _I64, P, ctypes.c_int, P, P], None),
+        "oracle_quantize_rows_fp32_product": ([_I64, _I64, P, ctypes.c_int, P], None),
         "oracle_pearson_bwd": ([_I64, _I64, P, P, P, P, P], None),
         "oracle_wvar_bwd": ([_I64, _I64, P, P, P, P, P], None),
     }
@@ -221,16 +222,34 @@ def softmax_logits_bwd(x, dy) -> np.ndarray:
 
 
 def quantize_rows(x, fmt: str):
-    """Row-wise quantisation of FP32-representable values; decisions in FP32.
-    fmt 'int8' -> (int8 codes, FP32 scales); 'fp8' -> (uint8 e4m3 codes, scales)."""
-    x32 = np.ascontiguousarray(x, dtype=np.float32)
-    if x32.astype(np.float64).tolist() != np.asarray(x, dtype=np.float64).tolist():
-        raise ValueError("quantize_rows takes values exactly representable in FP32")
+    """Row-wise quantisation of FP32-representable values (Sec. IV-A workload):
+    codes = nearest grid point to x * Q / amax, ties to even, decided exactly
+    (Q = 127 for 'int8', 448 for 'fp8'); scale = amax / Q rounded to FP32.
+    Returns (int8 codes, FP32 scales) or (uint8 e4m3 codes, scales)."""
+    x32 = _fp32_exact(x)
     M, N = x32.shape
     codes = np.empty((M, N), dtype=np.uint8)
     scale = np.empty(M, dtype=np.float32)
     _load().oracle_quantize_rows(M, N, _p(x32), 0 if fmt == "int8" else 1, _p(codes), _p(scale))
     return (codes.view(np.int8) if fmt == "int8" else codes), scale
+
+
+def quantize_rows_fp32_product(x, fmt: str):
+    """The codes an FP32 evaluation gives: v = x * fl32(Q / amax) rounded to
+    FP32, then rounded to the grid.  Not the definition: used by the tests to
+    show where it departs from it."""
+    x32 = _fp32_exact(x)
+    M, N = x32.shape
+    codes = np.empty((M, N), dtype=np.uint8)
+    _load().oracle_quantize_rows_fp32_product(M, N, _p(x32), 0 if fmt == "int8" else 1, _p(codes))
+    return codes.view(np.int8) if fmt == "int8" else codes
+
+
+def _fp32_exact(x):
+    x32 = np.ascontiguousarray(x, dtype=np.float32)
+    if x32.astype(np.float64).tolist() != np.asarray(x, dtype=np.float64).tolist():
+        raise ValueError("quantize_rows takes values exactly representable in FP32")
+    return x32
 
 
 def pearson_bwd(x, y, dr):

@@ -346,17 +346,75 @@ void oracle_softmax_logits_bwd(int64_t M, int64_t N, const double *x, const doub
     }
 }
 
-/* Row-wise quantisation (the int8-quantisation workload).  The codes are
- * integer decisions, so they are taken in the precision the library computes
- * in, FP32, step by step: amax = max |x| (exact), inv = Q / amax and
- * scale = amax / Q, each one correctly rounded FP32 division (1 and 1 for an
- * all-zero row), v = x * inv rounded to FP32.  fmt 0 (int8, Q = 127):
- * code = v rounded half to even, clamped to [-127, 127], stored two's
- * complement.  fmt 1 (e4m3, Q = 448): code = e4m3 RNE of v saturated to +-448.
+/* Row-wise quantisation (the int8-quantisation workload of Sec. IV-A).  Per
+ * row: amax = max |x| (exact), and each code is the nearest point of the code
+ * grid to the real number x * Q / amax, ties to the even code; the row scale is
+ * amax / Q rounded once to FP32.  An all-zero row has scale 1 and codes 0.
+ * fmt 0 (int8, Q = 127): the grid is the integers -127..127, stored two's
+ * complement.  fmt 1 (e4m3, Q = 448): the grid is the finite e4m3fn values
+ * (|x| <= amax keeps x * Q / amax inside +-448, so nothing saturates).
+ *
+ * The decisions are exact: x and amax are binary32 numbers (24-bit
+ * significands), Q is a 7- or 9-bit integer, and every grid point or midpoint
+ * g has at most 9 significant bits, so both sides of the comparison
+ * x * Q <=> g * amax are exact products in binary64.  Nothing here evaluates
+ * x * Q / amax in floating point to take a decision.
  * x holds FP32 values (BF16 inputs are exact in FP32). */
+
+/* Sorted non-negative e4m3 magnitudes: codes 0x00..0x7E are increasing. */
+static double e4m3_mag[127];
+static void e4m3_mag_init(void)
+{
+    for (int c = 0; c < 127; ++c) e4m3_mag[c] = e4m3_value((uint8_t)c);
+}
+
+/* int8 code of x * Q / amax (amax > 0). */
+static int8_t int8_code_exact(double x, double Q, double amax)
+{
+    const double xq = x * Q;                /* exact */
+    /* f = floor(x * Q / amax): start from a nearby integer, then step until
+     * f * amax <= xq < (f + 1) * amax holds exactly */
+    double f = floor(xq / amax);
+    while (f * amax > xq) f -= 1.0;
+    while ((f + 1.0) * amax <= xq) f += 1.0;
+    /* nearest of f, f + 1: compare 2 xq with (2f + 1) amax, both exact */
+    const double lhs = 2.0 * xq, mid = (2.0 * f + 1.0) * amax;
+    double c;
+    if (lhs < mid)
+        c = f;
+    else if (lhs > mid)
+        c = f + 1.0;
+    else
+        c = fmod(f, 2.0) == 0.0 ? f : f + 1.0;   /* tie: the even integer */
+    if (c > 127.0) c = 127.0;
+    if (c < -127.0) c = -127.0;
+    return (int8_t)c;
+}
+
+/* e4m3 code of x * Q / amax (amax > 0). */
+static uint8_t e4m3_code_exact(double x, double Q, double amax)
+{
+    const uint8_t sign = signbit(x) ? 0x80 : 0;
+    const double aq = fabs(x) * Q;          /* exact */
+    /* largest grid magnitude g[lo] with g[lo] * amax <= aq (binary search) */
+    int lo = 0, hi = 126;
+    while (lo < hi) {
+        const int m = (lo + hi + 1) / 2;
+        if (e4m3_mag[m] * amax <= aq) lo = m; else hi = m - 1;
+    }
+    int c = lo;
+    if (lo < 126) {
+        /* nearest of g[lo], g[lo + 1]: compare 2 aq with (g[lo] + g[lo + 1]) amax */
+        const double lhs = 2.0 * aq, mid = (e4m3_mag[lo] + e4m3_mag[lo + 1]) * amax;
+        if (lhs > mid || (lhs == mid && (lo & 1))) c = lo + 1;   /* tie: even code */
+    }
+    return sign | (uint8_t)c;
+}
+
 void oracle_quantize_rows(int64_t M, int64_t N, const float *x, int fmt, uint8_t *codes, float *scale)
 {
-    const float Q = fmt == 0 ? 127.0f : 448.0f;
+    const float Qf = fmt == 0 ? 127.0f : 448.0f;
+    e4m3_mag_init();
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t m = 0; m < M; ++m) {
         const float *xr = x + m * N;
@@ -366,18 +424,40 @@ void oracle_quantize_rows(int64_t M, int64_t N, const float *x, int fmt, uint8_t
             float a = fabsf(xr[i]);
             if (a > amax) amax = a;
         }
-        volatile float inv = amax > 0.0f ? Q / amax : 1.0f;
-        volatile float sc = amax > 0.0f ? amax / Q : 1.0f;
+        volatile float sc = amax > 0.0f ? amax / Qf : 1.0f;   /* one correctly rounded FP32 division */
         scale[m] = sc;
+        for (int64_t i = 0; i < N; ++i) {
+            if (amax == 0.0f)
+                cr[i] = fmt == 0 ? 0 : (signbit(xr[i]) ? 0x80 : 0);
+            else if (fmt == 0)
+                cr[i] = (uint8_t)int8_code_exact((double)xr[i], (double)Qf, (double)amax);
+            else
+                cr[i] = e4m3_code_exact((double)xr[i], (double)Qf, (double)amax);
+        }
+    }
+}
+
+/* The same codes taken with FP32 arithmetic instead: inv = Q / amax and
+ * v = x * inv, each rounded to FP32, then v rounded to the grid.  This is not
+ * the definition; the tests use it only to count where the two disagree. */
+void oracle_quantize_rows_fp32_product(int64_t M, int64_t N, const float *x, int fmt, uint8_t *codes)
+{
+    const float Q = fmt == 0 ? 127.0f : 448.0f;
+    for (int64_t m = 0; m < M; ++m) {
+        const float *xr = x + m * N;
+        float amax = 0.0f;
+        for (int64_t i = 0; i < N; ++i)
+            if (fabsf(xr[i]) > amax) amax = fabsf(xr[i]);
+        volatile float inv = amax > 0.0f ? Q / amax : 1.0f;
         for (int64_t i = 0; i < N; ++i) {
             volatile float v = xr[i] * inv;
             if (fmt == 0) {
-                float r = rintf(v);  /* round half to even in the default mode */
+                float r = rintf(v);
                 if (r > 127.0f) r = 127.0f;
                 if (r < -127.0f) r = -127.0f;
-                cr[i] = (uint8_t)(int8_t)r;
+                codes[m * N + i] = (uint8_t)(int8_t)r;
             } else {
-                cr[i] = e4m3_from_double((double)v);
+                codes[m * N + i] = e4m3_from_double((double)v);
             }
         }
     }

@@ -65,15 +65,12 @@ def test_softmax_logits_bwd_two_elements_closed_form():
 
 
 # ---------------------------------------------------------- quantisation
-def _brute_int8(v32: np.ndarray) -> np.ndarray:
-    # nearest integer code in [-127, 127] to each FP32 value; ties to the even code
-    codes = np.arange(-127, 128, dtype=np.float64)
-    out = np.empty(v32.shape, dtype=np.int64)
-    for idx, v in np.ndenumerate(v32.astype(np.float64)):
-        d = np.abs(codes - v)
-        best = np.flatnonzero(d == d.min())
-        out[idx] = int(codes[best[0]] if len(best) == 1 else [c for c in codes[best] if int(c) % 2 == 0][0])
-    return out
+# The code is the grid point nearest to x * Q / amax, ties to even; the pins
+# compare the oracle with brute force over the whole grid in rational
+# arithmetic (tests/_quant_rows.py), on random rows, on exact ties whose
+# reciprocal Q / amax is inexact in FP32, and on values where an FP32
+# evaluation of the same formula departs from the definition.
+from _quant_rows import exact_codes, fp32_departure_rows, fp32_product_codes, tie_rows  # noqa: E402
 
 
 def _quant_inputs():
@@ -81,80 +78,71 @@ def _quant_inputs():
     x[1, 3] = 40.0
     x[2, :] = 0.0  # all-zero row
     x[3, 5] = -7.5
+    x[4, 7] = -0.0
     return x
 
 
-def _tie_rows(q: float):
-    # exact ties of the decision variable: amax = 127 (int8) or 448 (e4m3)
-    # makes the reciprocal scale exactly 1, so v = x
-    row = np.zeros(37, dtype=np.float32)
-    if q == 127.0:
-        row[:9] = [127.0, 0.5, 1.5, 2.5, -0.5, -2.5, 3.5, -126.5, 100.5]
-        # a row with amax = 3 and two values where x * fl(127 / amax) and
-        # x / fl(amax / 127) round to different integers (the decision is the
-        # product with the FP32 reciprocal scale)
-        row2 = np.zeros(37, dtype=np.float32)
-        row2[:3] = [3.0] + np.array([1074418857, 1074220701], dtype=np.uint32).view(np.float32).tolist()
-        return np.stack([row, row2])
-    else:  # e4m3 steps are 1/8 in [1, 2) and 16 in [256, 448]
-        row[:9] = [448.0, 1.0625, 1.1875, -1.0625, -1.1875, 264.0, 280.0, -296.0, 0.5 + 1.0 / 32]
-    return row[None, :]
+def _scale_is_nearest_fp32(scale: np.float32, amax: np.float32, q: int) -> bool:
+    from fractions import Fraction
+    exact = Fraction(float(amax)) / q
+    s = np.float32(scale)
+    lo, hi = np.nextafter(s, np.float32(-np.inf)), np.nextafter(s, np.float32(np.inf))
+    ds = abs(Fraction(float(s)) - exact)
+    return ds <= abs(Fraction(float(lo)) - exact) and ds <= abs(Fraction(float(hi)) - exact)
 
 
-def test_quantize_int8_brute_force_nearest_code():
-    x = np.concatenate([_quant_inputs(), _tie_rows(127.0)])
-    codes, scale = oracle.quantize_rows(x, "int8")
+@pytest.mark.parametrize("fmt", ["int8", "fp8"])
+def test_quantize_codes_brute_force_exact_definition(fmt):
+    x = np.concatenate([_quant_inputs(), tie_rows(37, fmt).astype(np.float32),
+                        fp32_departure_rows(37, fmt, per_row=6).astype(np.float32)])
+    codes, scale = oracle.quantize_rows(x, fmt)
+    q = 127 if fmt == "int8" else 448
     for m in range(x.shape[0]):
+        assert np.array_equal(codes[m].view(np.uint8), exact_codes(x[m], fmt)), m
         amax = np.float32(np.max(np.abs(x[m])))
         if amax == 0:
-            assert scale[m] == np.float32(1.0) and np.all(codes[m] == 0)
+            assert scale[m] == np.float32(1.0)
             continue
-        # the decision variable: FP32 product of x with the FP32 reciprocal scale
-        inv = np.float32(np.float32(127.0) / amax)
-        v = (x[m] * inv).astype(np.float32)
-        assert np.array_equal(codes[m].astype(np.int64), _brute_int8(v))
-        assert scale[m] == np.float32(amax / np.float32(127.0))
-        # the largest magnitude lands on +-127
-        assert np.max(np.abs(codes[m].astype(np.int64))) == 127
+        assert _scale_is_nearest_fp32(scale[m], amax, q), m
+        # the largest magnitude lands on the end of the grid
+        got = codes[m].view(np.int8).astype(np.int64) if fmt == "int8" else oracle.decode_e4m3(codes[m])
+        assert np.max(np.abs(got)) == q
+
+
+@pytest.mark.parametrize("fmt", ["int8", "fp8"])
+def test_quantize_is_not_the_fp32_product(fmt):
+    # values next to decision boundaries where x * fl32(Q / amax) rounds to
+    # another code: the oracle takes the definition's code at every one of them
+    x = fp32_departure_rows(101, fmt, per_row=12).astype(np.float32)
+    codes, _ = oracle.quantize_rows(x, fmt)
+    fp32 = oracle.quantize_rows_fp32_product(x, fmt)
+    departs = np.stack([fp32_product_codes(r, fmt) for r in x]) != np.stack([exact_codes(r, fmt) for r in x])
+    assert departs.sum() >= 4 * 12
+    assert np.array_equal(fp32.view(np.uint8) != codes.view(np.uint8), departs)
 
 
 def test_quantize_int8_error_bound_and_symmetry():
     x = (RNG.standard_normal((8, 300)) * 2).astype(np.float32)
     codes, scale = oracle.quantize_rows(x, "int8")
-    deq = codes.astype(np.float64) * scale[:, None].astype(np.float64)
-    # half a quantisation step, plus the FP32 rounding of scale and product
-    assert np.all(np.abs(deq - x) <= 0.5 * scale[:, None] * (1 + 1e-5))
+    amax = np.max(np.abs(x), axis=1).astype(np.float64)
+    step = amax / 127.0
+    # the code is the nearest integer to x * 127 / amax: within half a step
+    assert np.all(np.abs(codes.astype(np.float64) * step[:, None] - x) <= 0.5 * step[:, None] * (1 + 1e-12))
     ncodes, nscale = oracle.quantize_rows(-x, "int8")
     assert np.array_equal(ncodes.astype(np.int64), -codes.astype(np.int64))
     assert np.array_equal(nscale, scale)
 
 
-def test_quantize_fp8_brute_force_nearest_e4m3():
-    x = np.concatenate([_quant_inputs(), _tie_rows(448.0)])
+def test_quantize_fp8_error_bound_and_symmetry():
+    x = (RNG.standard_normal((8, 300)) * 3).astype(np.float32)
     codes, scale = oracle.quantize_rows(x, "fp8")
-    allc = np.arange(256, dtype=np.uint8)
-    vals = torch.from_numpy(allc).view(torch.float8_e4m3fn).double().numpy()
-    finite = np.isfinite(vals)
-    fc, fv = allc[finite], vals[finite]
-    for m in range(x.shape[0]):
-        amax = np.float32(np.max(np.abs(x[m])))
-        if amax == 0:
-            assert scale[m] == np.float32(1.0) and np.all(oracle.decode_e4m3(codes[m]) == 0)
-            continue
-        inv = np.float32(np.float32(448.0) / amax)
-        v = (x[m] * inv).astype(np.float32).astype(np.float64)
-        got = oracle.decode_e4m3(codes[m])
-        for i, vi in enumerate(v):
-            vi = min(448.0, max(-448.0, vi))
-            d = np.abs(fv - vi)
-            cand = fv[d == d.min()]
-            if len(set(cand.tolist())) == 1:
-                assert got[i] == cand[0]
-            else:  # tie: the even mantissa (lowest code bit 0)
-                even = [fv[j] for j in np.flatnonzero(d == d.min()) if fc[j] % 2 == 0]
-                assert got[i] == even[0]
-        assert np.max(np.abs(got)) == 448.0
-        assert scale[m] == np.float32(amax / np.float32(448.0))
+    amax = np.max(np.abs(x), axis=1).astype(np.float64)
+    v = x * 448.0 / amax[:, None]
+    got = oracle.decode_e4m3(codes)
+    steps = np.vectorize(oracle.e4m3_step)(np.abs(v))
+    assert np.all(np.abs(got - v) <= 0.5 * steps * (1 + 1e-12))
+    ncodes, nscale = oracle.quantize_rows(-x, "fp8")
+    assert np.array_equal(ncodes ^ 0x80, codes) and np.array_equal(nscale, scale)
 
 
 # ------------------------------------------------------------ Pearson
