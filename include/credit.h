@@ -44,12 +44,18 @@
  *   - The workspace must be zero-filled before its first use; the library
  *     keeps it valid across calls.  Two calls that may run concurrently must
  *     not share a workspace.
+ *   - Operator calls never allocate device memory and never time kernels.
+ *     With plan == NULL they run the plan cached for the shape (credit_select
+ *     fills the cache with the configured selector's choice, timing kernels
+ *     where that selector times), else the learned network's first legal
+ *     choice, computed on the handle's stream in buffers allocated when the
+ *     model was set (the fixed rule without a model).
  *   - Operator calls may be recorded into a HIP graph (stream capture) and
  *     replayed: a recorded split-row launch is preceded by a one-thread kernel
  *     that advances a device-side exchange epoch, so every replay is a new
- *     epoch.  Make one eager call per shape first when the selector would
- *     time kernels or run its network (plan == NULL), so that capture finds
- *     the plan cached; operator calls record no memset nodes.
+ *     epoch.  A plan == NULL call on a shape with no cached plan, made while
+ *     its stream is capturing, takes the fixed rule (host arithmetic only) and
+ *     caches nothing; operator calls record no memset nodes.
  *   - A split-row launch assumes its workgroups can all be resident at once:
  *     its grid is the occupancy bound times the CU count.  The library orders
  *     its own such launches on a device one after another, whatever their
@@ -138,14 +144,15 @@ const char *credit_version(void);
 credit_status_t credit_create(int device, credit_handle_t *h);
 credit_status_t credit_destroy(credit_handle_t h);
 
-/* Selector used when an operator is called with plan == NULL. */
+/* Selector of credit_select (and so of the plans cached for operator calls
+ * with plan == NULL). */
 credit_status_t credit_set_selector(credit_handle_t h, credit_selector_t s);
 
 /* Bytes of workspace an operator call needs for (op, dir, dtype, M, N) under
- * `plan` (NULL: the plan the current selector picks; this may time kernels on
- * first use of a shape, Sec. III-D).  The size covers split-row exchange slots
- * (M * stages * k * q * 8 bytes) and, for normalisation backward, per-row-group
- * dgamma/dbeta column partials. */
+ * `plan` (NULL: the largest over the plans legal for the shape, enough for
+ * whatever plan a call with plan == NULL runs; nothing is selected or timed).
+ * The size covers split-row exchange slots (M * stages * k * q * 8 bytes) and,
+ * for normalisation backward, per-row-group dgamma/dbeta column partials. */
 credit_status_t credit_workspace_size(credit_handle_t h, credit_op_t op, credit_dir_t dir,
                                       credit_dtype_t dt, int64_t M, int64_t N,
                                       const credit_plan_t *plan, size_t *bytes);
@@ -158,9 +165,11 @@ credit_status_t credit_plan_legal(credit_handle_t h, credit_op_t op, credit_dir_
                                   credit_dtype_t dt, int64_t M, int64_t N,
                                   const credit_plan_t *plan);
 
-/* Picks a plan for the shape with the handle's selector (Sec. III-D).
- * predicted_us (nullable) receives the model's predicted time where the
- * selector has one, else -1. */
+/* Picks a plan for the shape with the handle's selector (Sec. III-D) and
+ * caches it for operator calls with plan == NULL.  Selectors that time kernels
+ * allocate the handle's timing buffers here (inputs of the shape and a
+ * 512 MiB cache-flush buffer).  predicted_us (nullable) receives the model's
+ * predicted time where the selector has one, else -1. */
 credit_status_t credit_select(credit_handle_t h, credit_op_t op, credit_dir_t dir,
                               credit_dtype_t dt, int64_t M, int64_t N, credit_plan_t *out,
                               float *predicted_us);
@@ -432,7 +441,10 @@ typedef enum {
     CREDIT_OPT_TEST_DROP_PUBLISH = 1, /* test only: member 1 of each row group skips
                                          publishing its partials (forces the timeout
                                          path of CREDIT_ERR_TIMEOUT) */
-    CREDIT_OPT_MAX_GROUPS = 2   /* cap on concurrent row groups (0: occupancy bound) */
+    CREDIT_OPT_MAX_GROUPS = 2,  /* cap on concurrent row groups (0: occupancy bound) */
+    CREDIT_OPT_TEST_SKEW = 3    /* test only: before each exchange, member c of a row
+                                   group waits (c * 7 + row) % 13 microseconds, so the
+                                   members publish out of step (Sec. III-C) */
 } credit_option_t;
 credit_status_t credit_set_option(credit_handle_t h, credit_option_t opt, int64_t value);
 
@@ -447,6 +459,28 @@ credit_status_t credit_plan_geometry(credit_handle_t h, credit_op_t op, credit_d
                                      credit_dtype_t dt, int64_t M, int64_t N,
                                      const credit_plan_t *plan, int32_t *grid, int32_t *block,
                                      int32_t *vpt, int32_t *per_cu);
+
+/* Resources of the row-resident / split-row kernel instance of (op, dir, dt)
+ * that holds `vpt` 16-byte vectors per thread per tensor (vpt in
+ * {1, 2, 4, 8, 12, 16, 24, 32}, up to the operator's register capacity):
+ * registers per lane, private (scratch) bytes per lane, workgroups per CU by
+ * the occupancy query and by the library's register model, and, for an
+ * instance that uses private memory, the workgroups per CU its co-residency
+ * probe verified when the handle was created (-1: no private memory, not
+ * probed; 0: no split plan of it is run).  Split plans of a probed instance
+ * never exceed the verified count (Sec. III-C: every member must be live for
+ * the exchange to complete).  Returns CREDIT_ERR_UNSUPPORTED for a vpt the
+ * operator does not instantiate.  With h == NULL only model_per_cu is filled
+ * (the others are -1) and no device is touched.  Host-only. */
+typedef struct {
+    int32_t registers;
+    int32_t private_bytes;
+    int32_t per_cu;
+    int32_t model_per_cu;
+    int32_t coresident_per_cu;
+} credit_instance_t;
+credit_status_t credit_instance_info(credit_handle_t h, credit_op_t op, credit_dir_t dir,
+                                     credit_dtype_t dt, int32_t vpt, credit_instance_t *out);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,7 @@ SOFTMAX_LOGITS, QUANT_INT8, QUANT_FP8, PEARSON, WVAR, LAYERNORM_FP8_OUT = 3, 4, 
 FWD, BWD = 0, 1
 TWO_PASS, ROW_RESIDENT, SPLIT_ROW = 0, 1, 2
 SEL_LEARNED, SEL_ANALYTIC, SEL_EXHAUSTIVE, SEL_FIXED, SEL_PEAK, SEL_LEARNED_TIMED = range(6)
-OPT_SPIN_LIMIT, OPT_TEST_DROP_PUBLISH, OPT_MAX_GROUPS = range(3)
+OPT_SPIN_LIMIT, OPT_TEST_DROP_PUBLISH, OPT_MAX_GROUPS, OPT_TEST_SKEW = range(4)
 NUM_FEATURES, NUM_PLANS, MLP_HIDDEN = 12, 7, 64
 DTYPE_NAMES = {"f32": F32, "bf16": BF16, "fp8": FP8}
 
@@ -53,6 +53,11 @@ class Plan(ctypes.Structure):
 class Workload(ctypes.Structure):
     _fields_ = [("b_base", ctypes.c_float), ("b_staged", ctypes.c_float), ("b_reread", ctypes.c_float),
                 ("b_keep", ctypes.c_float), ("stages", ctypes.c_int32), ("q", ctypes.c_int32 * 4)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("registers", ctypes.c_int32), ("private_bytes", ctypes.c_int32), ("per_cu", ctypes.c_int32),
+                ("model_per_cu", ctypes.c_int32), ("coresident_per_cu", ctypes.c_int32)]
 
 
 class Primitives(ctypes.Structure):
@@ -137,6 +142,7 @@ _SIGS = {
     "credit_probe_primitives": ([_P, _S, ctypes.POINTER(Primitives)], _S),
     "credit_plan_geometry": ([_P, _S, _S, _S, _I64, _I64, _PP, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                               ctypes.POINTER(_I32), ctypes.POINTER(_I32)], _S),
+    "credit_instance_info": ([_P, _S, _S, _S, _I32, ctypes.POINTER(Instance)], _S),
 }
 
 
@@ -219,6 +225,19 @@ def plan_geometry(handle, op, direction, dtype, M, N, p: Plan):
         return None
     check(s, "credit_plan_geometry")
     return {"grid": g.value, "block": b.value, "vpt": v.value, "per_cu": o.value}
+
+
+def instance_info(handle, op, direction, dtype, vpt: int):
+    """Registers, private bytes per lane, workgroups per CU (occupancy query,
+    register model, verified co-residency; -1 when not probed) of one
+    row-resident / split-row instance, or None if it does not exist."""
+    out = Instance()
+    h = handle.ptr if handle is not None else None
+    s = lib().credit_instance_info(h, op, direction, dtype, int(vpt), ctypes.byref(out))
+    if s == ERR_UNSUPPORTED:
+        return None
+    check(s, "credit_instance_info")
+    return {f: getattr(out, f) for f, _ in Instance._fields_}
 
 
 def set_epoch(e: int) -> None:
@@ -308,6 +327,11 @@ class Handle:
             check(lib().credit_create(self.device, ctypes.byref(p)), "credit_create")
         self.ptr = p
         self._ws = {}
+        # workspaces replaced by a larger one stay allocated until the handle
+        # goes away: a launch recorded into a HIP graph keeps the raw address of
+        # the workspace it was captured with, and replaying it must not write
+        # into memory the caching allocator has handed to someone else
+        self._retired = []
         self.model_loaded = False
         if load_default_model and os.path.exists(MODEL_PATH):
             self.model_loaded = lib().credit_load_model(self.ptr, MODEL_PATH.encode()) == OK
@@ -449,7 +473,12 @@ class Handle:
         key = int(stream)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < nbytes:
-            ws = torch.zeros(max(nbytes, 1 << 16), dtype=torch.uint8, device=f"cuda:{self.device}")
+            # grow at least twofold, so the retired ones add up to less than
+            # the live one
+            n = max(nbytes, 1 << 16, 2 * ws.numel() if ws is not None else 0)
+            if ws is not None:
+                self._retired.append(ws)
+            ws = torch.zeros(n, dtype=torch.uint8, device=f"cuda:{self.device}")
             self._ws[key] = ws
         return ws
 
@@ -617,6 +646,19 @@ def softmax_logits_bwd(x, dy, x_scale=None, dy_scale=None, p: Optional[Plan] = N
     return dx, dxs
 
 
+def _check_codes_out(out, M: int, N: int, fmt: str, device):
+    """The code dtype of fmt; a caller-supplied codes tensor must be [M, N] of
+    that dtype with unit inner stride on the input's device (its row stride is
+    passed to the library in elements of one byte)."""
+    torch = _torch()
+    code_dt = torch.int8 if fmt == "int8" else torch.uint8
+    if out is not None and (out.dim() != 2 or tuple(out.shape) != (M, N) or out.device != device
+                            or out.dtype != code_dt or out.stride(1) != 1):
+        raise ValueError(f"out: expected [{M}, {N}] {code_dt} codes with unit inner stride on {device}, "
+                         f"got {tuple(out.shape)} {out.dtype} on {out.device}")
+    return code_dt
+
+
 def quantize_rows(x, fmt: str = "int8", p: Optional[Plan] = None, out=None, out_scale=None,
                   h: Optional[Handle] = None):
     """Row-wise quantisation of an FP32 / BF16 matrix.  fmt 'int8': codes
@@ -628,10 +670,8 @@ def quantize_rows(x, fmt: str = "int8", p: Optional[Plan] = None, out=None, out_
     op = {"int8": QUANT_INT8, "fp8": QUANT_FP8}[fmt]
     M, N = x.shape
     _validate(M, N, x, [], [(out_scale, M, "out_scale")])
-    if out is not None and (tuple(out.shape) != (M, N) or out.device != x.device):
-        raise ValueError(f"out: expected [{M}, {N}] codes on {x.device}, got {tuple(out.shape)} on {out.device}")
-    q = out if out is not None else torch.empty((M, N), dtype=torch.int8 if fmt == "int8" else torch.uint8,
-                                                device=x.device)
+    code_dt = _check_codes_out(out, M, N, fmt, x.device)
+    q = out if out is not None else torch.empty((M, N), dtype=code_dt, device=x.device)
     qs = out_scale if out_scale is not None else _scale_out(x, M)
     s = h._stream()
     pp = None if p is None else ctypes.byref(p)

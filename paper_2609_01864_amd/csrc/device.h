@@ -92,10 +92,12 @@ template <> __device__ __forceinline__ u32x4 encode<DT_FP8>(const float *f, floa
     return v;
 }
 
-// Row-quantisation codes of EPV values (one byte each, packed little-endian
-// into EPV / 4 words).  The code decision is taken in FP32 on v = f * inv:
-// int8 rounds half to even and clamps to [-127, 127]; e4m3 rounds to nearest
-// even with saturation to +-448.
+// One-byte codes of EPV FP32 values scaled by inv (packed little-endian into
+// EPV / 4 words): int8 rounds f * inv half to even and clamps to [-127, 127];
+// e4m3 rounds to nearest even with saturation to +-448.  Used for outputs
+// computed in FP32 (the LayerNorm -> e4m3 forward), whose accuracy is judged
+// against the FP64 result; the row-quantisation operator takes its codes
+// from quant_codes_exact below.
 template <bool I8, int EPV> __device__ __forceinline__ void quant_codes(const float *f, float inv, unsigned *w) {
 #pragma unroll
     for (int i = 0; i < EPV / 4; ++i) {
@@ -113,6 +115,118 @@ template <bool I8, int EPV> __device__ __forceinline__ void quant_codes(const fl
             w[i] = (unsigned)word;
         }
     }
+}
+
+// Row-quantisation codes by their definition: the grid point nearest to
+// x * Q / amax, ties to the even code (Q = 127: the integers -127..127; Q = 448:
+// the finite e4m3 values).  `inv` is Q / (amax * sc) rounded to FP32 and `sc`
+// a power of two that keeps that reciprocal finite (2^64 when amax < 2^-100,
+// else 1), so v = (x * sc) * inv is x * Q / amax within 2^-23 |v|.  Rounding v
+// therefore gives the exact code except where x * Q / amax lies within a few
+// FP32 units of a decision boundary (a half-integer, or the midpoint of two
+// adjacent e4m3 values).  Those elements are decided exactly: x * Q and
+// b * amax, for a boundary b with at most 9 significant bits, are exact FP64
+// products, and so is their comparison.  amax > 0.
+__device__ __forceinline__ float fp8_byte_value(unsigned code) {
+    return __builtin_amdgcn_cvt_f32_fp8((int)code, 0);
+}
+// The exact code of one element whose FP32 estimate lies near a boundary:
+// byte b (int8 two's complement or e4m3) is the rounding of the estimate,
+// at most one grid step from the exact code; aq = |x| Q (exact in FP64).
+__device__ __forceinline__ unsigned exact_code_fix(bool i8, float x, unsigned b, float amax) {
+    const double aq = (double)__builtin_fabsf(x) * (double)(i8 ? 127.f : kFp8Max);
+    if (i8) {
+        // magnitude m of the code, the grid points m - 1, m, m + 1 of |x| Q / amax
+        const int c = (int)(signed char)(unsigned char)b;
+        int m = c < 0 ? -c : c;
+        const double up = (double)(2 * m + 1) * (double)amax * 0.5;
+        const double dn = (double)(2 * m - 1) * (double)amax * 0.5;
+        if (aq > up || (aq == up && (m & 1))) ++m;
+        else if (m > 0 && (aq < dn || (aq == dn && (m & 1)))) --m;
+        m = m > 127 ? 127 : m;
+        const int code = x < 0.f ? -m : m;
+        return (unsigned)code & 0xffu;
+    }
+    unsigned mc = b & 0x7fu;
+    const float g = fp8_byte_value(mc);
+    if (mc < 0x7eu) {
+        const double up = (double)((g + fp8_byte_value(mc + 1u)) * 0.5f) * (double)amax;
+        if (aq > up || (aq == up && (mc & 1u))) return (b & 0x80u) | (mc + 1u);
+    }
+    if (mc > 0u) {
+        const double dn = (double)((g + fp8_byte_value(mc - 1u)) * 0.5f) * (double)amax;
+        if (aq < dn || (aq == dn && (mc & 1u))) return (b & 0x80u) | (mc - 1u);
+    }
+    return b;
+}
+template <bool I8, int EPV>
+__device__ __forceinline__ void quant_codes_exact(const float *f, float sc, float inv, float amax, unsigned *w) {
+    float v[EPV];
+#pragma unroll
+    for (int i = 0; i < EPV; ++i) v[i] = (f[i] * sc) * inv;
+    unsigned nm = 0;  // elements whose estimate lies near a decision boundary
+    if constexpr (I8) {
+#pragma unroll
+        for (int i = 0; i < EPV / 4; ++i) w[i] = 0u;
+#pragma unroll
+        for (int i = 0; i < EPV; ++i) {
+            const float c = __builtin_rintf(__builtin_amdgcn_fmed3f(v[i], -127.f, 127.f));
+            // |v - x Q / amax| <= 127 * 2^-23 < 2^-16
+            nm |= (__builtin_fabsf(v[i] - c) > 0.5f - 0x1p-14f ? 1u : 0u) << i;
+            w[i / 4] |= ((unsigned)(int)c & 0xffu) << (8 * (i % 4));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < EPV / 4; ++i) {
+            int word = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(v[4 * i]), sat448(v[4 * i + 1]), 0, false);
+            word = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(v[4 * i + 2]), sat448(v[4 * i + 3]), word, true);
+            w[i] = (unsigned)word;
+        }
+#pragma unroll
+        for (int i = 0; i < EPV; ++i) {
+            const float a = __builtin_fabsf(v[i]);
+            // normal e4m3 range: a midpoint has FP32 fraction bits 19..0 equal
+            // to 0x80000 and v is within 2 FP32 units of x Q / amax; subnormal
+            // range: midpoints at (j + 1/2) 2^-9
+            const unsigned low = __float_as_uint(a) & 0xfffffu;
+            const float t = a * 512.f;
+            const bool near = a >= 0x1p-6f ? low - 0x7fffcu <= 8u
+                                           : __builtin_fabsf(t - __builtin_floorf(t) - 0.5f) < 0x1p-12f;
+            nm |= (near ? 1u : 0u) << i;
+        }
+    }
+    while (nm) {  // rare: one element at a time
+        const int i = __builtin_ctz(nm);
+        nm &= nm - 1u;
+        // element i and its code word by selects over values the compiler
+        // cannot regroup into an array (a lane-varying index into a register
+        // array would place the array in private memory)
+        float x = 0.f;
+        unsigned word = 0u;
+#pragma unroll
+        for (int k = 0; k < EPV; ++k) {
+            float fk = f[k];
+            asm volatile("" : "+v"(fk));
+            x = i == k ? fk : x;
+        }
+#pragma unroll
+        for (int k = 0; k < EPV / 4; ++k) {
+            unsigned wk = w[k];
+            asm volatile("" : "+v"(wk));
+            word = (i >> 2) == k ? wk : word;
+        }
+        const int sh = 8 * (i & 3);
+        const unsigned nb = exact_code_fix(I8, x, (word >> sh) & 0xffu, amax);
+        const unsigned nw = (word & ~(0xffu << sh)) | (nb << sh);
+#pragma unroll
+        for (int k = 0; k < EPV / 4; ++k) w[k] = (i >> 2) == k ? nw : w[k];
+    }
+}
+// Per-row factors of quant_codes_exact: the power-of-two pre-scale and the
+// FP32 reciprocal Q / (amax * sc).  amax > 0.
+__device__ __forceinline__ void quant_row_factors(float amax, float Q, float &sc, float &inv) {
+    sc = amax < 0x1p-100f ? 0x1p64f : 1.f;
+    inv = Q / (amax * sc);
 }
 
 // ------------------------------------------------------------ loads/stores
@@ -350,6 +464,28 @@ __device__ __forceinline__ void member_of(const RowArgs &a, int bid, int &c, int
     }
 }
 
+// ---------------------------------------------------- co-residency probe
+// Launched in place of the row work (F_PROBE) at a split-row grid: every
+// workgroup announces itself on a counter, then waits (bounded) until the
+// counter holds the whole grid; a workgroup that gives up counts a miss.  No
+// miss means every workgroup of the grid was resident at the same time, with
+// the kernel's own register, LDS and private-memory demand.  Counter words:
+// errflag[96] (arrivals) and errflag[97] (misses), zeroed by the host.
+__device__ __forceinline__ void coresidency_probe(const RowArgs &a) {
+    if (threadIdx.x == 0) {
+        unsigned *arrived = a.errflag + 96, *missed = a.errflag + 97;
+        __hip_atomic_fetch_add(arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned spins = 0;
+        while (__hip_atomic_load(arrived, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
+            if (++spins > a.spin_limit) {
+                __hip_atomic_fetch_add(missed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+}
+
 // --------------------------------------------------- split-row exchange
 // Slot word: high 32 bits = launch epoch, low 32 bits = FP32 partial.  Each
 // word is written with one agent-scope atomic store and polled with
@@ -369,6 +505,15 @@ __device__ __forceinline__ void exchange(const RowArgs &a, int64_t row, int stag
                                          const float (&mine)[Q], float *xb) {
     const int tid = threadIdx.x;
     const int kq = a.k * Q;
+    if (a.flags & F_TEST_SKEW) {
+        // test only: member c of row `row` publishes about (c * 7 + row) % 13
+        // microseconds late, so members reach the exchange out of step
+        // (the real-time counter runs at 100 MHz)
+        const uint64_t ticks = (uint64_t)((c * 7 + row) % 13) * 100u;
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while (__builtin_amdgcn_s_memrealtime() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
+        __syncthreads();
+    }
     if (tid < Q) {
         bool drop = (a.flags & F_TEST_DROP_PUBLISH) && c == 1;
         if (!drop) {

@@ -197,7 +197,13 @@ struct credit_handle_s {
     credit_plan_t force_plan{CREDIT_TWO_PASS, 1};
     int64_t spin_limit = 1 << 22;
     bool drop_publish = false;
+    bool skew = false;  // test only: members publish out of step
     int64_t max_groups = 0;
+    // private memory (bytes per lane) of the row-resident / split-row
+    // instances, and for those that use it the workgroups per CU verified
+    // co-resident at handle creation (0: none)
+    std::map<const void *, size_t> scratch;
+    std::map<const void *, int> coresident;
     std::recursive_mutex lock;
     std::map<const void *, int> occ_cache;
     std::map<std::tuple<int, int, int, int64_t, int64_t, int>, credit_plan_t> plan_cache;
@@ -208,8 +214,11 @@ struct credit_handle_s {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float copy_gbps = 0.f;
     std::tuple<int, int, int64_t, int64_t> prepared{-1, -1, -1, -1};  // inputs currently filled
-    // learned selector
+    // learned selector; `inf` holds the network and one row of activations on
+    // the device, allocated when a model is set, so that picking a plan in an
+    // operator call allocates nothing
     bool has_model = false;
+    float *inf = nullptr;
     std::vector<float> params = std::vector<float>(kMlpParams, 0.f);
     float mu[CREDIT_NUM_FEATURES] = {0};
     float sd[CREDIT_NUM_FEATURES] = {0};
@@ -297,6 +306,14 @@ credit_status_t resolve(credit_handle_t h, int k_op, int dt, int64_t M, int64_t 
     if (!L.fn) return CREDIT_ERR_UNSUPPORTED;
     int occ = h ? occupancy(h, L.fn, L.block, 0) : model_waves(k_op, dt, vpt);
     if (occ <= 0) return h ? CREDIT_ERR_HIP : CREDIT_ERR_UNSUPPORTED;
+    if (h && k > 1) {
+        // an instance that uses private memory runs split plans only at the
+        // per-CU count its co-residency probe verified (dispatch of waves that
+        // need private memory is also bounded by the runtime's allocation)
+        auto it = h->coresident.find(L.fn);
+        if (it != h->coresident.end()) occ = std::min(occ, it->second);
+        if (occ <= 0) return CREDIT_ERR_UNSUPPORTED;
+    }
     L.per_cu = occ;
     int64_t cap = (int64_t)occ * cus;
     int64_t gmax = cap / k;
@@ -394,7 +411,8 @@ struct OpCall {
     const float *rowg;  // per-row upstream gradient (Pearson dr, weighted-variance dv)
 };
 
-credit_status_t pick_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t *out, float *pred);
+credit_status_t pick_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t *out, float *pred,
+                          bool may_time, bool capturing);
 
 // Issues an operator with a resolved launch on `stream`.
 credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void *ws, hipStream_t stream,
@@ -422,6 +440,7 @@ credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void 
     if ((!c.gamma || al16(c.gamma)) && (!c.beta || al16(c.beta))) flags |= F_ALIGNP;
     if (recompute) flags |= F_RECOMPUTE;
     if (h->drop_publish) flags |= F_TEST_DROP_PUBLISH;
+    if (h->skew) flags |= F_TEST_SKEW;
     char *w = (char *)ws;
     const int ncp = ncp_of(c.k_op);
     hipError_t e = hipSuccess;
@@ -535,7 +554,10 @@ credit_status_t run_op(credit_handle_t h, const OpCall &c, const credit_plan_t *
     if (plan) {
         p = *plan;
     } else {
-        credit_status_t st = pick_plan(h, c.k_op, c.dt, c.M, c.N, &p, nullptr);
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess) return CREDIT_ERR_HIP;
+        credit_status_t st = pick_plan(h, c.k_op, c.dt, c.M, c.N, &p, nullptr, false,
+                                       cs == hipStreamCaptureStatusActive);
         if (st != CREDIT_OK) return st;
     }
     Launch L;
@@ -860,6 +882,7 @@ void features(int k_op, int dt, int64_t M, int64_t N, float *f) {
 }
 
 credit_status_t mlp_predict_dev(credit_handle_t h, const float *feats, int64_t n, float *logits);
+credit_status_t mlp_logits_one(credit_handle_t h, const float *feats, float *logits);
 
 credit_status_t analytic_pick(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, bool peak,
                               credit_plan_t *out, float *pred) {
@@ -937,7 +960,7 @@ credit_status_t learned_pick(credit_handle_t h, int k_op, int dt, int64_t M, int
                              credit_plan_t *out, float *pred) {
     float f[CREDIT_NUM_FEATURES], logits[CREDIT_NUM_PLANS];
     features(k_op, dt, M, N, f);
-    credit_status_t st = mlp_predict_dev(h, f, 1, logits);
+    credit_status_t st = mlp_logits_one(h, f, logits);
     if (st != CREDIT_OK) return st;
     int best = -1, second = -1;
     for (int c = 0; c < CREDIT_NUM_PLANS; ++c) {
@@ -962,8 +985,15 @@ credit_status_t learned_pick(credit_handle_t h, int k_op, int dt, int64_t M, int
     return CREDIT_OK;
 }
 
+// The plan of a shape.  Selectors that time kernels (exhaustive, analytic,
+// peak, learned with timing) run only when `may_time` (credit_select): an
+// operator call never times, allocates or synchronises beyond the network's
+// one-row forward pass.  It uses the plan cached for the shape, else the
+// network's first legal choice (the fixed rule without a model) -- and while
+// its stream is being captured into a graph, where no other device work may
+// run, the fixed rule, which is host arithmetic only and is not cached.
 credit_status_t pick_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t *out,
-                          float *pred) {
+                          float *pred, bool may_time, bool capturing) {
     std::lock_guard<std::recursive_mutex> g(h->lock);
     if (h->force_set && plan_ok(h, k_op, dt, M, N, h->force_plan)) {
         *out = h->force_plan;
@@ -982,6 +1012,18 @@ credit_status_t pick_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_
     }
     if (pred) *pred = -1.f;
     credit_status_t st = CREDIT_OK;
+    if (!may_time) {
+        if (capturing) {
+            *out = fixed_rule(h, k_op, dt, M, N);
+            return CREDIT_OK;
+        }
+        st = CREDIT_ERR_MODEL;
+        if (sel != CREDIT_SEL_FIXED && h->has_model && core_op(k_op))
+            st = learned_pick(h, k_op, dt, M, N, false, out, pred);
+        if (st != CREDIT_OK) *out = fixed_rule(h, k_op, dt, M, N);
+        h->plan_cache[key] = *out;
+        return CREDIT_OK;
+    }
     switch (sel) {
     case CREDIT_SEL_LEARNED:
         // the learned selector's features cover the softmax / LayerNorm /
@@ -1000,6 +1042,55 @@ credit_status_t pick_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_
     }
     if (st == CREDIT_OK) h->plan_cache[key] = *out;
     return st;
+}
+
+// ------------------------------------------------------ co-residency
+// Every row-resident / split-row instance whose compiled code uses private
+// memory (register spills, stack arrays) is launched once in probe mode at
+// its full persistent grid, occupancy x CUs: every workgroup announces itself
+// and waits for all the others (bounded).  Split plans of the instance then
+// use the largest per-CU count at which no workgroup gave up, so their grid
+// is one the device was seen to hold at once.  Instances without private
+// memory are bounded by registers, LDS and wave slots alone, which the
+// occupancy query reports.
+credit_status_t verify_coresidency(credit_handle_t h) {
+    constexpr unsigned kProbeSpins = 1u << 15;
+    for (int k_op = 0; k_op < OP_COUNT; ++k_op) {
+        for (int dt = CREDIT_F32; dt <= CREDIT_FP8_E4M3; ++dt) {
+            if (!dt_ok(k_op, dt)) continue;
+            for (int vpt : kVpts) {
+                if (vpt > max_vpt(k_op, dt)) continue;
+                const void *fn = resident_fn(k_op, dt, vpt);
+                if (!fn) continue;
+                hipFuncAttributes at;
+                if (hipFuncGetAttributes(&at, fn) != hipSuccess) return CREDIT_ERR_HIP;
+                h->scratch[fn] = at.localSizeBytes;
+                if (at.localSizeBytes == 0) continue;
+                const int occ = occupancy(h, fn, kBlockThreads, 0);
+                int ok = 0;
+                for (int per = occ; per >= 1 && !ok; --per) {
+                    RowArgs a;
+                    std::memset(&a, 0, sizeof(a));
+                    a.errflag = h->errflag;
+                    a.spin_limit = kProbeSpins;
+                    a.flags = F_PROBE;
+                    a.k = 1;
+                    void *args[] = {&a};
+                    unsigned missed = 1;
+                    if (hipMemsetAsync(h->errflag + 96, 0, 8, h->stream) != hipSuccess ||
+                        fenced_launch(h->device, false, fn, per * h->cus, kBlockThreads, 0, h->stream, args) !=
+                            hipSuccess ||
+                        hipMemcpyAsync(&missed, h->errflag + 97, 4, hipMemcpyDeviceToHost, h->stream) !=
+                            hipSuccess ||
+                        hipStreamSynchronize(h->stream) != hipSuccess)
+                        return CREDIT_ERR_HIP;
+                    if (missed == 0) ok = per;
+                }
+                h->coresident[fn] = ok;
+            }
+        }
+    }
+    return CREDIT_OK;
 }
 
 // ------------------------------------------------------------------- MLP
@@ -1090,6 +1181,47 @@ bool mlp_upload(credit_handle_t h, MlpDev &d, const float *feats, const float *t
     if (ok && targets) ok = hipMemcpy(d.tg, targets, n * kC * 4, hipMemcpyHostToDevice) == hipSuccess;
     if (ok && mask) ok = hipMemcpy(d.mask, mask, n * kC, hipMemcpyHostToDevice) == hipSuccess;
     return ok;
+}
+
+// Offsets (in floats) of the single-row inference block h->inf.
+constexpr size_t iP = 0, iMu = iP + kMlpParams, iSd = iMu + kF, iRaw = iSd + kF, iZ = iRaw + kF, iH1 = iZ + kF,
+                 iH2 = iH1 + kH, iLg = iH2 + kH, iEnd = iLg + kC;
+
+// Allocates the single-row inference block (once) and uploads the current
+// network into it.  Called whenever a model is set, never from an operator.
+credit_status_t upload_infer(credit_handle_t h) {
+    if (!h->inf && hipMalloc(&h->inf, iEnd * 4) != hipSuccess) {
+        h->inf = nullptr;
+        (void)hipGetLastError();
+        return CREDIT_ERR_HIP;
+    }
+    if (hipMemcpy(h->inf + iP, h->params.data(), kMlpParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->inf + iMu, h->mu, kF * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->inf + iSd, h->sd, kF * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return CREDIT_ERR_HIP;
+    return CREDIT_OK;
+}
+
+// The network's logits for one feature row, through the HIP kernels on the
+// handle's stream, in the preallocated block: no allocation.
+credit_status_t mlp_logits_one(credit_handle_t h, const float *feats, float *logits) {
+    if (!h->inf) return CREDIT_ERR_MODEL;
+    MlpDev d;  // a view of h->inf (owns nothing)
+    d.n = 1;
+    d.p = h->inf + iP;
+    d.mu = h->inf + iMu;
+    d.sd = h->inf + iSd;
+    d.raw = h->inf + iRaw;
+    d.z = h->inf + iZ;
+    d.h1 = h->inf + iH1;
+    d.h2 = h->inf + iH2;
+    d.lg = h->inf + iLg;
+    if (hipMemcpyAsync(d.raw, feats, kF * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        mlp_forward(d, h->stream) != hipSuccess ||
+        hipMemcpyAsync(logits, d.lg, kC * 4, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return CREDIT_ERR_HIP;
+    return CREDIT_OK;
 }
 
 credit_status_t mlp_predict_dev(credit_handle_t h, const float *feats, int64_t n, float *logits) {
@@ -1192,6 +1324,10 @@ credit_status_t credit_create(int device, credit_handle_t *out) {
             return CREDIT_ERR_HIP;
         }
         read_env(h);
+        if (verify_coresidency(h) != CREDIT_OK) {
+            credit_destroy(h);
+            return CREDIT_ERR_HIP;
+        }
         *out = h;
         return CREDIT_OK;
     } catch (...) {
@@ -1204,6 +1340,7 @@ credit_status_t credit_destroy(credit_handle_t h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->arena) (void)hipFree(h->arena);
     if (h->flushbuf) (void)hipFree(h->flushbuf);
+    if (h->inf) (void)hipFree(h->inf);
     if (h->errflag) (void)hipFree(h->errflag);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
@@ -1229,20 +1366,26 @@ credit_status_t credit_workspace_size(credit_handle_t h, credit_op_t op, credit_
                                       int64_t M, int64_t N, const credit_plan_t *plan, size_t *bytes) {
     if (!h || !bytes || !valid_enum(op, dir, dt) || M < 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
     try {
-        credit_plan_t p;
-        if (plan) {
-            p = *plan;
-        } else if (M == 0) {
-            p = {CREDIT_TWO_PASS, 1};
-        } else {
-            credit_status_t st = pick_plan(h, kop(op, dir), dt, M, N, &p, nullptr);
-            if (st != CREDIT_OK) return st;
-        }
         Launch L;
         std::lock_guard<std::recursive_mutex> g(h->lock);
-        credit_status_t st = resolve(h, kop(op, dir), dt, M, N, p, true, L);
-        if (st != CREDIT_OK) return st;
-        *bytes = L.ws_bytes;
+        if (plan) {
+            credit_status_t st = resolve(h, kop(op, dir), dt, M, N, *plan, true, L);
+            if (st != CREDIT_OK) return st;
+            *bytes = L.ws_bytes;
+            return CREDIT_OK;
+        }
+        // no plan: enough for any plan an automatic call may pick (the
+        // largest over the legal plans), so sizing selects nothing
+        size_t most = 0;
+        bool any = false;
+        for (int c = 0; c < CREDIT_NUM_PLANS; ++c) {
+            if (resolve(h, kop(op, dir), dt, std::max<int64_t>(M, 1), N, class_plan(c), true, L) != CREDIT_OK)
+                continue;
+            most = std::max(most, L.ws_bytes);
+            any = true;
+        }
+        if (!any) return CREDIT_ERR_UNSUPPORTED;
+        *bytes = most;
         return CREDIT_OK;
     } catch (...) {
         return CREDIT_ERR_HIP;
@@ -1285,7 +1428,7 @@ credit_status_t credit_select(credit_handle_t h, credit_op_t op, credit_dir_t di
     if (!h || !out || !valid_enum(op, dir, dt) || M <= 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
     try {
         float pred = -1.f;
-        credit_status_t st = pick_plan(h, kop(op, dir), dt, M, N, out, &pred);
+        credit_status_t st = pick_plan(h, kop(op, dir), dt, M, N, out, &pred, true, false);
         if (predicted_us) *predicted_us = pred;
         return st;
     } catch (...) {
@@ -1672,6 +1815,7 @@ credit_status_t credit_mlp_set(credit_handle_t h, const float *params, const flo
     std::memcpy(h->params.data(), params, kMlpParams * 4);
     std::memcpy(h->mu, mu, kF * 4);
     std::memcpy(h->sd, sd, kF * 4);
+    if (upload_infer(h) != CREDIT_OK) return CREDIT_ERR_HIP;
     h->has_model = true;
     h->plan_cache.clear();
     return CREDIT_OK;
@@ -1754,6 +1898,7 @@ credit_status_t credit_mlp_train(credit_handle_t h, const float *feats, const fl
             return CREDIT_ERR_HIP;
         if (final_loss && hipMemcpy(final_loss, d.lmean, 4, hipMemcpyDeviceToHost) != hipSuccess)
             return CREDIT_ERR_HIP;
+        if (upload_infer(h) != CREDIT_OK) return CREDIT_ERR_HIP;
         h->has_model = true;
         h->plan_cache.clear();
         return CREDIT_OK;
@@ -1816,7 +1961,34 @@ credit_status_t credit_load_model(credit_handle_t h, const char *path) {
     std::memcpy(h->params.data(), p.data(), kMlpParams * 4);
     std::memcpy(h->mu, mu, sizeof(mu));
     std::memcpy(h->sd, sd, sizeof(sd));
+    if (upload_infer(h) != CREDIT_OK) return CREDIT_ERR_HIP;
     h->has_model = true;
+    return CREDIT_OK;
+}
+
+credit_status_t credit_instance_info(credit_handle_t h, credit_op_t op, credit_dir_t dir, credit_dtype_t dt,
+                                     int32_t vpt, credit_instance_t *out) {
+    if (!out || !valid_enum(op, dir, dt)) return CREDIT_ERR_INVALID_ARG;
+    const int k_op = kop(op, dir);
+    bool known = false;
+    for (int v : kVpts) known |= v == vpt;
+    if (!known || vpt > max_vpt(k_op, dt)) return CREDIT_ERR_UNSUPPORTED;
+    const void *fn = resident_fn(k_op, dt, vpt);
+    if (!fn) return CREDIT_ERR_UNSUPPORTED;
+    if (!h) {  // the register model only
+        out->registers = out->private_bytes = out->per_cu = out->coresident_per_cu = -1;
+        out->model_per_cu = model_waves(k_op, dt, vpt);
+        return CREDIT_OK;
+    }
+    std::lock_guard<std::recursive_mutex> g(h->lock);
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, fn) != hipSuccess) return CREDIT_ERR_HIP;
+    out->registers = at.numRegs;
+    out->private_bytes = (int32_t)at.localSizeBytes;
+    out->per_cu = occupancy(h, fn, kBlockThreads, 0);
+    out->model_per_cu = model_waves(k_op, dt, vpt);
+    auto it = h->coresident.find(fn);
+    out->coresident_per_cu = it == h->coresident.end() ? -1 : it->second;
     return CREDIT_OK;
 }
 
@@ -1829,6 +2001,7 @@ credit_status_t credit_set_option(credit_handle_t h, credit_option_t opt, int64_
         h->spin_limit = value;
         return CREDIT_OK;
     case CREDIT_OPT_TEST_DROP_PUBLISH: h->drop_publish = value != 0; return CREDIT_OK;
+    case CREDIT_OPT_TEST_SKEW: h->skew = value != 0; return CREDIT_OK;
     case CREDIT_OPT_MAX_GROUPS:
         if (value < 0) return CREDIT_ERR_INVALID_ARG;
         h->max_groups = value;

@@ -34,6 +34,8 @@ enum KFlags {
     F_TEST_DROP_PUBLISH = 32,  // test only: member 1 never publishes
     F_ALIGNP = 64,             // gamma / beta 16-byte aligned
     F_ALIGNO1 = 128,           // rows of out1 start 16-byte aligned
+    F_PROBE = 256,             // co-residency probe: no row work (see coresidency_probe)
+    F_TEST_SKEW = 512,         // test only: members publish after a member- and row-dependent delay
 };
 
 // Statistics exchanged per stage (slot stride of the exchange workspace).

@@ -261,6 +261,17 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
         }
     }
 
+    // The resident slice of the row being processed.  With CREDIT_ROW_PREFETCH
+    // the next row's slot j is loaded into d0[j] / d1[j] as soon as the output
+    // of slot j has been stored, so the next row's loads overlap this row's
+    // stores instead of following all of them.
+#ifndef CREDIT_ROW_PREFETCH
+#define CREDIT_ROW_PREFETCH 0
+#endif
+    constexpr bool PF = CREDIT_ROW_PREFETCH != 0;
+    u32x4 d0[VPT];
+    u32x4 d1[T::TWO ? VPT : 1];
+    bool prefetched = false;  // uniform: d0 / d1 already hold this row's slice
     for (int64_t row = grp; row < a.M; row += a.groups) {
         const char *r0 = (const char *)a.in0 + row * a.ld0 * B;
         const char *r1 = T::TWO ? (const char *)a.in1 + row * a.ld1 * B : nullptr;
@@ -287,19 +298,33 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
         auto pofs = [&](int j) -> uint32_t {
             return (FULLS || ok_of(j)) ? poff + (uint32_t)sv(j) * (kBlock * EPV * 4u) : 0u;
         };
+        // next row of the row group: its slot j is loaded after slot j's last store
+        const int64_t nrow = row + a.groups;
+        const bool pf_next = PF && nrow < a.M && (FULLS || sl.nfv > 0);
+        const char *nb0 = (const char *)a.in0 + nrow * a.ld0 * B + sl.c0 * B;
+        const char *nb1 = T::TWO ? (const char *)a.in1 + nrow * a.ld1 * B + sl.c0 * B : nullptr;
+        auto NEXT = [&](int j) {
+            if (pf_next) {
+                d0[j] = vload_nt<AL>(nb0, doff(j));
+                if constexpr (T::TWO) d1[j] = vload_nt<AL>(nb1, doff(j));
+            }
+        };
         auto ST = [&](int j, u32x4 v) {
             if (FULLS || ok_of(j)) vstore_nt<AL>(bo, toff + (uint32_t)sv(j) * (kBlock * 16u), v);
+            if constexpr (!T::TWOO) NEXT(j);
         };
         auto ST1 = [&](int j, u32x4 v) {
             if (FULLS || ok_of(j)) vstore_nt<AL>(bo1, toff + (uint32_t)sv(j) * (kBlock * 16u), v);
+            NEXT(j);
         };
         auto QST = [&](int j, const unsigned *w) {
             if (FULLS || ok_of(j)) bstore_nt<EPV, AL>(bo, qoff + (uint32_t)sv(j) * (uint32_t)(kBlock * EPV), w);
+            NEXT(j);
         };
         auto PAR = [&](const float *p, int j, float *out) { load_params_v<DT, AL>(p + sl.c0, pofs(j), out); };
-        u32x4 d0[VPT];
-        u32x4 d1[T::TWO ? VPT : 1];
-        if (FULLS || sl.nfv > 0) {  // uniform: a slice without full vectors issues no vector load
+        if (prefetched) {
+            // loaded during the previous row's output pass
+        } else if (FULLS || sl.nfv > 0) {  // uniform: a slice without full vectors issues no vector load
 #pragma unroll
             for (int j = 0; j < VPT; ++j) d0[j] = vload_nt<AL>(b0, doff(j));
             if constexpr (T::TWO) {
@@ -1008,8 +1033,9 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 store_vec<DT>(orow, tcol, tn, false, encode<DT>(dx, oinv));
             }
         } else if constexpr (T::QUANT) {
-            // Row-wise quantisation: amax stage, then codes RNE(x * qmax / amax)
-            // with the row scale amax / qmax (1 for an all-zero row).
+            // Row-wise quantisation: amax stage, then the code nearest to
+            // x * qmax / amax (decided exactly, ties to even) with the row scale
+            // amax / qmax (1 for an all-zero row).
             constexpr bool I8 = OP == OP_QUANT_I8;
             float am[1] = {0.f};
             fresh();
@@ -1028,22 +1054,24 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             }
             row_reduce<1>(am, MergeMax(), a, row, 0, c, red, xb, parity);
             const float qm = I8 ? 127.f : kFp8Max;
-            const float inv = am[0] > 0.f ? qm / am[0] : 1.f;
-            if (writer) a.so[row] = am[0] > 0.f ? am[0] / qm : 1.f;
+            const float amx = am[0];
+            float qsc = 1.f, inv = 1.f;  // an all-zero row: every code is 0
+            if (amx > 0.f) quant_row_factors(amx, qm, qsc, inv);
+            if (writer) a.so[row] = amx > 0.f ? amx / qm : 1.f;
             fresh();
 #pragma unroll
             for (int j = 0; j < VPT; ++j) {
                 float q[EPV];
                 decode<DT>(d0[j], q, 1.f);
                 unsigned w[EPV / 4];
-                quant_codes<I8, EPV>(q, inv, w);
+                quant_codes_exact<I8, EPV>(q, qsc, inv, amx > 0.f ? amx : 1.f, w);
                 QST(j, w);
             }
             if (tail) {
                 float q[EPV];
                 decode<DT>(t0, q, 1.f);
                 unsigned w[EPV / 4];
-                quant_codes<I8, EPV>(q, inv, w);
+                quant_codes_exact<I8, EPV>(q, qsc, inv, amx > 0.f ? amx : 1.f, w);
                 for (int i = 0; i < tn; ++i) orow[tcol + i] = (char)((w[i / 4] >> (8 * (i % 4))) & 0xffu);
             }
         } else if constexpr (OP == OP_PEARSON_BWD) {
@@ -1202,6 +1230,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 store_vec<DT>(orow1, tcol, tn, false, encode<DT>(gw, 1.f));
             }
         }
+        prefetched = pf_next;
     }
 
     if constexpr (NCP) {
@@ -1224,6 +1253,10 @@ template <int OP, int DT, int VPT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(resident_waves<OP, DT, VPT>())))
 void k_resident(RowArgs a) {
     constexpr int EPV = Io<DT>::EPV;
+    if (a.flags & F_PROBE) {
+        coresidency_probe(a);
+        return;
+    }
     // a launch recorded in a graph takes its epoch from device memory, bumped
     // by the kernel launched before it on every replay
     if (a.epoch == 0u && a.epoch_ptr)

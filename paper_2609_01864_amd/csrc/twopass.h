@@ -379,14 +379,16 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
             });
             block_reduce<NW, 1>(am, MergeMax(), red, parity);
             const float qm = I8 ? 127.f : kFp8Max;
-            const float inv = am[0] > 0.f ? qm / am[0] : 1.f;
-            if (writer) a.so[row] = am[0] > 0.f ? am[0] / qm : 1.f;
+            const float amx = am[0];
+            float qsc = 1.f, inv = 1.f;  // an all-zero row: every code is 0
+            if (amx > 0.f) quant_row_factors(amx, qm, qsc, inv);
+            if (writer) a.so[row] = amx > 0.f ? amx / qm : 1.f;
             stream_row<DT, BLOCK, U, true>(r0, nullptr, N, al0, al1, [&](int64_t v, u32x4 xv, u32x4, int nv) {
                 if (nv == 0) return;
                 float q[EPV];
                 decode<DT>(xv, q, 1.f);
                 unsigned w[EPV / 4];
-                quant_codes<I8, EPV>(q, inv, w);
+                quant_codes_exact<I8, EPV>(q, qsc, inv, amx > 0.f ? amx : 1.f, w);
                 code_store<EPV>(orow, v, nv, w);
             });
         } else if constexpr (OP == OP_PEARSON_BWD) {

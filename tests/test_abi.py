@@ -155,3 +155,28 @@ def test_operand_validation_before_launch():
     for mats, vecs in bad:
         with pytest.raises(ValueError):
             C._validate(3, 8, x, mats, vecs)
+
+
+def test_codes_out_validation():
+    # a caller-supplied codes tensor must match the format's dtype (int8 for
+    # 'int8', uint8 for 'fp8'), the shape and unit inner stride
+    import torch
+
+    from paper_2609_01864_amd import credit as C
+
+    dev = torch.device("cpu")
+    assert C._check_codes_out(None, 3, 8, "int8", dev) == torch.int8
+    C._check_codes_out(torch.zeros((3, 8), dtype=torch.int8), 3, 8, "int8", dev)
+    C._check_codes_out(torch.zeros((3, 8), dtype=torch.uint8), 3, 8, "fp8", dev)
+    bad = [
+        (torch.zeros((3, 8), dtype=torch.float32), "int8"),   # element size 4
+        (torch.zeros((3, 8), dtype=torch.int16), "int8"),
+        (torch.zeros((3, 8), dtype=torch.uint8), "int8"),     # would reinterpret the codes
+        (torch.zeros((3, 8), dtype=torch.int8), "fp8"),
+        (torch.zeros((8, 3), dtype=torch.int8).t(), "int8"),  # not unit inner stride
+        (torch.zeros((3, 7), dtype=torch.int8), "int8"),
+        (torch.zeros(24, dtype=torch.int8), "int8"),
+    ]
+    for out, fmt in bad:
+        with pytest.raises(ValueError):
+            C._check_codes_out(out, 3, 8, fmt, dev)

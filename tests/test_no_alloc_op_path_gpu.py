@@ -1,0 +1,87 @@
+"""Operator calls allocate nothing and time nothing, whatever the selector:
+with plan == NULL a call on a shape it has never seen runs the network's
+untimed first choice in buffers allocated when the model was set (the timing
+selectors act only through credit_select), so the device's free memory is the
+same before and after; and a first call on a fresh shape made while the stream
+is being captured into a graph records and replays correctly."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2609_01864_amd import credit as C
+from paper_2609_01864_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+EPS = 1e-5
+
+
+@pytest.fixture(scope="module")
+def hmodel(lib_built):
+    h = C.Handle(0)  # with the installed selector model
+    assert h.model_loaded
+    yield h
+    h.close()
+
+
+@pytest.mark.parametrize("sel", [None, C.SEL_LEARNED, C.SEL_LEARNED_TIMED, C.SEL_ANALYTIC, C.SEL_EXHAUSTIVE,
+                                 C.SEL_PEAK, C.SEL_FIXED])
+def test_plan_null_call_on_a_fresh_shape_allocates_nothing(hmodel, sel):
+    h = hmodel
+    if sel is not None:
+        h.set_selector(sel)
+    M, N = 96, 70001 + (sel or 0) * 17  # a shape this handle has not seen
+    x64 = I.norm_rows(M, N, seed=90)
+    g32, b32 = I.norm_params(N, seed=90)
+    x = torch.from_numpy(x64.astype(np.float32)).cuda()
+    g, b = torch.from_numpy(g32).cuda(), torch.from_numpy(b32).cuda()
+    y = torch.empty_like(x)
+    mean = torch.empty(M, device="cuda")
+    rstd = torch.empty(M, device="cuda")
+    nbytes = h.workspace_size(C.LAYERNORM, C.FWD, C.F32, M, N, None)
+    ws = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    print(f"[no-alloc] selector={sel} M={M} N={N} ws={nbytes}", flush=True)
+    st = C.lib().credit_layernorm_fwd(h.ptr, M, N, C.F32, x.data_ptr(), N, None, g.data_ptr(), b.data_ptr(), EPS,
+                                      y.data_ptr(), N, None, mean.data_ptr(), rstd.data_ptr(), None,
+                                      ws.data_ptr(), nbytes, s)
+    assert st == C.OK
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] == free0
+    ref, _, _ = oracle.layernorm_fwd(x64.astype(np.float32).astype(np.float64), g32.astype(np.float64),
+                                     b32.astype(np.float64), EPS)
+    assert np.max(np.abs(y.double().cpu().numpy() - ref)) <= 1e-5
+    assert h.check_errors() == C.OK
+    h.set_selector(C.SEL_LEARNED)
+
+
+def test_first_call_on_a_fresh_shape_inside_a_capture(hmodel):
+    h = hmodel
+    M, N = 40, 50021
+    g32, b32 = I.norm_params(N, seed=91)
+    gamma, beta = torch.from_numpy(g32).cuda(), torch.from_numpy(b32).cuda()
+    sx = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    side = torch.cuda.Stream()
+    # the workspace the capture will use exists beforehand (sized without a plan)
+    h.workspace(h.workspace_size(C.LAYERNORM, C.FWD, C.F32, M, N, None), side.cuda_stream)
+    h.workspace(h.workspace_size(C.SOFTMAX, C.FWD, C.F32, M, N, None), side.cuda_stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    print("[no-alloc] capture of a fresh shape", flush=True)
+    with torch.cuda.graph(graph, stream=side):
+        yl, _, _, _ = C.layernorm_fwd(sx, gamma, beta, EPS, h=h)
+        ys, _ = C.softmax_fwd(sx, h=h)
+    for rep in range(3):
+        x32 = (I.norm_rows(M, N, seed=400 + rep) * (1 + rep)).astype(np.float32)
+        sx.copy_(torch.from_numpy(x32))
+        graph.replay()
+        torch.cuda.synchronize()
+        xr = x32.astype(np.float64)
+        ref, _, _ = oracle.layernorm_fwd(xr, g32.astype(np.float64), b32.astype(np.float64), EPS)
+        assert np.max(np.abs(yl.double().cpu().numpy() - ref)) <= 1e-5
+        assert np.max(np.abs(ys.double().cpu().numpy() - oracle.softmax_fwd(xr))) <= 2e-6
+    assert h.check_errors() == C.OK

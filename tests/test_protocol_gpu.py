@@ -91,3 +91,37 @@ def test_primitive_probes(gpu_handle):
     assert min(p["lds_read_bpc"], p["lds_write_bpc"], p["l2_read_bpc"], p["global_write_bpc"]) > 0
     assert p["clock_mhz"] > 50
     assert gpu_handle.check_errors() == C.OK
+
+
+@pytest.mark.parametrize("op,dtype", [("layernorm_fwd", "f32"), ("softmax_fwd", "bf16"), ("layernorm_bwd", "f32"),
+                                      ("rmsnorm_fwd", "fp8")])
+def test_exchange_under_member_skew(gpu_handle, op, dtype):
+    # test-only skew: before each exchange, member c of row r waits
+    # (7 c + r) % 13 microseconds, so members publish out of step and some
+    # reach their wait long before the others publish (Sec. III-C: the
+    # exchange must not depend on arrival order).  Every split factor: the
+    # skewed run matches the oracle and is bitwise equal to the unskewed run.
+    # Waits stay bounded (the default spin limit), so every kernel exits.
+    h = gpu_handle
+    case = Case(op, dtype, 48, 65536, seed=77)
+    ref = case.reference()
+    main = "y" if op.endswith("fwd") else "dx"
+    for k in (2, 4, 8, 16, 32):
+        p = C.plan("split", k)
+        if not h.plan_legal(*{"layernorm_fwd": (C.LAYERNORM, C.FWD), "softmax_fwd": (C.SOFTMAX, C.FWD),
+                              "layernorm_bwd": (C.LAYERNORM, C.BWD), "rmsnorm_fwd": (C.RMSNORM, C.FWD)}[op],
+                            {"f32": C.F32, "bf16": C.BF16, "fp8": C.FP8}[dtype], case.M, case.N, p):
+            continue
+        plain = case.run(h, p, ref=ref)
+        h.set_option(C.OPT_TEST_SKEW, 1)
+        try:
+            print(f"[protocol] skew {op} {dtype} k={k}", flush=True)
+            skewed = case.run(h, p, ref=ref)
+        finally:
+            h.set_option(C.OPT_TEST_SKEW, 0)
+        assert h.check_errors() == C.OK
+        check_case(case, skewed, ref)
+        assert np.array_equal(plain[main], skewed[main]), f"k={k}: skew changed the result"
+        if op == "layernorm_bwd":
+            assert np.array_equal(plain["dgamma"], skewed["dgamma"]) and np.array_equal(plain["dbeta"],
+                                                                                     skewed["dbeta"])

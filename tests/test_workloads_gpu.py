@@ -4,8 +4,9 @@ quantisation, Pearson-correlation backward, weighted-variance backward --
 through the C ABI, against the FP64 oracle on the values the GPU consumed.
 
 Tolerances:
-* quantisation: bit-exact codes and scales (both sides take the decisions in
-  FP32 with the same operations);
+* quantisation: bit-exact codes and scales (the code nearest to
+  x * Q / amax, decided exactly on both sides; the scale amax / Q rounded
+  once to FP32);
 * FP32 gradients: |got - ref| <= 1e-5 * m elementwise, with m the magnitude
   of the terms of the last operation, each statistic that cancels counted at
   the size of its summands (e.g. Pearson |dr / sqrt(Sxx Syy)| |y - mean y|
