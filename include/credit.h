@@ -200,6 +200,26 @@ credit_status_t credit_layernorm_fwd(credit_handle_t h, int64_t M, int64_t N, cr
                                      const credit_plan_t *plan, void *ws, size_t ws_bytes,
                                      void *stream);
 
+/* The same LayerNorm forward without a workspace argument and without any
+ * allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * split-row exchange slots live in a library-owned scratch array of
+ * credit_noalloc_scratch_bytes() (16 MiB) per device, set up when the handle
+ * is created and kept until the process ends; a plan needing more
+ * (M * 3 * k * 2 * 8 + 256 bytes for LayerNorm) returns CREDIT_ERR_WORKSPACE.
+ * plan == NULL takes the cached plan of the shape, else the fixed rule (no
+ * device work besides the operator's own kernels).  Every call on a device
+ * shares that device's scratch: calls that may overlap on one device (two
+ * streams, two threads) race and must be serialised by the caller.  `stream`
+ * must belong to the handle's device. */
+credit_status_t credit_layernorm_fwd_noalloc(credit_handle_t h, int64_t M, int64_t N,
+                                             credit_dtype_t dt, const void *x, int64_t ldx,
+                                             const float *x_scale, const float *gamma,
+                                             const float *beta, float eps, void *y, int64_t ldy,
+                                             float *y_scale, float *mean, float *rstd,
+                                             const credit_plan_t *plan, void *stream);
+size_t credit_noalloc_scratch_bytes(void);
+
 /* LayerNorm backward: xhat = (x - mean) * rstd, g = dy * gamma,
  * dx = rstd * (g - mean(g) - xhat * mean(g * xhat)),
  * dgamma = sum over rows of dy * xhat, dbeta = sum over rows of dy.

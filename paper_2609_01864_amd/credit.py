@@ -107,6 +107,9 @@ _SIGS = {
     "credit_softmax_fwd": ([_P, _I64, _I64, _S, _P, _I64, _P, _P, _I64, _P, _PP, _P, _SZ, _P], _S),
     "credit_softmax_bwd": ([_P, _I64, _I64, _S, _P, _I64, _P, _P, _I64, _P, _P, _I64, _P, _PP, _P, _SZ, _P], _S),
     "credit_layernorm_fwd": ([_P, _I64, _I64, _S, _P, _I64, _P, _P, _P, _F, _P, _I64, _P, _P, _P, _PP, _P, _SZ, _P], _S),
+    "credit_layernorm_fwd_noalloc": ([_P, _I64, _I64, _S, _P, _I64, _P, _P, _P, _F, _P, _I64, _P, _P, _P, _PP,
+                                      _P], _S),
+    "credit_noalloc_scratch_bytes": ([], _SZ),
     "credit_layernorm_bwd": ([_P, _I64, _I64, _S, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, _F, _P, _I64, _P, _P, _P,
                               _PP, _P, _SZ, _P], _S),
     "credit_rmsnorm_fwd": ([_P, _I64, _I64, _S, _P, _I64, _P, _P, _F, _P, _I64, _P, _P, _PP, _P, _SZ, _P], _S),

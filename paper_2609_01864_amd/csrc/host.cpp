@@ -185,8 +185,18 @@ struct Launch {
 
 }  // namespace
 
+// Device scratch of the allocation-free entry point
+// (credit_layernorm_fwd_noalloc): split-row exchange slots in place of a
+// caller's workspace.  One copy per device, kept until the process ends and
+// shared by every call on that device.  Host code never hands `scratch`
+// itself to a kernel: each handle takes the array's address on its device
+// with hipGetSymbolAddress when it is created.
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct credit_handle_s {
     int device = 0;
+    char *scratch_dev = nullptr;  // this device's copy of `scratch`
     int cus = kDefaultCUs;
     std::string arch;
     hipStream_t stream = nullptr;  // timing stream
@@ -524,8 +534,10 @@ credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void 
     return CREDIT_OK;
 }
 
+// `host_pick`: with plan == NULL and no cached plan, take the fixed rule
+// (host arithmetic) instead of running the network on the device.
 credit_status_t run_op(credit_handle_t h, const OpCall &c, const credit_plan_t *plan, void *ws, size_t ws_bytes,
-                       void *stream, bool recompute) {
+                       void *stream, bool recompute, bool host_pick = false) {
     if (!h) return CREDIT_ERR_INVALID_ARG;
     if (c.M < 0 || c.N <= 0) return CREDIT_ERR_INVALID_ARG;
     if (!dt_ok(c.k_op, c.dt)) return CREDIT_ERR_INVALID_ARG;
@@ -557,7 +569,7 @@ credit_status_t run_op(credit_handle_t h, const OpCall &c, const credit_plan_t *
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess) return CREDIT_ERR_HIP;
         credit_status_t st = pick_plan(h, c.k_op, c.dt, c.M, c.N, &p, nullptr, false,
-                                       cs == hipStreamCaptureStatusActive);
+                                       host_pick || cs == hipStreamCaptureStatusActive);
         if (st != CREDIT_OK) return st;
     }
     Launch L;
@@ -1324,6 +1336,37 @@ credit_status_t credit_create(int device, credit_handle_t *out) {
             return CREDIT_ERR_HIP;
         }
         read_env(h);
+        // the allocation-free entry point's scratch on this device: its
+        // address, and (once per device and process) its slots zeroed by a
+        // fill kernel; the wait-fence event is created here too, so that no
+        // operator call creates one
+        void *sp = nullptr;
+        if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+            (void)hipGetLastError();
+            credit_destroy(h);
+            return CREDIT_ERR_HIP;
+        }
+        h->scratch_dev = (char *)sp;
+        {
+            static std::mutex zm;
+            static bool zeroed[64] = {false};
+            std::lock_guard<std::mutex> zg(zm);
+            if (!zeroed[device & 63]) {
+                if (zero_words(sp, (int64_t)(kScratchBytes / 4), h->stream) != hipSuccess ||
+                    hipStreamSynchronize(h->stream) != hipSuccess) {
+                    credit_destroy(h);
+                    return CREDIT_ERR_HIP;
+                }
+                zeroed[device & 63] = true;
+            }
+            WaitFence &f = wait_fence(device);
+            std::lock_guard<std::mutex> fg(f.m);
+            if (!f.ev && hipEventCreateWithFlags(&f.ev, hipEventDisableTiming) != hipSuccess) {
+                f.ev = nullptr;
+                credit_destroy(h);
+                return CREDIT_ERR_HIP;
+            }
+        }
         if (verify_coresidency(h) != CREDIT_OK) {
             credit_destroy(h);
             return CREDIT_ERR_HIP;
@@ -1475,6 +1518,29 @@ credit_status_t credit_layernorm_fwd(credit_handle_t h, int64_t M, int64_t N, cr
     c.ld1 = N;
     try { return run_op(h, c, plan, ws, ws_bytes, stream, false); } catch (...) { return CREDIT_ERR_HIP; }
 }
+
+credit_status_t credit_layernorm_fwd_noalloc(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt,
+                                             const void *x, int64_t ldx, const float *x_scale, const float *gamma,
+                                             const float *beta, float eps, void *y, int64_t ldy, float *y_scale,
+                                             float *mean, float *rstd, const credit_plan_t *plan, void *stream) {
+    if (!h || !h->scratch_dev) return CREDIT_ERR_INVALID_ARG;
+    OpCall c;
+    std::memset(&c, 0, sizeof(c));
+    c.k_op = OP_LN_FWD; c.dt = dt; c.M = M; c.N = N;
+    c.in0 = x; c.ld0 = ldx; c.s0 = x_scale;
+    c.gamma = gamma; c.beta = beta; c.eps = eps;
+    c.out = y; c.ldo = ldy; c.so = y_scale;
+    c.mean_out = mean; c.rstd_out = rstd;
+    c.ld1 = N;
+    // a plan whose workspace exceeds the scratch returns CREDIT_ERR_WORKSPACE
+    try {
+        return run_op(h, c, plan, h->scratch_dev, kScratchBytes, stream, false, true);
+    } catch (...) {
+        return CREDIT_ERR_HIP;
+    }
+}
+
+size_t credit_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 credit_status_t credit_layernorm_bwd(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const void *x,
                                      int64_t ldx, const float *x_scale, const void *dy, int64_t lddy,
