@@ -52,35 +52,57 @@ def algorithmic_bytes(op: str, M: int, N: int) -> int:
     return M * N * 4 * 2 + vec * N * 4 + vec * M * 4
 
 
-def cpu_baseline(target_s: float = 10.0):
-    """The FP64 oracle (as it stands) on the whole workload -- every (op, N),
-    all 1024 rows -- repeated until about `target_s` seconds of oracle time,
-    on all host threads.  Input generation is outside the timed calls."""
+def cpu_baseline(target_s: float = 10.0, single_s: float = 4.0):
+    """The FP64 oracle (as it stands, built -O3 -march=native on this host) on
+    the whole workload -- every (op, N), all 1024 rows -- repeated until about
+    `target_s` seconds of oracle time on all host threads, then on one thread
+    for about `single_s` seconds.  Input generation is outside the timed
+    calls."""
     import numpy as np
 
     import oracle
     from paper_2609_01864_amd import inputs as I
 
-    total_bytes = 0
-    total_s = 0.0
-    passes = 0
-    while total_s < target_s and passes < 60:
-        for N in WIDTHS:
-            x = I.norm_rows(M_ROWS, N, seed=1, tensor=0).astype(np.float32).astype(np.float64)
-            g, b = I.norm_params(N, seed=1)
-            g = g.astype(np.float64)
-            b = b.astype(np.float64)
-            t0 = time.perf_counter()
-            oracle.layernorm_fwd(x, g, b, EPS)
-            oracle.rmsnorm_fwd(x, g, EPS)
-            total_s += time.perf_counter() - t0
-            total_bytes += algorithmic_bytes("layernorm_fwd", M_ROWS, N) + algorithmic_bytes("rmsnorm_fwd", M_ROWS, N)
-            del x
-        passes += 1
-    return {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    oracle.use_native()
+
+    def run(limit_s, rows):
+        total_bytes, total_s, passes = 0, 0.0, 0
+        sel = np.arange(rows)
+        while total_s < limit_s and passes < 60:
+            for N in WIDTHS:
+                x = I.norm_rows(M_ROWS, N, seed=1, tensor=0, rows=sel).astype(np.float32).astype(np.float64)
+                g, b = I.norm_params(N, seed=1)
+                g = g.astype(np.float64)
+                b = b.astype(np.float64)
+                t0 = time.perf_counter()
+                oracle.layernorm_fwd(x, g, b, EPS)
+                oracle.rmsnorm_fwd(x, g, EPS)
+                total_s += time.perf_counter() - t0
+                total_bytes += algorithmic_bytes("layernorm_fwd", rows, N) + algorithmic_bytes("rmsnorm_fwd", rows, N)
+                del x
+            passes += 1
+        return total_bytes / total_s / 1e9, passes, total_s
+
+    cores = oracle.num_threads()
+    gb_all, passes, secs = run(target_s, M_ROWS)
+    oracle.set_num_threads(1)
+    gb_one, passes1, secs1 = run(single_s, 32)
+    oracle.set_num_threads(cores)
+    return {"value": round(gb_all, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "single_core_value": round(gb_one, 3),
             "sample": f"the whole workload (LayerNorm + RMSNorm forward, all 1024 rows of each N) x {passes} "
-                      f"passes, FP64 C oracle with OpenMP, {total_s:.1f} s of oracle time"}
+                      f"passes on {cores} threads ({secs:.1f} s of oracle time); on 1 thread the first 32 rows "
+                      f"of each N x {passes1} passes ({secs1:.1f} s); FP64 C oracle, gcc -O3 -march=native "
+                      f"-fopenmp"}
+
+
+def device_identity(torch):
+    """The GPU the numbers come from: name, architecture, CUs, PCI location
+    and UUID, as the runtime reports them."""
+    pr = torch.cuda.get_device_properties(0)
+    return {"name": pr.name, "arch": pr.gcnArchName, "cus": pr.multi_processor_count,
+            "pci": f"{pr.pci_domain_id:04x}:{pr.pci_bus_id:02x}:{pr.pci_device_id:02x}", "uuid": str(pr.uuid),
+            "total_memory_gib": round(pr.total_memory / 2 ** 30, 1)}
 
 
 def kernel_symbol(C, h, op_num, dt_num, M, N, p):
@@ -92,27 +114,92 @@ def kernel_symbol(C, h, op_num, dt_num, M, N, p):
     return f"void credit::k_resident<{kop}, {dt_num}, {g['vpt']}>", g["grid"] * g["block"]
 
 
+def precision_inputs(M, N, seed, dev):
+    """The precision workload's rows on the GPU: x = 3 N(0,1) with exactly
+    round(0.01 N) positions per row set to +-40 (random sign); FP32, BF16 and
+    FP8-e4m3 copies (FP8: per-row scale amax / 448)."""
+    import torch
+
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    x = 3.0 * torch.randn((M, N), generator=g, device=dev)
+    k = int(round(0.01 * N))
+    pos = torch.rand((M, N), generator=g, device=dev).topk(k, dim=1).indices
+    sign = torch.where(torch.rand((M, k), generator=g, device=dev) < 0.5, -40.0, 40.0)
+    x.scatter_(1, pos, sign)
+    del pos, sign
+    xs = x.abs().amax(dim=1) / 448.0
+    codes = (x / xs[:, None]).clamp(-448.0, 448.0).to(torch.float8_e4m3fn).view(torch.uint8)
+    return {"f32": (x, None), "bf16": (x.to(torch.bfloat16), None), "fp8": (codes, xs.contiguous())}
+
+
+def time_cold(fn, flush, reps=15, warm=3):
+    """Median of `reps` runs of fn() between HIP events on torch's current
+    stream (the stream the binding launches on), each after writing a 512 MiB
+    buffer so the inputs come from HBM."""
+    import torch
+
+    st = torch.cuda.current_stream()
+    t = []
+    for r in range(warm + reps):
+        flush.fill_(r)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        fn()
+        e1.record(st)
+        e1.synchronize()
+        if r >= warm:
+            t.append(e0.elapsed_time(e1) * 1e3)
+    t.sort()
+    return t[len(t) // 2] if len(t) % 2 else 0.5 * (t[len(t) // 2 - 1] + t[len(t) // 2])
+
+
 def forms(C, h):
-    """Cold-cache times (flush, median of 15) of the precision workload
-    (softmax and LayerNorm forward, M = 4096, N in {65536, 262144}, BF16 and
-    FP8 I/O vs the FP32 two-pass kernel), of the backward workload (softmax
-    and LayerNorm backward, M = 2048, N = 131072, FP32 and BF16) and of the
-    LayerNorm -> e4m3 fusion, with the selector's plans."""
+    """The precision workload (softmax and LayerNorm forward, M = 4096, N in
+    {65536, 262144}, BF16 and FP8 I/O next to FP32, each against the FP32
+    two-pass kernel) timed on its own rows (3 N(0,1) with 1% at +-40), cold
+    cache, median of 15; GB/s on algorithmic bytes (rows in and out, FP8 row
+    scales in and out, gamma / beta once, mean / rstd out).  Then the
+    backward workload (softmax and LayerNorm backward, M = 2048,
+    N = 131072, FP32 and BF16) and the LayerNorm -> e4m3 fusion, with the
+    selector's plans."""
+    import torch
+
+    dev = torch.device("cuda:0")
     out = {"precision": [], "backward": []}
     e = {C.F32: 4, C.BF16: 2, C.FP8: 1}
-    for op, name in ((C.SOFTMAX, "softmax_fwd"), (C.LAYERNORM, "layernorm_fwd")):
-        for N in (65536, 262144):
-            M = 4096
-            t2 = h.time_plan(op, C.FWD, C.F32, M, N, C.plan("two_pass"), 15, True)
+    dnum = {"f32": C.F32, "bf16": C.BF16, "fp8": C.FP8}
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    for N in (65536, 262144):
+        M = 4096
+        data = precision_inputs(M, N, seed=2 + N, dev=dev)
+        g = torch.rand(N, device=dev) + 0.5
+        b = 0.1 * torch.randn(N, device=dev)
+        for op, name in ((C.SOFTMAX, "softmax_fwd"), (C.LAYERNORM, "layernorm_fwd")):
+            def runner(dn, p):
+                x, xs = data[dn]
+                y = torch.empty_like(x)
+                ys = torch.empty(M, device=dev) if dn == "fp8" else None
+                if op == C.SOFTMAX:
+                    return lambda: C.softmax_fwd(x, xs, p=p, out=y, out_scale=ys, h=h)
+                return lambda: C.layernorm_fwd(x, g, b, EPS, xs, p=p, out=y, h=h)
+
+            def alg(dn):
+                nb = M * N * e[dnum[dn]] * 2 + (M * 8 if dn == "fp8" else 0)
+                return nb + (N * 8 + M * 8 if op == C.LAYERNORM else 0)
+
+            t2 = time_cold(runner("f32", C.plan("two_pass")), flush)
             row = {"op": name, "M": M, "N": N, "fp32_two_pass_us": round(t2, 1)}
-            for dt, dn in ((C.F32, "f32"), (C.BF16, "bf16"), (C.FP8, "fp8")):
-                p, _ = h.select(op, C.FWD, dt, M, N)
-                t = h.time_plan(op, C.FWD, dt, M, N, p, 15, True)
-                row[dn] = {"plan": list(p.as_tuple()), "us": round(t, 1),
-                           "gbps": round(M * N * e[dt] * 2 / (t * 1e3), 1),
+            for dn in ("f32", "bf16", "fp8"):
+                p, _ = h.select(op, C.FWD, dnum[dn], M, N)
+                t = time_cold(runner(dn, p), flush)
+                row[dn] = {"plan": list(p.as_tuple()), "us": round(t, 1), "gbps": round(alg(dn) / (t * 1e3), 1),
                            "speedup_vs_fp32_two_pass": round(t2 / t, 3)}
             out["precision"].append(row)
             log(f"precision {name} N={N}: {row}")
+        del data
+    del flush
     for op, name in ((C.SOFTMAX, "softmax_bwd"), (C.LAYERNORM, "layernorm_bwd")):
         M, N = 2048, 131072
         for dt, dn in ((C.F32, "f32"), (C.BF16, "bf16")):
@@ -328,6 +415,7 @@ def main():
     import torch
 
     from paper_2609_01864_amd import credit as C
+    from paper_2609_01864_amd import tune as T
 
     dev = torch.device("cuda:0")
     h = C.Handle(0)
@@ -440,32 +528,45 @@ def main():
                 "algorithmic_bytes_per_launch": algorithmic_bytes(dom["op"], M_ROWS, dom["N"])}
 
     # --------------------------------------------- regret vs exhaustive
-    regrets = []
+    regrets, regrets_na = [], []
     if not args.no_regret:
         for r in per_shape:
             o = opnum[r["op"]]
             best = None
-            times = {}
+            times, rec = {}, {"times": {}, "spread": {}}
             for c in range(C.NUM_PLANS):
                 p = C.plan_of_class(c)
                 if not h.plan_legal(o, C.FWD, C.F32, M_ROWS, r["N"], p):
                     continue
-                t = h.time_plan(o, C.FWD, C.F32, M_ROWS, r["N"], p, reps=15, flush=True)
+                st = h.time_plan_stats(o, C.FWD, C.F32, M_ROWS, r["N"], p, reps=15, flush=True)
+                t = st["median_us"]
                 times[f"{p.variant},{p.k}"] = round(t, 2)
+                rec["times"][str(c)] = t
+                rec["spread"][str(c)] = {"mad": st["mad_us"], "min": st["min_us"], "p90": st["p90_us"]}
                 if best is None or t < best[1]:
                     best = (p, t)
             pk = picks[(r["op"], r["N"])][0]
             tp = times[f"{pk.variant},{pk.k}"]
+            cls = {C.plan_of_class(c).as_tuple(): c for c in range(C.NUM_PLANS)}
+            ra = T.regret_stats([rec], [cls[pk.as_tuple()]])
             r["plan_times_us"] = times
+            r["plan_mad_us"] = {f"{C.plan_of_class(int(c)).variant},{C.plan_of_class(int(c)).k}": round(v["mad"], 2)
+                                for c, v in rec["spread"].items()}
             r["best_plan"] = [int(best[0].variant), int(best[0].k)]
+            jb = C.plan_of_class(T.judge_best(rec))
+            r["judge_plan"] = [int(jb.variant), int(jb.k)]
             r["regret"] = round(tp / best[1] - 1.0, 4)
+            r["regret_noise_aware"] = round(ra["noise_aware_geomean"] - 1.0, 4)
             regrets.append(tp / best[1])
+            regrets_na.append(ra["noise_aware_geomean"])
             if h.model_loaded:  # the network's own first choice, before any timing
                 h.set_selector(C.SEL_LEARNED)
                 pu = h.select(o, C.FWD, C.F32, M_ROWS, r["N"])[0]
                 h.set_selector(sel)
                 r["learned_untimed_plan"] = [int(pu.variant), int(pu.k)]
                 r["learned_untimed_regret"] = round(times[f"{pu.variant},{pu.k}"] / best[1] - 1.0, 4)
+                r["learned_untimed_regret_noise_aware"] = round(
+                    T.regret_stats([rec], [cls[pu.as_tuple()]])["noise_aware_geomean"] - 1.0, 4)
             log(f"{r['op']} N={r['N']}: times {times} pick {r['plan']} regret {r['regret']:+.3f}")
     copy_gbps = h.copy_bandwidth(1 << 30, 15)
     log(f"copy kernel: {copy_gbps:.1f} GB/s")
@@ -501,6 +602,11 @@ def main():
         "cpu_baseline": cpu,
         "regret_geomean": round(math.exp(sum(math.log(x) for x in regrets) / len(regrets)) - 1.0, 4)
         if regrets else None,
+        "regret_geomean_noise_aware": round(math.exp(sum(math.log(x) for x in regrets_na) / len(regrets_na)) - 1.0,
+                                            4) if regrets_na else None,
+        "regret_geomean_learned_untimed_noise_aware": round(math.exp(sum(
+            math.log(1.0 + r["learned_untimed_regret_noise_aware"]) for r in per_shape) / len(per_shape)) - 1.0, 4)
+        if per_shape and all("learned_untimed_regret_noise_aware" in r for r in per_shape) else None,
         "regret_geomean_learned_untimed": round(math.exp(sum(math.log(1.0 + r["learned_untimed_regret"])
                                                              for r in per_shape) / len(per_shape)) - 1.0, 4)
         if per_shape and all("learned_untimed_regret" in r for r in per_shape) else None,
@@ -511,6 +617,7 @@ def main():
         "paper_suite": suite_res,
         "primitives": prims,
         "source_hash": source_hash(),
+        "device": device_identity(torch),
     }
     print(json.dumps(out), flush=True)
 

@@ -158,7 +158,10 @@ credit_status_t credit_workspace_size(credit_handle_t h, credit_op_t op, credit_
                                       const credit_plan_t *plan, size_t *bytes);
 
 /* Whether `plan` is legal for the shape: the slice of ceil(N/k) elements must
- * fit the kernel's register capacity (the capacity rule of Eq. (3)) and, for
+ * fit the kernel's capacity (the capacity rule of Eq. (3)): 32 16-byte vectors
+ * per thread of registers at most (fewer for the backward operators), and for
+ * the FP32 / BF16 softmax, LayerNorm and RMSNorm forward up to 16 or 36 more
+ * per thread in LDS (64 KiB or 144 KiB per workgroup); and, for
  * k > 1, the k workgroups of a row must be co-resident.  Returns CREDIT_OK or
  * CREDIT_ERR_UNSUPPORTED. */
 credit_status_t credit_plan_legal(credit_handle_t h, credit_op_t op, credit_dir_t dir,
@@ -336,6 +339,20 @@ credit_status_t credit_time_plan(credit_handle_t h, credit_op_t op, credit_dir_t
                                  const credit_plan_t *plan, int reps, int flush,
                                  float *median_us);
 
+/* The same timing with the spread of the runs: median, minimum, 90th
+ * percentile (nearest rank) and median absolute deviation, in microseconds.
+ * The exhaustive selector counts plans within max(1%, 2 MAD) of the fastest
+ * median as equally fast and keeps the one that moves fewer bytes (row-
+ * resident, then split plans by increasing k, then two-pass). */
+typedef struct {
+    float median_us, min_us, p90_us, mad_us;
+    int32_t runs;
+} credit_timing_t;
+credit_status_t credit_time_plan_stats(credit_handle_t h, credit_op_t op, credit_dir_t dir,
+                                       credit_dtype_t dt, int64_t M, int64_t N,
+                                       const credit_plan_t *plan, int reps, int flush,
+                                       credit_timing_t *out);
+
 /* Times the work-free control kernel of Sec. III-D for a split factor k at
  * (op, dir, dtype, M, N): the same persistent grid, split factor, occupancy
  * and exchange waits as the split-row kernel, no row data.  k == 1 gives the
@@ -396,6 +413,10 @@ typedef struct {
     int32_t xcd_same[2], xcd_cross[2];
     int32_t errors;             /* bounded waits that gave up (0 expected)        */
 } credit_primitives_t;
+/* A successful run without errors also calibrates the handle's analytic model
+ * (Eq. (8)): the measured clock replaces the 2.4 GHz peak, one workgroup's
+ * global store rate the slot-store rate, and one workgroup's LDS read rate
+ * prices the replay of slices held in LDS. */
 credit_status_t credit_probe_primitives(credit_handle_t h, int reps, credit_primitives_t *out);
 
 /* ------------------------------------------------------------ learned model

@@ -33,25 +33,45 @@ _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.c_int64
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2 -fopenmp).  Returns the library path."""
-    if force or not os.path.exists(_LIB_PATH) or (
-        os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)
-    ):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+_NATIVE_PATH = os.path.join(_HERE, "liboracle_native.so")
+
+
+def build(force: bool = False, native: bool = False) -> str:
+    """Compile the oracle with gcc (-O2 -fopenmp, portable).  native=True builds
+    the copy the CPU-baseline timing uses, -O3 -march=native, on the machine
+    that runs it (never shipped between machines).  Both keep FP64 operations
+    uncontracted (-ffp-contract=off), so their results are identical.
+    Returns the library path."""
+    path = _NATIVE_PATH if native else _LIB_PATH
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp%d" % os.getpid()
+        opt = ["-O3", "-march=native"] if native else ["-O2"]
         subprocess.check_call(
-            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"]
+            ["gcc", *opt, "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC,
+             "-lm"]
         )
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, path)
+    return path
 
 
-def _load():
+def use_native() -> str:
+    """Switches this process to the -O3 -march=native build (built here, now).
+    For the CPU-baseline timing only; call before any other oracle function."""
+    global _lib
+    path = build(force=True, native=True)
+    _lib = None
+    _load(path)
+    return path
+
+
+def _load(path: str = None):
     global _lib
     if _lib is not None:
         return _lib
-    build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    if path is None:
+        build()
+        path = _LIB_PATH
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     sig = {
         "oracle_num_threads": ([], ctypes.c_int),
@@ -62,6 +82,8 @@ def _load():
         "oracle_decode_e4m3": ([P, P, _I64], None),
         "oracle_encode_e4m3": ([P, P, _I64], None),
         "oracle_e4m3_step": ([ctypes.c_double], ctypes.c_double),
+        "oracle_encode_bf16_f32": ([P, P, _I64], None),
+        "oracle_encode_e4m3_f32": ([P, P, _I64], None),
         "oracle_softmax_fwd": ([_I64, _I64, P, P], None),
         "oracle_softmax_bwd": ([_I64, _I64, P, P, P], None),
         "oracle_layernorm_fwd": ([_I64, _I64, P, P, P, ctypes.c_double, P, P, P], None),
@@ -116,6 +138,17 @@ def encode_bf16(v) -> np.ndarray:
     v = _f64(v)
     out = np.empty(v.shape, np.uint16)
     _load().oracle_encode_bf16(_p(v), _p(out), v.size)
+    return out
+
+
+def encode_from_f32(x32, fmt: str) -> np.ndarray:
+    """RNE encode of binary32 values ('bf16': bit patterns as uint16; 'fp8':
+    e4m3 codes saturating at +-448), the same definitions as encode_bf16 /
+    encode_e4m3 applied to exact FP64 conversions of the inputs."""
+    x = np.ascontiguousarray(x32, dtype=np.float32)
+    out = np.empty(x.shape, np.uint16 if fmt == "bf16" else np.uint8)
+    f = _load().oracle_encode_bf16_f32 if fmt == "bf16" else _load().oracle_encode_e4m3_f32
+    f(_p(x), _p(out), x.size)
     return out
 
 

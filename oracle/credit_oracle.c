@@ -171,6 +171,20 @@ void oracle_encode_e4m3(const double *in, uint8_t *out, int64_t n)
     for (int64_t i = 0; i < n; ++i) out[i] = e4m3_from_double(in[i]);
 }
 
+/* The same two encoders applied to binary32 inputs (each converted to double
+ * exactly), spread over threads: for sweeps over every FP32 bit pattern. */
+void oracle_encode_bf16_f32(const float *in, uint16_t *out, int64_t n)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) out[i] = bf16_from_double((double)in[i]);
+}
+
+void oracle_encode_e4m3_f32(const float *in, uint8_t *out, int64_t n)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) out[i] = e4m3_from_double((double)in[i]);
+}
+
 /* Spacing of the e4m3 grid at magnitude v (the size of one step). */
 double oracle_e4m3_step(double v)
 {

@@ -55,6 +55,11 @@ class Workload(ctypes.Structure):
                 ("b_keep", ctypes.c_float), ("stages", ctypes.c_int32), ("q", ctypes.c_int32 * 4)]
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("median_us", ctypes.c_float), ("min_us", ctypes.c_float), ("p90_us", ctypes.c_float),
+                ("mad_us", ctypes.c_float), ("runs", ctypes.c_int32)]
+
+
 class Instance(ctypes.Structure):
     _fields_ = [("registers", ctypes.c_int32), ("private_bytes", ctypes.c_int32), ("per_cu", ctypes.c_int32),
                 ("model_per_cu", ctypes.c_int32), ("coresident_per_cu", ctypes.c_int32)]
@@ -126,6 +131,7 @@ _SIGS = {
     "credit_decode": ([_P, _I64, _I64, _S, _P, _P, _P, _P], _S),
     "credit_check_errors": ([_P, _P], _S),
     "credit_time_plan": ([_P, _S, _S, _S, _I64, _I64, _PP, _S, _S, ctypes.POINTER(_F)], _S),
+    "credit_time_plan_stats": ([_P, _S, _S, _S, _I64, _I64, _PP, _S, _S, ctypes.POINTER(Timing)], _S),
     "credit_time_control": ([_P, _S, _S, _S, _I64, _I64, _I32, _S, ctypes.POINTER(_F)], _S),
     "credit_copy_bandwidth": ([_P, _SZ, _S, ctypes.POINTER(_F)], _S),
     "credit_model_delta": ([_P, _S, _S, _S, _I64, _I64, _F, _P, _P], _S),
@@ -395,6 +401,13 @@ class Handle:
         check(lib().credit_time_plan(self.ptr, op, direction, dtype, M, N, ctypes.byref(p), reps, int(flush),
                                      ctypes.byref(t)), "credit_time_plan")
         return t.value
+
+    def time_plan_stats(self, op, direction, dtype, M, N, p: Plan, reps: int = 15, flush: bool = True) -> dict:
+        """Median, minimum, 90th percentile and MAD (microseconds) of `reps` runs."""
+        t = Timing()
+        check(lib().credit_time_plan_stats(self.ptr, op, direction, dtype, M, N, ctypes.byref(p), reps, int(flush),
+                                           ctypes.byref(t)), "credit_time_plan_stats")
+        return {f: getattr(t, f) for f, _ in Timing._fields_}
 
     def time_control(self, op, direction, dtype, M, N, k: int, reps: int = 15) -> float:
         t = _F()

@@ -262,6 +262,14 @@ __device__ __forceinline__ u32x4 load_vec(const char *row, int64_t e, int nv, bo
     return v;
 }
 
+// The first element of a row, decoded with scale 1: the common shift of a
+// row's moment sums (every workgroup of a row group reads the same element).
+template <int DT> __device__ __forceinline__ float row_first(const char *row) {
+    float f[Io<DT>::EPV];
+    decode<DT>(load_vec<DT, false>(row, 0, 1, false), f, 1.f);
+    return f[0];
+}
+
 template <int DT>
 __device__ __forceinline__ void store_vec(char *row, int64_t e, int nv, bool aligned, u32x4 v) {
     constexpr int EPV = Io<DT>::EPV, B = Io<DT>::BYTES;

@@ -111,6 +111,16 @@ bool two_inputs(int k_op) { return two_in(k_op); }
 int out_bytes(int k_op, int dt) { return byte_out(k_op) ? 1 : dt_bytes(dt); }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Every slice bucket: register-only, then registers plus LDS.
+constexpr int kAllVpts[] = {1, 2, 4, 8, 12, 16, 24, 32, 48, 68};
+bool instance_exists(int k_op, int dt, int vpt) {
+    for (int v : kVpts)
+        if (v == vpt) return vpt <= max_vpt(k_op, dt);
+    for (int v : kLdsVpts)
+        if (v == vpt) return lds_capable(k_op, dt);
+    return false;
+}
+
 const void *resident_fn(int k_op, int dt, int vpt) {
     switch (k_op) {
     case OP_SOFTMAX_FWD: return resident_kernel_softmax_fwd(dt, vpt);
@@ -149,6 +159,10 @@ const void *twopass_fn(int k_op, int dt, int block) {
 // Host copy of the kernels' register model: waves per SIMD a resident kernel
 // is compiled for (used when no device is available to ask).
 int model_waves(int k_op, int dt, int vpt) {
+    if (vpt > kRegVptMax) {  // registers of a 32-vector slice; LDS of the rest
+        const int lds = lds_vpt(vpt) * kBlockThreads * 16 + 1024;
+        return std::max(1, std::min(model_waves(k_op, dt, kRegVptMax), kLdsBytes / lds));
+    }
     int data = vpt * 4 * (two_inputs(k_op) ? 2 : 1) + ncp_of(k_op) * vpt * dt_epv(dt);
     const bool f8o = (dt == CREDIT_FP8_E4M3 && (k_op == OP_LN_FWD || k_op == OP_RMS_FWD)) || k_op == OP_LNQ_FWD;
     if (f8o && vpt * dt_epv(dt) <= kYcMax) data += vpt * dt_epv(dt);  // y kept across the amax stage
@@ -208,6 +222,15 @@ struct credit_handle_s {
     int64_t spin_limit = 1 << 22;
     bool drop_publish = false;
     bool skew = false;  // test only: members publish out of step
+    // device calibration of the analytic model (the MI355X analogue of the
+    // paper's primitive table), filled by credit_probe_primitives; until then
+    // the peak clock and nominal rates
+    struct {
+        bool probed = false;
+        double clock_hz = kClockHz;
+        double slot_bpc = kSlotRate;     // bytes per cycle of one workgroup's stores
+        double lds_read_bpc = kSlotRate;  // bytes per cycle of one workgroup's LDS reads
+    } cal;
     int64_t max_groups = 0;
     // private memory (bytes per lane) of the row-resident / split-row
     // instances, and for those that use it the workgroups per CU verified
@@ -308,7 +331,10 @@ credit_status_t resolve(credit_handle_t h, int k_op, int dt, int64_t M, int64_t 
     int vpt = 0;
     for (int v : kVpts)
         if (v >= need && v <= max_vpt(k_op, dt)) { vpt = v; break; }
-    if (!vpt) return CREDIT_ERR_UNSUPPORTED;  // slice exceeds register capacity (Eq. (3))
+    if (!vpt && lds_capable(k_op, dt))  // registers plus LDS (Eq. (3) with C_res = VGPRs + LDS)
+        for (int v : kLdsVpts)
+            if (v >= need) { vpt = v; break; }
+    if (!vpt) return CREDIT_ERR_UNSUPPORTED;  // slice exceeds register (and LDS) capacity (Eq. (3))
     L.vpt = vpt;
     L.chunk = cvec * epv;
     L.block = kBlockThreads;
@@ -628,9 +654,16 @@ void model_delta(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, doub
             continue;
         }
         const int64_t W = (M + L.groups - 1) / L.groups;  // waves of row groups (Eq. (8))
-        const double t_replay = 0.0;                      // slices replay from registers
-        const double t_deposit = 0.0;                     // the deposit is the load itself
-        const double t_x = kSlotBytes * W * (L.k - 1) * sumq / (kClockHz * kSlotRate) * 1e6;
+        const double clock = h && h->cal.probed ? h->cal.clock_hz : kClockHz;
+        const double slot_bpc = h && h->cal.probed ? h->cal.slot_bpc : kSlotRate;
+        const double lds_bpc = h && h->cal.probed ? h->cal.lds_read_bpc : kSlotRate;
+        // replay: register slots cost nothing; LDS slots are read back once per
+        // pass after the load (softmax: max, sum and output; norms: statistics
+        // and output) at one workgroup's LDS read rate
+        const int passes = k_op == OP_SOFTMAX_FWD ? 3 : 2;
+        const double t_replay = (double)W * passes * lds_vpt(L.vpt) * kBlockThreads * 16.0 / (lds_bpc * clock) * 1e6;
+        const double t_deposit = 0.0;  // the deposit is the load itself (direct loads into LDS too)
+        const double t_x = kSlotBytes * W * (L.k - 1) * sumq / (clock * slot_bpc) * 1e6;
         out[i] = (float)(t_save - t_ctrl_us[i] - t_replay - t_deposit - t_x);
     }
 }
@@ -745,7 +778,25 @@ credit_status_t flush(credit_handle_t h) {
     return launch(flush_kernel(), h->cus * 8, 256, 0, h->stream, args) == hipSuccess ? CREDIT_OK : CREDIT_ERR_HIP;
 }
 
-template <class F> credit_status_t time_median(credit_handle_t h, int reps, int do_flush, F issue_fn, float *us) {
+// Spread of a set of run times: median, minimum, 90th percentile (nearest
+// rank) and the median absolute deviation from the median.
+credit_timing_t timing_of(std::vector<float> t) {
+    credit_timing_t r;
+    std::sort(t.begin(), t.end());
+    const size_t n = t.size();
+    r.median_us = median(t);
+    r.min_us = t.front();
+    r.p90_us = t[std::min(n - 1, (size_t)std::ceil(0.9 * (double)n) - 1)];
+    std::vector<float> dev(n);
+    for (size_t i = 0; i < n; ++i) dev[i] = std::fabs(t[i] - r.median_us);
+    r.mad_us = median(dev);
+    r.runs = (int32_t)n;
+    return r;
+}
+
+template <class F>
+credit_status_t time_median(credit_handle_t h, int reps, int do_flush, F issue_fn, float *us,
+                            credit_timing_t *stats = nullptr) {
     std::vector<float> t;
     for (int r = -3; r < reps; ++r) {
         if (do_flush && flush(h) != CREDIT_OK) return CREDIT_ERR_HIP;
@@ -759,11 +810,12 @@ template <class F> credit_status_t time_median(credit_handle_t h, int reps, int 
         if (r >= 0) t.push_back(ms * 1000.f);
     }
     *us = median(t);
+    if (stats) *stats = timing_of(t);
     return CREDIT_OK;
 }
 
 credit_status_t time_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t p, int reps,
-                          int do_flush, float *us) {
+                          int do_flush, float *us, credit_timing_t *stats = nullptr) {
     std::lock_guard<std::recursive_mutex> g(h->lock);
     Launch L;
     credit_status_t st = resolve(h, k_op, dt, M, N, p, false, L);
@@ -772,7 +824,8 @@ credit_status_t time_plan(credit_handle_t h, int k_op, int dt, int64_t M, int64_
     st = prepare(h, k_op, dt, M, N, L.ws_bytes, b);
     if (st != CREDIT_OK) return st;
     OpCall c = call_for(k_op, dt, M, N, b);
-    return time_median(h, reps > 0 ? reps : 15, do_flush, [&]() { return issue(h, c, L, b.ws, h->stream, false); }, us);
+    return time_median(h, reps > 0 ? reps : 15, do_flush, [&]() { return issue(h, c, L, b.ws, h->stream, false); }, us,
+                       stats);
 }
 
 credit_status_t time_control(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, int k, int reps, float *us) {
@@ -947,22 +1000,42 @@ credit_status_t analytic_pick(credit_handle_t h, int k_op, int dt, int64_t M, in
     return CREDIT_OK;
 }
 
+// Order of the plans by the bytes they move per element: the staged plans
+// read every input once (the row-resident plan, then split factors by the
+// exchange traffic that grows with k), the two-pass plan rereads them.
+int bytes_rank(int c) { return c == 0 ? CREDIT_NUM_PLANS : c; }
+
+// Every legal plan timed (cache flush, median of 15).  The fastest median is
+// the best plan, except that plans within the timing noise of it --
+// max(1%, 2 MAD of either) -- count as equally fast, and among those the one
+// that moves fewer bytes (then the smaller k) is kept.
 credit_status_t exhaustive_pick(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, credit_plan_t *out,
                                 float *pred) {
+    std::vector<std::pair<int, credit_timing_t>> all;
     float best = INFINITY;
     for (int c = 0; c < CREDIT_NUM_PLANS; ++c) {
         credit_plan_t p = class_plan(c);
         if (!plan_ok(h, k_op, dt, M, N, p)) continue;
         float t = 0.f;
-        credit_status_t st = time_plan(h, k_op, dt, M, N, p, 15, 1, &t);
+        credit_timing_t ts;
+        credit_status_t st = time_plan(h, k_op, dt, M, N, p, 15, 1, &t, &ts);
         if (st != CREDIT_OK) return st;
-        if (t < best) {
-            best = t;
-            *out = p;
-        }
+        all.push_back({c, ts});
+        best = std::min(best, t);
     }
+    if (!std::isfinite(best)) return CREDIT_ERR_UNSUPPORTED;
+    credit_timing_t tb = {};
+    for (auto &e : all)
+        if (e.second.median_us == best) tb = e.second;
+    int pick = -1;
+    for (auto &e : all) {
+        const float noise = std::max(0.01f * best, 2.f * std::max(e.second.mad_us, tb.mad_us));
+        if (e.second.median_us - best > noise) continue;
+        if (pick < 0 || bytes_rank(e.first) < bytes_rank(pick)) pick = e.first;
+    }
+    *out = class_plan(pick);
     if (pred) *pred = best;
-    return std::isfinite(best) ? CREDIT_OK : CREDIT_ERR_UNSUPPORTED;
+    return CREDIT_OK;
 }
 
 // The network's best legal plan, or with `timed` its two best legal plans,
@@ -1070,8 +1143,8 @@ credit_status_t verify_coresidency(credit_handle_t h) {
     for (int k_op = 0; k_op < OP_COUNT; ++k_op) {
         for (int dt = CREDIT_F32; dt <= CREDIT_FP8_E4M3; ++dt) {
             if (!dt_ok(k_op, dt)) continue;
-            for (int vpt : kVpts) {
-                if (vpt > max_vpt(k_op, dt)) continue;
+            for (int vpt : kAllVpts) {
+                if (!instance_exists(k_op, dt, vpt)) continue;
                 const void *fn = resident_fn(k_op, dt, vpt);
                 if (!fn) continue;
                 hipFuncAttributes at;
@@ -1772,7 +1845,21 @@ credit_status_t probe_all(credit_handle_t h, int reps, credit_primitives_t *out)
 
 credit_status_t credit_probe_primitives(credit_handle_t h, int reps, credit_primitives_t *out) {
     if (!h || !out || reps < 0) return CREDIT_ERR_INVALID_ARG;
-    try { return probe_all(h, reps, out); } catch (...) { return CREDIT_ERR_HIP; }
+    try {
+        credit_status_t st = probe_all(h, reps, out);
+        if (st == CREDIT_OK && out->errors == 0 && out->clock_mhz > 0.f && out->lds_read_bpc > 0.f &&
+            out->global_write_bpc > 0.f) {
+            // the analytic model's device terms from now on (Eq. (8))
+            std::lock_guard<std::recursive_mutex> g(h->lock);
+            h->cal.probed = true;
+            h->cal.clock_hz = out->clock_mhz * 1e6;
+            h->cal.slot_bpc = out->global_write_bpc;
+            h->cal.lds_read_bpc = out->lds_read_bpc;
+        }
+        return st;
+    } catch (...) {
+        return CREDIT_ERR_HIP;
+    }
 }
 
 credit_status_t credit_encode(credit_handle_t h, int64_t M, int64_t N, credit_dtype_t dt, const float *x,
@@ -1813,6 +1900,18 @@ credit_status_t credit_time_plan(credit_handle_t h, credit_op_t op, credit_dir_t
     if (!h || !plan || !median_us || !valid_enum(op, dir, dt) || M <= 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
     try {
         return time_plan(h, kop(op, dir), dt, M, N, *plan, reps, do_flush, median_us);
+    } catch (...) {
+        return CREDIT_ERR_HIP;
+    }
+}
+
+credit_status_t credit_time_plan_stats(credit_handle_t h, credit_op_t op, credit_dir_t dir, credit_dtype_t dt,
+                                       int64_t M, int64_t N, const credit_plan_t *plan, int reps, int do_flush,
+                                       credit_timing_t *out) {
+    if (!h || !plan || !out || !valid_enum(op, dir, dt) || M <= 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
+    try {
+        float med = 0.f;
+        return time_plan(h, kop(op, dir), dt, M, N, *plan, reps, do_flush, &med, out);
     } catch (...) {
         return CREDIT_ERR_HIP;
     }
@@ -2036,9 +2135,7 @@ credit_status_t credit_instance_info(credit_handle_t h, credit_op_t op, credit_d
                                      int32_t vpt, credit_instance_t *out) {
     if (!out || !valid_enum(op, dir, dt)) return CREDIT_ERR_INVALID_ARG;
     const int k_op = kop(op, dir);
-    bool known = false;
-    for (int v : kVpts) known |= v == vpt;
-    if (!known || vpt > max_vpt(k_op, dt)) return CREDIT_ERR_UNSUPPORTED;
+    if (!instance_exists(k_op, dt, vpt)) return CREDIT_ERR_UNSUPPORTED;
     const void *fn = resident_fn(k_op, dt, vpt);
     if (!fn) return CREDIT_ERR_UNSUPPORTED;
     if (!h) {  // the register model only

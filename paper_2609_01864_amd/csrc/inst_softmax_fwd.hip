@@ -14,10 +14,16 @@ namespace credit {
     CREDIT_R(DT, 1) CREDIT_R(DT, 2) CREDIT_R(DT, 4) CREDIT_R(DT, 8) \
     CREDIT_R(DT, 12) CREDIT_R(DT, 16) CREDIT_R(DT, 24) CREDIT_R(DT, 32)
 
+// slices beyond the register file: 32 vectors in registers, the rest in LDS
+#define CREDIT_RL(DT, V) \
+    if (dt == DT && vpt == V) return (const void *)&k_resident<OP_SOFTMAX_FWD, DT, kRegVptMax, V - kRegVptMax>;
+
 const void *resident_kernel_softmax_fwd(int dt, int vpt) {
     CREDIT_RV(DT_F32)
     CREDIT_RV(DT_BF16)
     CREDIT_RV(DT_FP8)
+    CREDIT_RL(DT_F32, 48) CREDIT_RL(DT_F32, 68)
+    CREDIT_RL(DT_BF16, 48) CREDIT_RL(DT_BF16, 68)
     return nullptr;
 }
 

@@ -53,6 +53,19 @@ constexpr bool byte_out(int op) { return is_quant(op) || op == OP_LNQ_FWD; }  //
 // Register-resident slice sizes: vectors (16 bytes) per thread per tensor.
 constexpr int kVpts[] = {1, 2, 4, 8, 12, 16, 24, 32};
 constexpr int kNumVpts = 8;
+// Slices beyond the register file: 32 vectors per thread in registers plus
+// L = vpt - 32 in LDS (4 KiB per vector x 256 threads): 48 (64 KiB of LDS,
+// two workgroups per CU) and 68 (144 KiB: one workgroup per CU, whose LDS also
+// holds the reduction and exchange buffers; slots in multiples of 4).  Built for
+// the single-input forward operators with FP32 / BF16 rows, whose register
+// slices end at 32 vectors.
+constexpr int kLdsVpts[] = {48, 68};
+constexpr int kRegVptMax = 32;
+constexpr bool lds_capable(int op, int dt) {
+    return (op == OP_SOFTMAX_FWD || op == OP_LN_FWD || op == OP_RMS_FWD) && (dt == DT_F32 || dt == DT_BF16);
+}
+// LDS vectors per thread of a slice bucket (0: registers only).
+constexpr int lds_vpt(int vpt) { return vpt > kRegVptMax ? vpt - kRegVptMax : 0; }
 // Largest instantiated vectors-per-thread for (op, dtype): bounded by the
 // register file (data of one or two tensors, plus FP32 dgamma/dbeta column
 // partials for normalisation backward).

@@ -88,13 +88,26 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef u32x2 u32x2_u __attribute__((aligned(1)));
 typedef unsigned u32_u __attribute__((aligned(1)));
 
+#ifndef CREDIT_LOAD_NT
+#define CREDIT_LOAD_NT 1
+#endif
+#ifndef CREDIT_STORE_NT
+#define CREDIT_STORE_NT 1
+#endif
 template <bool AL> __device__ __forceinline__ u32x4 vload_nt(const char *base, uint32_t off) {
+    if constexpr (!CREDIT_LOAD_NT)
+        return AL ? *(const u32x4 *)(base + off) : *(const u32x4_u *)(base + off);
     if constexpr (AL)
         return __builtin_nontemporal_load((const u32x4 *)(base + off));
     else
         return __builtin_nontemporal_load((const u32x4_u *)(base + off));
 }
 template <bool AL> __device__ __forceinline__ void vstore_nt(char *base, uint32_t off, u32x4 v) {
+    if constexpr (!CREDIT_STORE_NT) {
+        if constexpr (AL) *(u32x4 *)(base + off) = v;
+        else *(u32x4_u *)(base + off) = v;
+        return;
+    }
     if constexpr (AL)
         __builtin_nontemporal_store(v, (u32x4 *)(base + off));
     else
@@ -210,8 +223,17 @@ struct Slice {
     int owner;     // thread that holds it
 };
 
-template <int OP, int DT, int VPT, bool AL, bool FULLS>
-__device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const Slice &sl, float *red, float *xb) {
+// Slots of the slice held in LDS beyond the VPT register slots (the overflow
+// of Eq. (3)'s capacity into LDS): L vectors per thread, stored [L][256] so
+// that each wave writes and reads only its own 64-vector rows.
+template <int L> struct LdsSlice { u32x4 v[L][kBlock]; };
+template <> struct LdsSlice<0> { u32x4 v[1][1]; };
+
+template <int OP, int DT, int VPT, bool AL, bool FULLS, int L>
+__device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const Slice &sl, float *red, float *xb,
+                                         u32x4 *lds) {
+    static_assert(L == 0 || OP == OP_SOFTMAX_FWD || OP == OP_LN_FWD || OP == OP_RMS_FWD,
+                  "LDS slots exist for the single-input forward operators");
     using T = OpTraits<OP>;
     constexpr int EPV = Io<DT>::EPV, B = Io<DT>::BYTES, NCP = T::NCP;
     constexpr int OB = T::BOUT ? 1 : B;  // output element bytes
@@ -232,6 +254,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                                           OP == OP_LN_BWD || OP == OP_RMS_BWD);
     const int rot = ROT ? grp % VPT : 0;
     auto sv = [&](int j) -> int {
+        if (j >= VPT) return j;  // LDS slots keep their order
         const int r = j + rot;
         return r >= VPT ? r - VPT : r;
     };
@@ -243,9 +266,9 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
     // elements this thread holds (for the Chan counts)
     float held = 0.f;
     if (FULLS) {
-        held = (float)(VPT * EPV);
+        held = (float)((VPT + L) * EPV);
     } else {
-        for (int j = 0; j < VPT; ++j) held += ok_of(j) ? (float)EPV : 0.f;
+        for (int j = 0; j < VPT + L; ++j) held += ok_of(j) ? (float)EPV : 0.f;
         if (tail) held += (float)tn;
     }
 
@@ -261,17 +284,6 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
         }
     }
 
-    // The resident slice of the row being processed.  With CREDIT_ROW_PREFETCH
-    // the next row's slot j is loaded into d0[j] / d1[j] as soon as the output
-    // of slot j has been stored, so the next row's loads overlap this row's
-    // stores instead of following all of them.
-#ifndef CREDIT_ROW_PREFETCH
-#define CREDIT_ROW_PREFETCH 0
-#endif
-    constexpr bool PF = CREDIT_ROW_PREFETCH != 0;
-    u32x4 d0[VPT];
-    u32x4 d1[T::TWO ? VPT : 1];
-    bool prefetched = false;  // uniform: d0 / d1 already hold this row's slice
     for (int64_t row = grp; row < a.M; row += a.groups) {
         const char *r0 = (const char *)a.in0 + row * a.ld0 * B;
         const char *r1 = T::TWO ? (const char *)a.in1 + row * a.ld1 * B : nullptr;
@@ -298,33 +310,19 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
         auto pofs = [&](int j) -> uint32_t {
             return (FULLS || ok_of(j)) ? poff + (uint32_t)sv(j) * (kBlock * EPV * 4u) : 0u;
         };
-        // next row of the row group: its slot j is loaded after slot j's last store
-        const int64_t nrow = row + a.groups;
-        const bool pf_next = PF && nrow < a.M && (FULLS || sl.nfv > 0);
-        const char *nb0 = (const char *)a.in0 + nrow * a.ld0 * B + sl.c0 * B;
-        const char *nb1 = T::TWO ? (const char *)a.in1 + nrow * a.ld1 * B + sl.c0 * B : nullptr;
-        auto NEXT = [&](int j) {
-            if (pf_next) {
-                d0[j] = vload_nt<AL>(nb0, doff(j));
-                if constexpr (T::TWO) d1[j] = vload_nt<AL>(nb1, doff(j));
-            }
-        };
         auto ST = [&](int j, u32x4 v) {
             if (FULLS || ok_of(j)) vstore_nt<AL>(bo, toff + (uint32_t)sv(j) * (kBlock * 16u), v);
-            if constexpr (!T::TWOO) NEXT(j);
         };
         auto ST1 = [&](int j, u32x4 v) {
             if (FULLS || ok_of(j)) vstore_nt<AL>(bo1, toff + (uint32_t)sv(j) * (kBlock * 16u), v);
-            NEXT(j);
         };
         auto QST = [&](int j, const unsigned *w) {
             if (FULLS || ok_of(j)) bstore_nt<EPV, AL>(bo, qoff + (uint32_t)sv(j) * (uint32_t)(kBlock * EPV), w);
-            NEXT(j);
         };
         auto PAR = [&](const float *p, int j, float *out) { load_params_v<DT, AL>(p + sl.c0, pofs(j), out); };
-        if (prefetched) {
-            // loaded during the previous row's output pass
-        } else if (FULLS || sl.nfv > 0) {  // uniform: a slice without full vectors issues no vector load
+        u32x4 d0[VPT];
+        u32x4 d1[T::TWO ? VPT : 1];
+        if (FULLS || sl.nfv > 0) {  // uniform: a slice without full vectors issues no vector load
 #pragma unroll
             for (int j = 0; j < VPT; ++j) d0[j] = vload_nt<AL>(b0, doff(j));
             if constexpr (T::TWO) {
@@ -338,6 +336,28 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 if constexpr (T::TWO) d1[j] = u32x4{0u, 0u, 0u, 0u};
             }
         }
+        if constexpr (L > 0) {
+            // the LDS slots: direct global -> LDS loads (16 bytes per lane, the
+            // wave's 64 lanes land in its own row of the slot), in flight with
+            // the register loads; the same masked-slot addressing
+            if (FULLS || sl.nfv > 0) {
+                const int wave = tid >> 6;
+#pragma unroll
+                for (int l = 0; l < L; ++l)
+                    __builtin_amdgcn_global_load_lds((const void *)(b0 + doff(VPT + l)),
+                                                     (__attribute__((address_space(3))) void *)(lds + l * kBlock + wave * 64),
+                                                     16, 0, 0);
+            }
+        }
+        // LDS slot l (slot VPT + l of the slice), zero where masked; valid
+        // once lds_ready() has run in this row
+        auto LD = [&](int l) -> u32x4 {
+            const u32x4 v = lds[l * kBlock + tid];
+            return (FULLS || ok_of(VPT + l)) ? v : u32x4{0u, 0u, 0u, 0u};
+        };
+        auto lds_ready = [&]() {
+            if constexpr (L > 0) __builtin_amdgcn_s_waitcnt(0);
+        };
         u32x4 t0 = {0u, 0u, 0u, 0u}, t1 = {0u, 0u, 0u, 0u};
         if (tail) {
             t0 = load_vec<DT, false>(r0, tcol, tn, false);
@@ -369,8 +389,10 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             constexpr bool EC = ec_regs<OP, DT, VPT>() > 0;
             constexpr bool ECI = DT == DT_F32;
             float ec[EC ? VPT * EPV : 1];
+            static_assert(!(EC && L > 0), "kept exponentials cover register slots only");
             float qmax = -INFINITY;
             fresh();
+            lds_ready();
 #pragma unroll
             for (int j = 0; j < VPT; ++j) {
                 float q[EPV];
@@ -381,6 +403,15 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     qmax = fmaxf(qmax, ok ? q[i] : -INFINITY);
                     if constexpr (EC) ec[j * EPV + i] = q[i];
                 }
+                keep_order(qmax);
+            }
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                float q[EPV];
+                decode<DT>(LD(l), q, 1.f);
+                const bool ok = ok_of(VPT + l);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) qmax = fmaxf(qmax, ok ? q[i] : -INFINITY);
                 keep_order(qmax);
             }
             if (tail) {
@@ -405,6 +436,15 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 if constexpr (ECI)
                     d0[j] = u32x4{__float_as_uint(ev[0]), __float_as_uint(ev[1]), __float_as_uint(ev[2]),
                                   __float_as_uint(ev[3])};
+                keep_order(st[1]);
+            }
+#pragma unroll
+            for (int l = 0; l < L; ++l) {  // LDS slots: the exponentials are not kept
+                float q[EPV];
+                decode<DT>(LD(l), q, 1.f);
+                const bool ok = ok_of(VPT + l);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) st[1] += ok ? fast_exp2(fmaf(q[i], K, -ct)) : 0.f;
                 keep_order(st[1]);
             }
             if (tail) {
@@ -450,6 +490,14 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     ST(j, encode<DT>(y, 1.f));
                 }
             }
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                float q[EPV], y[EPV];
+                decode<DT>(LD(l), q, 1.f);
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, csh)) * omuls;
+                ST(VPT + l, encode<DT>(y, 1.f));
+            }
             if (tail) {
                 float q[EPV], y[EPV];
                 decode<DT>(t0, q, 1.f);
@@ -467,26 +515,32 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             const float xs = FP8 ? a.s0[row] : 1.f;
             float mean_q = 0.f, amul;
             if constexpr (LN) {
-                // one pass of moments about a per-thread shift (its first held
-                // value), turned into (count, mean, M2) and Chan-merged
-                float K = 0.f;
+                // one pass of moments about a per-thread shift Kt (its first
+                // held value), turned into (count, mean, M2) with the mean taken
+                // relative to the row's first element K (common to every
+                // member) and Chan-merged: the merged means are deviations of
+                // the size of the row's spread, not of its offset, so their
+                // roundings stay small; the mean is K + the merged deviation
+                const float K = row_first<DT>(r0);
+                float Kt = 0.f;
                 {
                     float q[EPV];
                     decode<DT>(d0[0], q, 1.f);
                     float qt[EPV];
                     decode<DT>(t0, qt, 1.f);
-                    K = (FULLS || ok_of(0)) ? q[0] : (tail ? qt[0] : 0.f);
+                    Kt = (FULLS || ok_of(0)) ? q[0] : (tail ? qt[0] : K);
                 }
                 float s1 = 0.f, s2 = 0.f;
                 fresh();
+                lds_ready();
 #pragma unroll
-                for (int j = 0; j < VPT; ++j) {
+                for (int j = 0; j < VPT + L; ++j) {
                     float q[EPV];
-                    decode<DT>(d0[j], q, 1.f);
+                    decode<DT>(j < VPT ? d0[j < VPT ? j : 0] : LD(j < VPT ? 0 : j - VPT), q, 1.f);
                     const bool ok = ok_of(j);
 #pragma unroll
                     for (int i = 0; i < EPV; ++i) {
-                        float d = ok ? q[i] - K : 0.f;
+                        float d = ok ? q[i] - Kt : 0.f;
                         s1 += d;
                         s2 = fmaf(d, d, s2);
                     }
@@ -496,7 +550,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     float q[EPV];
                     decode<DT>(t0, q, 1.f);
                     for (int i = 0; i < tn; ++i) {
-                        float d = q[i] - K;
+                        float d = q[i] - Kt;
                         s1 += d;
                         s2 = fmaf(d, d, s2);
                     }
@@ -504,11 +558,11 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 float st[3] = {held, 0.f, 0.f};
                 if (held > 0.f) {
                     const float m = s1 / held;
-                    st[1] = K + m;
+                    st[1] = (Kt - K) + m;
                     st[2] = fmaxf(s2 - s1 * m, 0.f);
                 }
                 row_reduce_chan(st, a, row, 0, c, red, xb, parity);
-                mean_q = st[1];
+                mean_q = K + st[1];
                 const float rstd = rsqrtf(xs * xs * (st[2] * invN) + a.eps);
                 amul = xs * rstd;
                 if (writer) {
@@ -518,10 +572,11 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             } else {
                 float st[1] = {0.f};
                 fresh();
+                lds_ready();
 #pragma unroll
-                for (int j = 0; j < VPT; ++j) {
+                for (int j = 0; j < VPT + L; ++j) {
                     float q[EPV];
-                    decode<DT>(d0[j], q, 1.f);
+                    decode<DT>(j < VPT ? d0[j < VPT ? j : 0] : LD(j < VPT ? 0 : j - VPT), q, 1.f);
 #pragma unroll
                     for (int i = 0; i < EPV; ++i) st[0] = fmaf(q[i], q[i], st[0]);
                     keep_order(st[0]);
@@ -569,7 +624,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             auto out_pass = [&](bool store, float oinv, float &amax) {
                 fresh();
 #pragma unroll
-                for (int jb = 0; jb < VPT; jb += GB) {
+                for (int jb = 0; jb < VPT + L; jb += GB) {
                     // keep the scheduler from hoisting every batch's parameter
                     // loads to the top (that would hold VPT slots of gamma/beta)
                     __builtin_amdgcn_sched_barrier(0);
@@ -583,7 +638,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     for (int u = 0; u < GB; ++u) {
                         const int j = jb + u;
                         float q[EPV], y[EPV];
-                        decode<DT>(d0[j], q, 1.f);
+                        decode<DT>(j < VPT ? d0[j < VPT ? j : 0] : LD(j < VPT ? 0 : j - VPT), q, 1.f);
                         h(q, g[u], LN ? bb[u] : g[u], y);
                         if (store) {
                             if constexpr (QO) {
@@ -713,13 +768,15 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
             float mean = 0.f, rstd;
             if (a.flags & F_RECOMPUTE) {
                 if constexpr (LN) {
-                    // one pass of moments about a per-thread shift, Chan-merged
-                    float K = 0.f;
+                    // moments about a per-thread shift, means relative to the
+                    // row's first element, Chan-merged (as in the forward)
+                    const float K = row_first<DT>(r0) * xs;
+                    float Kt = 0.f;
                     {
                         float x[EPV], xt[EPV];
                         decode<DT>(d0[0], x, xs);
                         decode<DT>(t0, xt, xs);
-                        K = (FULLS || ok_of(0)) ? x[0] : (tail ? xt[0] : 0.f);
+                        Kt = (FULLS || ok_of(0)) ? x[0] : (tail ? xt[0] : K);
                     }
                     float s1 = 0.f, s2 = 0.f;
                     fresh();
@@ -730,7 +787,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                         const bool ok = ok_of(j);
 #pragma unroll
                         for (int i = 0; i < EPV; ++i) {
-                            float d = ok ? x[i] - K : 0.f;
+                            float d = ok ? x[i] - Kt : 0.f;
                             s1 += d;
                             s2 = fmaf(d, d, s2);
                         }
@@ -740,7 +797,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                         float x[EPV];
                         decode<DT>(t0, x, xs);
                         for (int i = 0; i < tn; ++i) {
-                            float d = x[i] - K;
+                            float d = x[i] - Kt;
                             s1 += d;
                             s2 = fmaf(d, d, s2);
                         }
@@ -748,11 +805,11 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     float st[3] = {held, 0.f, 0.f};
                     if (held > 0.f) {
                         const float m = s1 / held;
-                        st[1] = K + m;
+                        st[1] = (Kt - K) + m;
                         st[2] = fmaxf(s2 - s1 * m, 0.f);
                     }
                     row_reduce_chan(st, a, row, 2, c, red, xb, parity);
-                    mean = st[1];
+                    mean = K + st[1];
                     rstd = rsqrtf(st[2] * invN + a.eps);
                 } else {
                     float st[1] = {0.f};
@@ -1230,7 +1287,6 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                 store_vec<DT>(orow1, tcol, tn, false, encode<DT>(gw, 1.f));
             }
         }
-        prefetched = pf_next;
     }
 
     if constexpr (NCP) {
@@ -1249,7 +1305,7 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
     }
 }
 
-template <int OP, int DT, int VPT>
+template <int OP, int DT, int VPT, int L = 0>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(resident_waves<OP, DT, VPT>())))
 void k_resident(RowArgs a) {
     constexpr int EPV = Io<DT>::EPV;
@@ -1263,6 +1319,7 @@ void k_resident(RowArgs a) {
         a.epoch = __hip_atomic_load(a.epoch_ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __shared__ float red[2 * 4 * 6];  // up to six statistics per reduction
     __shared__ float xb[kMaxK * kMaxQ];
+    __shared__ LdsSlice<L> ls;
     int c, grp;
     member_of(a, blockIdx.x, c, grp);
     Slice sl;
@@ -1275,10 +1332,10 @@ void k_resident(RowArgs a) {
     constexpr int AL_ALL = F_ALIGN0 | F_ALIGNO | F_ALIGNP | (OpTraits<OP>::TWO ? F_ALIGN1 : 0) |
                            (OpTraits<OP>::TWOO ? F_ALIGNO1 : 0);
     const bool al = (a.flags & AL_ALL) == AL_ALL;
-    if (al && sl.nval == (int64_t)VPT * kBlock * EPV)
-        row_loop<OP, DT, VPT, true, true>(a, c, grp, sl, red, xb);
+    if (al && sl.nval == (int64_t)(VPT + L) * kBlock * EPV)
+        row_loop<OP, DT, VPT, true, true, L>(a, c, grp, sl, red, xb, &ls.v[0][0]);
     else
-        row_loop<OP, DT, VPT, false, false>(a, c, grp, sl, red, xb);
+        row_loop<OP, DT, VPT, false, false, L>(a, c, grp, sl, red, xb, &ls.v[0][0]);
 }
 
 }  // namespace credit

@@ -155,7 +155,11 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
             float mean = 0.f, rstd = 0.f;
             if (!BWD || (a.flags & F_RECOMPUTE)) {
                 if constexpr (LN) {
-                    // Chan merge of exact per-vector (count, mean, M2).
+                    // Chan merge of exact per-vector (count, mean, M2), the
+                    // means taken relative to the row's first element K so
+                    // that the merged means are deviations of the size of the
+                    // row's spread; mean = K + the merged deviation
+                    const float K = row_first<DT>(r0) * xs;
                     float st[3] = {0.f, 0.f, 0.f};
                     stream_row<DT, BLOCK, U, false>(r0, nullptr, N, al0, al1, [&](int64_t, u32x4 v, u32x4, int nv) {
                         if (nv == 0) return;
@@ -163,18 +167,18 @@ __global__ __launch_bounds__(BLOCK) void k_twopass(RowArgs a) {
                         decode<DT>(v, x, xs);
                         float s = 0.f;
 #pragma unroll
-                        for (int i = 0; i < EPV; ++i) s += x[i];
+                        for (int i = 0; i < EPV; ++i) s += i < nv ? x[i] - K : 0.f;
                         const float n = (float)nv, m = s / n;
                         float m2 = 0.f;
 #pragma unroll
                         for (int i = 0; i < EPV; ++i) {
-                            float d = x[i] - m;
+                            float d = (x[i] - K) - m;
                             if (i < nv) m2 = fmaf(d, d, m2);
                         }
                         chan_merge(st[0], st[1], st[2], n, m, m2);
                     });
                     block_reduce<NW, 3>(st, MergeChan(), red, parity);
-                    mean = st[1];
+                    mean = K + st[1];
                     rstd = rsqrtf(st[2] * invN + a.eps);
                 } else {
                     float st[1] = {0.f};

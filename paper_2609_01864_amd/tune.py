@@ -102,16 +102,17 @@ def collect(h, shapes, path: str, reps: int = 15):
     with open(path, "a") as f:
         for i, s in enumerate(todo):
             legal = legal_classes(h, s)
-            times = {}
+            times, spread = {}, {}
             for c in legal:
-                times[str(c)] = h.time_plan(s["op"], s["dir"], s["dt"], s["M"], s["N"], C.plan_of_class(c), reps,
-                                            True)
+                st = h.time_plan_stats(s["op"], s["dir"], s["dt"], s["M"], s["N"], C.plan_of_class(c), reps, True)
+                times[str(c)] = st["median_us"]
+                spread[str(c)] = {"min": st["min_us"], "p90": st["p90_us"], "mad": st["mad_us"]}
             ctrl = {}
             for k in (1,) + SPLIT_KS:
                 p = C.plan("resident" if k == 1 else "split", k)
                 if k == 1 or h.plan_legal(s["op"], s["dir"], s["dt"], s["M"], s["N"], p):
                     ctrl[str(k)] = h.time_control(s["op"], s["dir"], s["dt"], s["M"], s["N"], k, 7)
-            rec = dict(s, legal=legal, times=times, ctrl=ctrl,
+            rec = dict(s, legal=legal, times=times, spread=spread, ctrl=ctrl,
                        feats=[float(v) for v in C.features(s["op"], s["dir"], s["dt"], s["M"], s["N"])])
             f.write(json.dumps(rec) + "\n")
             f.flush()
@@ -232,15 +233,56 @@ def pick_fixed(r):
     return 0
 
 
+def bytes_rank(c: int) -> int:
+    """Order of the plan classes by the bytes they move per element: the
+    row-resident plan, then split plans by increasing k (exchange traffic
+    grows with k), then the two-pass plan (it rereads the row)."""
+    return NUM_CLASSES if c == 0 else c
+
+
+NUM_CLASSES = C.NUM_PLANS
+
+
+def noise_of(rec, c: int, best: int) -> float:
+    """Timing noise between plan c and the best plan of a record: max(1% of
+    the best median, 2 MAD of either plan)."""
+    t = rec["times"]
+    sp = rec.get("spread", {})
+    mad = max(sp.get(str(c), {}).get("mad", 0.0), sp.get(str(best), {}).get("mad", 0.0))
+    return max(0.01 * t[str(best)], 2.0 * mad)
+
+
+def judge_best(rec) -> int:
+    """The exhaustive judge's plan: the fastest median, except that plans
+    within the timing noise of it count as equally fast and the one moving
+    fewer bytes (then the smaller k) is taken (the library's exhaustive
+    selector applies the same rule)."""
+    times = {int(c): v for c, v in rec["times"].items()}
+    fastest = min(times, key=times.get)
+    tied = [c for c, v in times.items() if v - times[fastest] <= noise_of(rec, c, fastest)]
+    return min(tied, key=bytes_rank)
+
+
 def regret_stats(recs, picks):
-    ratios = []
+    """Raw regret T(pick) / T(fastest) - 1, and noise-aware regret: 0 when
+    the pick is within the timing noise of the fastest plan (max(1%, 2 MAD)),
+    else the raw regret.  Also how often the pick is the judge's plan."""
+    ratios, noisy, judged = [], [], []
     for r, c in zip(recs, picks):
         times = {int(k): v for k, v in r["times"].items()}
-        ratios.append(times[c] / min(times.values()))
-    a = np.array(ratios)
+        fastest = min(times, key=times.get)
+        ratio = times[c] / times[fastest]
+        ratios.append(ratio)
+        noisy.append(1.0 if times[c] - times[fastest] <= noise_of(r, c, fastest) else ratio)
+        judged.append(c == judge_best(r))
+    a, b = np.array(ratios), np.array(noisy)
     return {"geomean": float(np.exp(np.mean(np.log(a)))), "p95": float(np.percentile(a, 95)),
             "max": float(a.max()), "share_within_5pct": float(np.mean(a <= 1.05)),
-            "exact": float(np.mean(a <= 1.0 + 1e-9)), "n": int(a.size)}
+            "exact": float(np.mean(a <= 1.0 + 1e-9)), "n": int(a.size),
+            "noise_aware_geomean": float(np.exp(np.mean(np.log(b)))),
+            "noise_aware_p95": float(np.percentile(b, 95)),
+            "share_within_noise": float(np.mean(b == 1.0)),
+            "share_judge_pick": float(np.mean(judged))}
 
 
 def evaluate(h, recs, copy_gbps: float):

@@ -73,14 +73,24 @@ def test_host_legality_follows_capacity(lib_built):
     from paper_2609_01864_amd import credit as C
 
     L = C.lib()
-    # FP32 forward: one workgroup holds up to 256 threads x 32 vectors x 4 = 32768 elements
+    # FP32 forward: one workgroup holds 256 threads x (32 vectors in registers
+    # + up to 36 in LDS) x 4 = 69632 elements; the geometry reports the bucket
     ok = lambda N, p: L.credit_plan_legal(None, C.SOFTMAX, C.FWD, C.F32, 64, N, ctypes.byref(p)) == C.OK
-    assert ok(32768, C.plan("resident"))
-    assert not ok(32769, C.plan("resident"))
-    assert ok(32769, C.plan("split", 2))
-    assert ok(1 << 20, C.plan("split", 32))
-    assert not ok((1 << 20) + 1, C.plan("split", 32))
+    vpt = lambda N, p: C.plan_geometry(None, C.SOFTMAX, C.FWD, C.F32, 64, N, p)["vpt"]
+    assert ok(32768, C.plan("resident")) and vpt(32768, C.plan("resident")) == 32
+    assert vpt(32769, C.plan("resident")) == 48 and vpt(49153, C.plan("resident")) == 68
+    assert ok(69632, C.plan("resident"))
+    assert not ok(69633, C.plan("resident"))
+    assert ok(69633, C.plan("split", 2))
+    assert ok(69632 * 32, C.plan("split", 32)) and vpt(1 << 20, C.plan("split", 32)) == 32
+    assert not ok(69632 * 32 + 1, C.plan("split", 32))
     assert ok(1 << 24, C.plan("two_pass"))
+    # the LDS buckets exist for the FP32 / BF16 softmax, LayerNorm and RMSNorm
+    # forward only: FP8 rows and the backward operators end at their registers
+    assert L.credit_plan_legal(None, C.LAYERNORM, C.FWD, C.BF16, 8, 65536 + 1,
+                               ctypes.byref(C.plan("resident"))) == C.OK
+    assert L.credit_plan_legal(None, C.LAYERNORM, C.FWD, C.FP8, 8, 65536 + 1,
+                               ctypes.byref(C.plan("resident"))) == C.ERR_UNSUPPORTED
     # malformed plans
     assert L.credit_plan_legal(None, 0, 0, 0, 64, 1024, ctypes.byref(C.plan("split", 3))) == C.ERR_UNSUPPORTED
     assert L.credit_plan_legal(None, 0, 0, 0, 64, 1024, ctypes.byref(C.plan("resident", 2))) == C.ERR_UNSUPPORTED
@@ -95,7 +105,9 @@ def test_geometry_is_persistent_and_xcd_rounded(lib_built):
     from paper_2609_01864_amd import credit as C
 
     g = C.plan_geometry(None, C.RMSNORM, C.FWD, C.F32, 1024, 524288, C.plan("split", 16))
-    assert C.plan_geometry(None, C.RMSNORM, C.FWD, C.F32, 1024, 524288, C.plan("split", 8)) is None
+    assert C.plan_geometry(None, C.RMSNORM, C.FWD, C.F32, 1024, 524288, C.plan("split", 4)) is None
+    g8 = C.plan_geometry(None, C.RMSNORM, C.FWD, C.F32, 1024, 524288, C.plan("split", 8))
+    assert g8["vpt"] == 68 and g8["per_cu"] == 1  # registers plus 144 KiB of LDS
     assert g["block"] == 256 and g["grid"] % 128 == 0  # multiple of 8 * k
     assert g["grid"] // 8 <= 1024
     g1 = C.plan_geometry(None, C.RMSNORM, C.FWD, C.F32, 5, 1000, C.plan("resident"))

@@ -20,7 +20,7 @@ from test_workloads_gpu import WCase, check as wcheck
 
 pytestmark = pytest.mark.gpu
 
-VPTS = (1, 2, 4, 8, 12, 16, 24, 32)
+VPTS = (1, 2, 4, 8, 12, 16, 24, 32, 48, 68)
 BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
 DTN = {"f32": C.F32, "bf16": C.BF16, "fp8": C.FP8}
 # name, (op, direction), I/O dtypes, case family

@@ -20,13 +20,13 @@ import pytest
 from paper_2609_01864_amd import build as B
 from paper_2609_01864_amd import credit as C
 
-VPTS = (1, 2, 4, 8, 12, 16, 24, 32)
+VPTS = (1, 2, 4, 8, 12, 16, 24, 32, 48, 68)
 # (kernel operator index, dtype index) -> public (op, direction)
 KOPS = {0: (C.SOFTMAX, C.FWD), 1: (C.LAYERNORM, C.FWD), 2: (C.RMSNORM, C.FWD), 3: (C.SOFTMAX, C.BWD),
         4: (C.LAYERNORM, C.BWD), 5: (C.RMSNORM, C.BWD), 6: (C.SOFTMAX_LOGITS, C.BWD), 7: (C.QUANT_INT8, C.FWD),
         8: (C.QUANT_FP8, C.FWD), 9: (C.PEARSON, C.BWD), 10: (C.WVAR, C.BWD), 11: (C.LAYERNORM_FP8_OUT, C.FWD)}
 # (kernel operator, dtype, vectors per thread) of the instances with private memory
-PRIVATE = {(0, 0, 16), (0, 0, 24), (0, 1, 16), (0, 1, 24), (1, 2, 12), (4, 0, 4), (4, 0, 8), (4, 1, 1), (4, 1, 2),
+PRIVATE = {(0, 0, 16), (0, 0, 24), (0, 0, 48), (0, 1, 16), (0, 1, 24), (0, 1, 48), (1, 2, 12), (4, 0, 4), (4, 0, 8), (4, 1, 1), (4, 1, 2),
            (4, 1, 4), (4, 2, 1), (4, 2, 2), (5, 1, 2), (5, 2, 2), (5, 2, 4), (6, 2, 1), (6, 2, 2), (6, 2, 4),
            (11, 1, 32)}
 
@@ -39,9 +39,12 @@ def report(lib_built):
         rep = json.load(f)
     out = {}
     for name, r in rep.items():
-        m = re.fullmatch(r"_ZN6credit10k_residentILi(\d+)ELi(\d+)ELi(\d+)EEEvNS_7RowArgsE", name)
+        # k_resident<op, dtype, register vectors, LDS vectors>: keyed by the
+        # slice bucket (register + LDS vectors per thread)
+        m = re.fullmatch(r"_ZN6credit10k_residentILi(\d+)ELi(\d+)ELi(\d+)ELi(\d+)EEEvNS_7RowArgsE", name)
         if m:
-            out[tuple(int(g) for g in m.groups())] = r
+            op, dt, v, lds = (int(g) for g in m.groups())
+            out[(op, dt, v + lds)] = r
     return out
 
 

@@ -1,8 +1,9 @@
-"""GPU parity at the largest rows each register-resident form accepts: a row
-exactly at a split plan's capacity (32 workgroups x 256 threads x the
-largest vectors-per-thread of the operator and dtype) runs every legal plan
-and matches the FP64 oracle; one element more makes every split plan illegal
-and the two-pass kernel takes it, also to the oracle's tolerance."""
+"""GPU parity at the largest rows each resident form accepts: a row exactly at
+a split plan's capacity (32 workgroups x 256 threads x the largest vectors
+per thread of the operator and dtype -- registers, plus LDS for the FP32 /
+BF16 softmax, LayerNorm and RMSNorm forward) runs every legal plan and
+matches the FP64 oracle; one element more makes every split plan illegal and
+the two-pass kernel takes it, also to the oracle's tolerance."""
 import pytest
 
 from paper_2609_01864_amd import credit as C
@@ -12,8 +13,8 @@ from _cases import ALL_PLANS, OPNUM, Case, check_case
 pytestmark = pytest.mark.gpu
 
 # (operator, dtype, elements per 16-byte vector, largest vectors per thread)
-LIMITS = [("layernorm_fwd", "f32", 4, 32), ("softmax_fwd", "bf16", 8, 32), ("rmsnorm_fwd", "fp8", 16, 16),
-          ("softmax_bwd", "f32", 4, 16), ("layernorm_bwd", "bf16", 8, 4)]
+LIMITS = [("layernorm_fwd", "f32", 4, 68), ("softmax_fwd", "bf16", 8, 68), ("rmsnorm_fwd", "f32", 4, 68),
+          ("rmsnorm_fwd", "fp8", 16, 16), ("softmax_bwd", "f32", 4, 16), ("layernorm_bwd", "bf16", 8, 4)]
 
 
 @pytest.mark.parametrize("op,dtype,epv,vmax", LIMITS)

@@ -44,3 +44,22 @@ def test_split_is_stratified_and_deterministic(lib_built):
     tr2, te2 = T.split(list(reversed(recs)))
     assert [T.key_of(r) for r in te] == [T.key_of(r) for r in te2]
     assert len(tr) + len(te) == len(recs) and len(te) == 18 * 4
+
+
+def test_noise_aware_regret_and_judge_tie_break():
+    # plan 2 (split k=2) is 0.5% slower than the two-pass plan: within the 1%
+    # noise floor, so the judge takes the plan moving fewer bytes (split k=2
+    # before two-pass); plan 3 is 3% slower but with MADs of 1%, 2 MAD covers it
+    rec = {"times": {"0": 100.0, "2": 100.5, "3": 103.0, "4": 110.0},
+           "spread": {"0": {"mad": 1.0}, "2": {"mad": 0.1}, "3": {"mad": 1.6}, "4": {"mad": 0.5}}}
+    assert T.judge_best(rec) == 2
+    st = T.regret_stats([rec] * 4, [0, 2, 3, 4])
+    assert math.isclose(st["geomean"], (1.0 * 1.005 * 1.03 * 1.10) ** 0.25)
+    assert math.isclose(st["noise_aware_geomean"], 1.10 ** 0.25)
+    assert st["share_within_noise"] == 0.75 and st["share_judge_pick"] == 0.25
+    # without spread (older records) only the 1% floor applies
+    bare = {"times": {"0": 100.0, "2": 100.5, "3": 103.0}}
+    assert T.judge_best(bare) == 2
+    assert T.regret_stats([bare], [3])["noise_aware_geomean"] == 1.03
+    # ranking by bytes: resident, split by increasing k, two-pass last
+    assert sorted(range(C.NUM_PLANS), key=T.bytes_rank) == [1, 2, 3, 4, 5, 6, 0]
