@@ -483,9 +483,16 @@ typedef enum {
                                          publishing its partials (forces the timeout
                                          path of CREDIT_ERR_TIMEOUT) */
     CREDIT_OPT_MAX_GROUPS = 2,  /* cap on concurrent row groups (0: occupancy bound) */
-    CREDIT_OPT_TEST_SKEW = 3    /* test only: before each exchange, member c of a row
+    CREDIT_OPT_TEST_SKEW = 3,   /* test only: before each exchange, member c of a row
                                    group waits (c * 7 + row) % 13 microseconds, so the
                                    members publish out of step (Sec. III-C) */
+    CREDIT_OPT_ROWS = 4         /* rows per workgroup of LayerNorm / RMSNorm forward
+                                   resident and split plans: 0 = the library's rule,
+                                   1 = one row at a time, 2 or 4 = that many rows at
+                                   once where the slice has at most 8 vectors per
+                                   thread (each gamma / beta vector loaded once per
+                                   2 or 4 rows, one exchange round per row block);
+                                   other values return CREDIT_ERR_INVALID_ARG */
 } credit_option_t;
 credit_status_t credit_set_option(credit_handle_t h, credit_option_t opt, int64_t value);
 
@@ -495,15 +502,18 @@ credit_status_t credit_set_epoch(uint32_t next_epoch);
 
 /* Launch geometry the library would use for a plan: grid size (workgroups),
  * threads per workgroup, per-thread vector count, co-resident workgroups per
- * CU.  Host-only. */
+ * CU, rows per workgroup.  Every output pointer is nullable.  Host-only. */
 credit_status_t credit_plan_geometry(credit_handle_t h, credit_op_t op, credit_dir_t dir,
                                      credit_dtype_t dt, int64_t M, int64_t N,
                                      const credit_plan_t *plan, int32_t *grid, int32_t *block,
-                                     int32_t *vpt, int32_t *per_cu);
+                                     int32_t *vpt, int32_t *per_cu, int32_t *rows);
 
 /* Resources of the row-resident / split-row kernel instance of (op, dir, dt)
  * that holds `vpt` 16-byte vectors per thread per tensor (vpt in
- * {1, 2, 4, 8, 12, 16, 24, 32}, up to the operator's register capacity):
+ * {1, 2, 4, 8, 12, 16, 24, 32}, up to the operator's register capacity, and
+ * 48 and 68 for the FP32 / BF16 forward operators with LDS slices) and
+ * `rows` rows per workgroup (1; 2 or 4 for the multi-row LayerNorm / RMSNorm
+ * forward with vpt <= 8):
  * registers per lane, private (scratch) bytes per lane, workgroups per CU by
  * the occupancy query and by the library's register model, and, for an
  * instance that uses private memory, the workgroups per CU its co-residency
@@ -521,7 +531,8 @@ typedef struct {
     int32_t coresident_per_cu;
 } credit_instance_t;
 credit_status_t credit_instance_info(credit_handle_t h, credit_op_t op, credit_dir_t dir,
-                                     credit_dtype_t dt, int32_t vpt, credit_instance_t *out);
+                                     credit_dtype_t dt, int32_t vpt, int32_t rows,
+                                     credit_instance_t *out);
 
 #ifdef __cplusplus
 }

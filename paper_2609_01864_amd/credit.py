@@ -28,7 +28,7 @@ SOFTMAX_LOGITS, QUANT_INT8, QUANT_FP8, PEARSON, WVAR, LAYERNORM_FP8_OUT = 3, 4, 
 FWD, BWD = 0, 1
 TWO_PASS, ROW_RESIDENT, SPLIT_ROW = 0, 1, 2
 SEL_LEARNED, SEL_ANALYTIC, SEL_EXHAUSTIVE, SEL_FIXED, SEL_PEAK, SEL_LEARNED_TIMED = range(6)
-OPT_SPIN_LIMIT, OPT_TEST_DROP_PUBLISH, OPT_MAX_GROUPS, OPT_TEST_SKEW = range(4)
+OPT_SPIN_LIMIT, OPT_TEST_DROP_PUBLISH, OPT_MAX_GROUPS, OPT_TEST_SKEW, OPT_ROWS = range(5)
 NUM_FEATURES, NUM_PLANS, MLP_HIDDEN = 12, 7, 64
 DTYPE_NAMES = {"f32": F32, "bf16": BF16, "fp8": FP8}
 
@@ -150,8 +150,8 @@ _SIGS = {
     "credit_set_epoch": ([ctypes.c_uint32], _S),
     "credit_probe_primitives": ([_P, _S, ctypes.POINTER(Primitives)], _S),
     "credit_plan_geometry": ([_P, _S, _S, _S, _I64, _I64, _PP, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
-                              ctypes.POINTER(_I32), ctypes.POINTER(_I32)], _S),
-    "credit_instance_info": ([_P, _S, _S, _S, _I32, ctypes.POINTER(Instance)], _S),
+                              ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], _S),
+    "credit_instance_info": ([_P, _S, _S, _S, _I32, _I32, ctypes.POINTER(Instance)], _S),
 }
 
 
@@ -226,23 +226,24 @@ def model_delta(handle, op, direction, dtype, M, N, t_base_us, t_ctrl_us):
 
 
 def plan_geometry(handle, op, direction, dtype, M, N, p: Plan):
-    g, b, v, o = _I32(), _I32(), _I32(), _I32()
+    g, b, v, o, r = _I32(), _I32(), _I32(), _I32(), _I32()
     h = handle.ptr if handle is not None else None
     s = lib().credit_plan_geometry(h, op, direction, dtype, M, N, ctypes.byref(p), ctypes.byref(g), ctypes.byref(b),
-                                   ctypes.byref(v), ctypes.byref(o))
+                                   ctypes.byref(v), ctypes.byref(o), ctypes.byref(r))
     if s == ERR_UNSUPPORTED:
         return None
     check(s, "credit_plan_geometry")
-    return {"grid": g.value, "block": b.value, "vpt": v.value, "per_cu": o.value}
+    return {"grid": g.value, "block": b.value, "vpt": v.value, "per_cu": o.value, "rows": r.value}
 
 
-def instance_info(handle, op, direction, dtype, vpt: int):
+def instance_info(handle, op, direction, dtype, vpt: int, rows: int = 1):
     """Registers, private bytes per lane, workgroups per CU (occupancy query,
     register model, verified co-residency; -1 when not probed) of one
-    row-resident / split-row instance, or None if it does not exist."""
+    row-resident / split-row instance (rows > 1: the multi-row norm forward),
+    or None if it does not exist."""
     out = Instance()
     h = handle.ptr if handle is not None else None
-    s = lib().credit_instance_info(h, op, direction, dtype, int(vpt), ctypes.byref(out))
+    s = lib().credit_instance_info(h, op, direction, dtype, int(vpt), int(rows), ctypes.byref(out))
     if s == ERR_UNSUPPORTED:
         return None
     check(s, "credit_instance_info")

@@ -21,6 +21,7 @@
 namespace credit {
 const void *resident_kernel_softmax_fwd(int, int);
 const void *resident_kernel_ln_fwd(int, int);
+const void *multirow_kernel(int, int, int, int);
 const void *resident_kernel_rms_fwd(int, int);
 const void *resident_kernel_softmax_bwd(int, int);
 const void *resident_kernel_ln_bwd(int, int);
@@ -138,6 +139,18 @@ const void *resident_fn(int k_op, int dt, int vpt) {
     }
     return nullptr;
 }
+// The row-resident / split-row instance of (op, dtype, vectors per thread)
+// that holds `rows` rows per workgroup (1: the single-row kernel).
+const void *instance_fn(int k_op, int dt, int vpt, int rows) {
+    if (rows <= 1) return resident_fn(k_op, dt, vpt);
+    if (!multirow_capable(k_op) || !multirow_fits(dt, vpt, rows)) return nullptr;
+    return multirow_kernel(k_op, dt, vpt, rows);
+}
+bool multirow_exists(int k_op, int dt, int vpt, int rows) {
+    bool r = false;
+    for (int x : kMrRows) r |= x == rows;
+    return r && multirow_capable(k_op) && instance_exists(k_op, dt, vpt) && multirow_fits(dt, vpt, rows);
+}
 const void *twopass_fn(int k_op, int dt, int block) {
     switch (k_op) {
     case OP_SOFTMAX_FWD: return twopass_kernel_softmax_fwd(dt, block);
@@ -176,6 +189,13 @@ int model_waves(int k_op, int dt, int vpt) {
     if (int ov = wave_override(k_op, dt, vpt)) return ov;
     return std::max(1, std::min(8, w));
 }
+// The same for the multi-row forward kernel (rows > 1).
+int model_waves(int k_op, int dt, int vpt, int rows) {
+    if (rows <= 1) return model_waves(k_op, dt, vpt);
+    const int data = rows * vpt * 4;
+    const int work = 80 + (dt == CREDIT_FP8_E4M3 ? (k_op == OP_LN_FWD ? 64 : 32) : 0) + 4 * rows;
+    return std::max(1, std::min(8, 512 / (data + work)));
+}
 
 // Number of exchange stages of a row (for the control kernel and the model).
 int stages_of(int k_op, int dt, bool recompute) {
@@ -189,6 +209,7 @@ struct Launch {
     int variant = 0, k = 1;
     const void *fn = nullptr;
     int grid = 0, block = 0, vpt = 0, groups = 0, per_cu = 0;
+    int rows = 1;  // rows per workgroup (multi-row norm forward when > 1)
     size_t shmem = 0;
     int64_t chunk = 0;
     bool xcd = false;
@@ -232,6 +253,7 @@ struct credit_handle_s {
         double lds_read_bpc = kSlotRate;  // bytes per cycle of one workgroup's LDS reads
     } cal;
     int64_t max_groups = 0;
+    int rows_opt = 0;  // rows per workgroup of norm-forward plans (0: the library's rule)
     // private memory (bytes per lane) of the row-resident / split-row
     // instances, and for those that use it the workgroups per CU verified
     // co-resident at handle creation (0: none)
@@ -278,6 +300,28 @@ size_t colsum_layout(Launch &L, int ncp, int64_t N, size_t off) {
     if (!L.slices) return off;
     L.off_colsum = off;
     return align256(off + (size_t)L.slices * ncp * N * 4);
+}
+
+// Rows per workgroup of a resident / split plan (Launch::rows): the option
+// when set, else the library's rule, from back-to-back timings on MI355X
+// (M = 1024..16384): two rows per workgroup where one exchange round per two
+// rows pays -- RMSNorm (every dtype) and BF16 LayerNorm at k >= 16 (RMSNorm
+// FP32 N = 131072 at k = 16: 199 -> 188 us, BF16 N = 262144 at k = 32:
+// 1206 -> 871 us) -- and for row-resident plans with enough rows to fill every
+// row-group slot twice over (FP32 LayerNorm 16384 x 4096: 106 -> 99 us).
+// Elsewhere one row: with fewer rows than slots two-row blocks leave
+// workgroups idle, and FP32 / FP8 LayerNorm at k = 16 lost 3% / 16% (FP8
+// keeps no normalised row across its amax stage here, so it reads gamma and
+// beta twice per row block).
+int rows_for(credit_handle_t h, int k_op, int dt, int vpt, int64_t M, int k, int64_t slots1) {
+    int want = h ? h->rows_opt : 0;
+    if (want == 0) {
+        want = 1;
+        if (k >= 16 && (k_op == OP_RMS_FWD || (k_op == OP_LN_FWD && dt == CREDIT_BF16))) want = 2;
+        if (k == 1 && dt != CREDIT_FP8_E4M3 && M >= 2 * slots1) want = 2;
+    }
+    if (want <= 1 || M < 2 || !multirow_exists(k_op, dt, vpt, want)) return 1;
+    return want;
 }
 
 // Resolves a plan into launch geometry and workspace layout.  Returns
@@ -338,9 +382,15 @@ credit_status_t resolve(credit_handle_t h, int k_op, int dt, int64_t M, int64_t 
     L.vpt = vpt;
     L.chunk = cvec * epv;
     L.block = kBlockThreads;
-    L.fn = resident_fn(k_op, dt, vpt);
+    {
+        // row-group slots of the one-row kernel (for the rows rule)
+        const void *f1 = resident_fn(k_op, dt, vpt);
+        const int occ1 = !f1 ? 0 : h ? occupancy(h, f1, kBlockThreads, 0) : model_waves(k_op, dt, vpt);
+        L.rows = rows_for(h, k_op, dt, vpt, M, k, (int64_t)std::max(occ1, 1) * cus / k);
+    }
+    L.fn = instance_fn(k_op, dt, vpt, L.rows);
     if (!L.fn) return CREDIT_ERR_UNSUPPORTED;
-    int occ = h ? occupancy(h, L.fn, L.block, 0) : model_waves(k_op, dt, vpt);
+    int occ = h ? occupancy(h, L.fn, L.block, 0) : model_waves(k_op, dt, vpt, L.rows);
     if (occ <= 0) return h ? CREDIT_ERR_HIP : CREDIT_ERR_UNSUPPORTED;
     if (h && k > 1) {
         // an instance that uses private memory runs split plans only at the
@@ -355,7 +405,8 @@ credit_status_t resolve(credit_handle_t h, int k_op, int dt, int64_t M, int64_t 
     int64_t gmax = cap / k;
     if (h && h->max_groups > 0) gmax = std::min<int64_t>(gmax, h->max_groups);
     if (gmax < 1) return CREDIT_ERR_UNSUPPORTED;  // k members cannot be co-resident
-    int64_t groups = std::min<int64_t>(std::max<int64_t>(M, 1), gmax);
+    const int64_t blocks = (M + L.rows - 1) / L.rows;  // row blocks of L.rows rows
+    int64_t groups = std::min<int64_t>(std::max<int64_t>(blocks, 1), gmax);
     if (groups >= 8) {  // XCD-aware member mapping needs grid % 8 == 0
         groups = groups / 8 * 8;
         L.xcd = true;
@@ -365,7 +416,7 @@ credit_status_t resolve(credit_handle_t h, int k_op, int dt, int64_t M, int64_t 
     size_t off = 256;
     if (k > 1) {
         L.off_slots = off;
-        off = align256(off + (size_t)M * kMaxStages * k * q_of(k_op) * 8);
+        off = align256(off + (size_t)blocks * kMaxStages * k * q_of(k_op) * L.rows * 8);
     }
     if (ncp) {
         L.parts = L.groups;
@@ -459,7 +510,7 @@ credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void 
     a.in0 = c.in0; a.in1 = c.in1; a.out = c.out; a.out1 = c.out1;
     a.ld0 = c.ld0; a.ld1 = c.ld1; a.ldo = c.ldo; a.ldo1 = c.ldo1;
     a.rowg = c.rowg;
-    a.qs = q_of(c.k_op);
+    a.qs = q_of(c.k_op) * L.rows;
     a.s0 = c.s0; a.s1 = c.s1; a.so = c.so;
     a.gamma = c.gamma; a.beta = c.beta;
     a.mean_in = c.mean_in; a.rstd_in = c.rstd_in;
@@ -653,7 +704,9 @@ void model_delta(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, doub
             out[i] = -INFINITY;
             continue;
         }
-        const int64_t W = (M + L.groups - 1) / L.groups;  // waves of row groups (Eq. (8))
+        // waves of row groups (Eq. (8)); a workgroup of L.rows rows exchanges
+        // once per row block, with L.rows times the statistics per round
+        const int64_t W = ((M + L.rows - 1) / L.rows + L.groups - 1) / L.groups;
         const double clock = h && h->cal.probed ? h->cal.clock_hz : kClockHz;
         const double slot_bpc = h && h->cal.probed ? h->cal.slot_bpc : kSlotRate;
         const double lds_bpc = h && h->cal.probed ? h->cal.lds_read_bpc : kSlotRate;
@@ -663,7 +716,7 @@ void model_delta(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, doub
         const int passes = k_op == OP_SOFTMAX_FWD ? 3 : 2;
         const double t_replay = (double)W * passes * lds_vpt(L.vpt) * kBlockThreads * 16.0 / (lds_bpc * clock) * 1e6;
         const double t_deposit = 0.0;  // the deposit is the load itself (direct loads into LDS too)
-        const double t_x = kSlotBytes * W * (L.k - 1) * sumq / (clock * slot_bpc) * 1e6;
+        const double t_x = kSlotBytes * W * (L.k - 1) * sumq * L.rows / (clock * slot_bpc) * 1e6;
         out[i] = (float)(t_save - t_ctrl_us[i] - t_replay - t_deposit - t_x);
     }
 }
@@ -853,7 +906,8 @@ credit_status_t time_control(credit_handle_t h, int k_op, int dt, int64_t M, int
     h->prepared = std::make_tuple(-1, -1, (int64_t)-1, (int64_t)-1);  // may overlap prepared inputs
     RowArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.M = M; a.N = N; a.k = L.k; a.groups = L.groups;
+    a.M = (M + L.rows - 1) / L.rows;  // one exchange round per row block
+    a.N = N; a.k = L.k; a.groups = L.groups;
     a.qs = q_of(k_op);
     a.slots = (unsigned long long *)(ws + L.off_slots);
     a.errflag = h->errflag;
@@ -1143,9 +1197,11 @@ credit_status_t verify_coresidency(credit_handle_t h) {
     for (int k_op = 0; k_op < OP_COUNT; ++k_op) {
         for (int dt = CREDIT_F32; dt <= CREDIT_FP8_E4M3; ++dt) {
             if (!dt_ok(k_op, dt)) continue;
-            for (int vpt : kAllVpts) {
+            for (int vr = 0; vr < (int)(std::size(kAllVpts) * 3); ++vr) {
+                const int vpt = kAllVpts[vr / 3], rows = vr % 3 == 0 ? 1 : kMrRows[vr % 3 - 1];
                 if (!instance_exists(k_op, dt, vpt)) continue;
-                const void *fn = resident_fn(k_op, dt, vpt);
+                if (rows > 1 && !multirow_exists(k_op, dt, vpt, rows)) continue;
+                const void *fn = instance_fn(k_op, dt, vpt, rows);
                 if (!fn) continue;
                 hipFuncAttributes at;
                 if (hipFuncGetAttributes(&at, fn) != hipSuccess) return CREDIT_ERR_HIP;
@@ -1521,7 +1577,7 @@ credit_status_t credit_plan_legal(credit_handle_t h, credit_op_t op, credit_dir_
 
 credit_status_t credit_plan_geometry(credit_handle_t h, credit_op_t op, credit_dir_t dir, credit_dtype_t dt,
                                      int64_t M, int64_t N, const credit_plan_t *plan, int32_t *grid, int32_t *block,
-                                     int32_t *vpt, int32_t *per_cu) {
+                                     int32_t *vpt, int32_t *per_cu, int32_t *rows) {
     if (!plan || !valid_enum(op, dir, dt) || M < 0 || N <= 0) return CREDIT_ERR_INVALID_ARG;
     Launch L;
     credit_status_t st;
@@ -1536,6 +1592,7 @@ credit_status_t credit_plan_geometry(credit_handle_t h, credit_op_t op, credit_d
     if (block) *block = L.block;
     if (vpt) *vpt = L.vpt;
     if (per_cu) *per_cu = L.per_cu;
+    if (rows) *rows = L.rows;
     return CREDIT_OK;
 }
 
@@ -2132,15 +2189,16 @@ credit_status_t credit_load_model(credit_handle_t h, const char *path) {
 }
 
 credit_status_t credit_instance_info(credit_handle_t h, credit_op_t op, credit_dir_t dir, credit_dtype_t dt,
-                                     int32_t vpt, credit_instance_t *out) {
-    if (!out || !valid_enum(op, dir, dt)) return CREDIT_ERR_INVALID_ARG;
+                                     int32_t vpt, int32_t rows, credit_instance_t *out) {
+    if (!out || !valid_enum(op, dir, dt) || rows < 1) return CREDIT_ERR_INVALID_ARG;
     const int k_op = kop(op, dir);
     if (!instance_exists(k_op, dt, vpt)) return CREDIT_ERR_UNSUPPORTED;
-    const void *fn = resident_fn(k_op, dt, vpt);
+    if (rows > 1 && !multirow_exists(k_op, dt, vpt, rows)) return CREDIT_ERR_UNSUPPORTED;
+    const void *fn = instance_fn(k_op, dt, vpt, rows);
     if (!fn) return CREDIT_ERR_UNSUPPORTED;
     if (!h) {  // the register model only
         out->registers = out->private_bytes = out->per_cu = out->coresident_per_cu = -1;
-        out->model_per_cu = model_waves(k_op, dt, vpt);
+        out->model_per_cu = model_waves(k_op, dt, vpt, rows);
         return CREDIT_OK;
     }
     std::lock_guard<std::recursive_mutex> g(h->lock);
@@ -2149,7 +2207,7 @@ credit_status_t credit_instance_info(credit_handle_t h, credit_op_t op, credit_d
     out->registers = at.numRegs;
     out->private_bytes = (int32_t)at.localSizeBytes;
     out->per_cu = occupancy(h, fn, kBlockThreads, 0);
-    out->model_per_cu = model_waves(k_op, dt, vpt);
+    out->model_per_cu = model_waves(k_op, dt, vpt, rows);
     auto it = h->coresident.find(fn);
     out->coresident_per_cu = it == h->coresident.end() ? -1 : it->second;
     return CREDIT_OK;
@@ -2170,6 +2228,13 @@ credit_status_t credit_set_option(credit_handle_t h, credit_option_t opt, int64_
         h->max_groups = value;
         h->plan_cache.clear();
         return CREDIT_OK;
+    case CREDIT_OPT_ROWS: {
+        bool ok = value == 0 || value == 1;
+        for (int r : kMrRows) ok |= value == r;
+        if (!ok) return CREDIT_ERR_INVALID_ARG;
+        h->rows_opt = (int)value;
+        return CREDIT_OK;
+    }
     }
     return CREDIT_ERR_INVALID_ARG;
 }

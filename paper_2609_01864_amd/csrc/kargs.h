@@ -66,6 +66,19 @@ constexpr bool lds_capable(int op, int dt) {
 }
 // LDS vectors per thread of a slice bucket (0: registers only).
 constexpr int lds_vpt(int vpt) { return vpt > kRegVptMax ? vpt - kRegVptMax : 0; }
+// Rows per workgroup of the multi-row LayerNorm / RMSNorm forward: a
+// workgroup holds the same slice of R rows at once (R x VPT vectors per
+// thread), so each gamma / beta vector is loaded once per R rows and one
+// exchange round carries the statistics of all R rows.  Built for slices of
+// up to kMrVptMax vectors per thread.
+constexpr int kMrRows[] = {2, 4};
+constexpr int kMrVptMax = 8;
+constexpr bool multirow_capable(int op) { return op == OP_LN_FWD || op == OP_RMS_FWD; }
+// Instances built: FP8 rows decode 16 values per vector, so FP8 holds at most
+// 8 vectors per thread over its R rows (beyond that the registers spill).
+constexpr bool multirow_fits(int dt, int vpt, int rows) {
+    return vpt <= kMrVptMax && (dt != DT_FP8 || vpt * rows <= 8);
+}
 // Largest instantiated vectors-per-thread for (op, dtype): bounded by the
 // register file (data of one or two tensors, plus FP32 dgamma/dbeta column
 // partials for normalisation backward).

@@ -319,7 +319,17 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
         auto QST = [&](int j, const unsigned *w) {
             if (FULLS || ok_of(j)) bstore_nt<EPV, AL>(bo, qoff + (uint32_t)sv(j) * (uint32_t)(kBlock * EPV), w);
         };
-        auto PAR = [&](const float *p, int j, float *out) { load_params_v<DT, AL>(p + sl.c0, pofs(j), out); };
+        // a slice without full vectors (only a trailing partial one, or none)
+        // has every slot masked and reads no parameter vector: sl.c0 may lie
+        // at or past N there
+        auto PAR = [&](const float *p, int j, float *out) {
+            if (FULLS || sl.nfv > 0) {
+                load_params_v<DT, AL>(p + sl.c0, pofs(j), out);
+            } else {
+#pragma unroll
+                for (int i = 0; i < EPV; ++i) out[i] = 0.f;
+            }
+        };
         u32x4 d0[VPT];
         u32x4 d1[T::TWO ? VPT : 1];
         if (FULLS || sl.nfv > 0) {  // uniform: a slice without full vectors issues no vector load

@@ -138,14 +138,17 @@ def test_library_model_delta_matches_oracle(lib_built, op, d, M, N):
             continue
         groups = geo["grid"] // k
         # the library's groups come from the occupancy bound and XCD rounding;
-        # the model itself is Eq. (9) with W = ceil(M / groups); slices held
-        # partly in LDS replay from it once per pass after the load (softmax
-        # 3, norms 2) at the uncalibrated rate of 64 bytes per cycle
-        W = math.ceil(M / groups)
+        # the model itself is Eq. (9) with W = ceil(M / groups) waves, counted
+        # in blocks of R rows where a workgroup holds R rows (one exchange
+        # round per block carrying R rows' statistics); slices held partly in
+        # LDS replay from it once per pass after the load (softmax 3, norms 2)
+        # at the uncalibrated rate of 64 bytes per cycle
+        R = geo["rows"]
+        W = math.ceil(math.ceil(M / R) / groups)
         lds = max(0, geo["vpt"] - 32) * 256 * 16
         replay = W * (3 if op == 0 else 2) * lds / (64.0 * 2.4e9) * 1e6
         ref = cm.delta_t(tb * w.b_reread / w.b_base, ctrl[i], replay, 0.0,
-                         8.0 * W * (k - 1) * sum(list(w.q)[: w.stages]) / (2.4e9 * 64.0) * 1e6)
+                         8.0 * W * (k - 1) * sum(list(w.q)[: w.stages]) * R / (2.4e9 * 64.0) * 1e6)
         assert math.isclose(got[i], ref, rel_tol=1e-5, abs_tol=1e-4), (k, got[i], ref)
 
 

@@ -1,8 +1,9 @@
 """The compiler's resource report of every kernel instance (written by the
 build from hipcc's kernel-resource-usage remarks), checked on the CPU:
 
-* every row-resident / split-row instance the library dispatches to is in the
-  report (registers, private bytes per lane, waves per SIMD);
+* every row-resident / split-row instance the library dispatches to, the
+  multi-row LayerNorm / RMSNorm forward included, is in the report
+  (registers, private bytes per lane, waves per SIMD);
 * the library's register model, which sizes the persistent grid where no
   device can be asked, never promises more workgroups per CU than the
   compiled code allows;
@@ -25,10 +26,12 @@ VPTS = (1, 2, 4, 8, 12, 16, 24, 32, 48, 68)
 KOPS = {0: (C.SOFTMAX, C.FWD), 1: (C.LAYERNORM, C.FWD), 2: (C.RMSNORM, C.FWD), 3: (C.SOFTMAX, C.BWD),
         4: (C.LAYERNORM, C.BWD), 5: (C.RMSNORM, C.BWD), 6: (C.SOFTMAX_LOGITS, C.BWD), 7: (C.QUANT_INT8, C.FWD),
         8: (C.QUANT_FP8, C.FWD), 9: (C.PEARSON, C.BWD), 10: (C.WVAR, C.BWD), 11: (C.LAYERNORM_FP8_OUT, C.FWD)}
-# (kernel operator, dtype, vectors per thread) of the instances with private memory
-PRIVATE = {(0, 0, 16), (0, 0, 24), (0, 0, 48), (0, 1, 16), (0, 1, 24), (0, 1, 48), (1, 2, 12), (4, 0, 4), (4, 0, 8), (4, 1, 1), (4, 1, 2),
-           (4, 1, 4), (4, 2, 1), (4, 2, 2), (5, 1, 2), (5, 2, 2), (5, 2, 4), (6, 2, 1), (6, 2, 2), (6, 2, 4),
-           (11, 1, 32)}
+ROWS = (1, 2, 4)
+# (kernel operator, dtype, vectors per thread, rows per workgroup) of the
+# instances with private memory
+PRIVATE = {(0, 0, 16, 1), (0, 0, 24, 1), (0, 0, 48, 1), (0, 1, 16, 1), (0, 1, 24, 1), (0, 1, 48, 1), (1, 2, 12, 1),
+           (4, 0, 4, 1), (4, 0, 8, 1), (4, 1, 1, 1), (4, 1, 2, 1), (4, 1, 4, 1), (4, 2, 1, 1), (4, 2, 2, 1),
+           (5, 1, 2, 1), (5, 2, 2, 1), (5, 2, 4, 1), (6, 2, 1, 1), (6, 2, 2, 1), (6, 2, 4, 1), (11, 1, 32, 1)}
 
 
 @pytest.fixture(scope="module")
@@ -44,7 +47,12 @@ def report(lib_built):
         m = re.fullmatch(r"_ZN6credit10k_residentILi(\d+)ELi(\d+)ELi(\d+)ELi(\d+)EEEvNS_7RowArgsE", name)
         if m:
             op, dt, v, lds = (int(g) for g in m.groups())
-            out[(op, dt, v + lds)] = r
+            out[(op, dt, v + lds, 1)] = r
+        # k_multirow<op, dtype, vectors, rows>
+        m = re.fullmatch(r"_ZN6credit10k_multirowILi(\d+)ELi(\d+)ELi(\d+)ELi(\d+)EEEvNS_7RowArgsE", name)
+        if m:
+            op, dt, v, rows = (int(g) for g in m.groups())
+            out[(op, dt, v, rows)] = r
     return out
 
 
@@ -52,12 +60,13 @@ def _dispatched():
     for kop, (o, d) in KOPS.items():
         for dt in (C.F32, C.BF16, C.FP8):
             for v in VPTS:
-                try:
-                    info = C.instance_info(None, o, d, dt, v)
-                except C.CreditError:  # no such (operator, dtype)
-                    continue
-                if info is not None:
-                    yield (kop, dt, v), info
+                for rows in ROWS:
+                    try:
+                        info = C.instance_info(None, o, d, dt, v, rows)
+                    except C.CreditError:  # no such (operator, dtype)
+                        continue
+                    if info is not None:
+                        yield (kop, dt, v, rows), info
 
 
 def test_every_dispatched_instance_is_reported(report):
@@ -67,7 +76,7 @@ def test_every_dispatched_instance_is_reported(report):
         r = report[key]
         assert {"vgprs", "scratch_bytes", "waves_per_simd"} <= set(r), key
         seen += 1
-    assert seen == len(report) > 150
+    assert seen == len(report) > 190
 
 
 def test_register_model_is_a_lower_bound(report):
