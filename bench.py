@@ -111,7 +111,10 @@ def kernel_symbol(C, h, op_num, dt_num, M, N, p):
     kop = op_num
     if p.variant == C.TWO_PASS:
         return f"void credit::k_twopass<{kop}, {dt_num}, {g['block']}, 4>", g["grid"] * g["block"]
-    return f"void credit::k_resident<{kop}, {dt_num}, {g['vpt']}>", g["grid"] * g["block"]
+    if g["rows"] > 1:  # the multi-row norm forward
+        return f"void credit::k_multirow<{kop}, {dt_num}, {g['vpt']}, {g['rows']}>", g["grid"] * g["block"]
+    reg = min(g["vpt"], 32)  # slices past 32 vectors per thread keep the rest in LDS
+    return f"void credit::k_resident<{kop}, {dt_num}, {reg}, {g['vpt'] - reg}>", g["grid"] * g["block"]
 
 
 def precision_inputs(M, N, seed, dev):
@@ -226,6 +229,68 @@ def forms(C, h):
                               "unfused_us": round(tl + tq, 1), "speedup": round((tl + tq) / tf, 3)})
         log(f"fusion N={N}: {out['fusion'][-1]}")
     return out
+
+
+def single(C, h, args):
+    """One forward workload alone (rows as the precision workload draws them:
+    3 N(0,1) with 1% at +-40), `warmup` untimed and `steps` timed launches
+    between HIP events on the launch stream, one 1 GiB copy launch first (the
+    traffic counters' calibration).  Returns the JSON the counter summaries
+    read: the launch's kernel, grid, average duration and algorithmic bytes."""
+    import torch
+
+    op_name, dn, M, N = args.single.split(":")
+    M, N = int(M), int(N)
+    op = {"softmax_fwd": C.SOFTMAX, "layernorm_fwd": C.LAYERNORM, "rmsnorm_fwd": C.RMSNORM}[op_name]
+    dnum = {"f32": C.F32, "bf16": C.BF16, "fp8": C.FP8}[dn]
+    dev = torch.device("cuda:0")
+    x, xs = precision_inputs(M, N, seed=2 + N, dev=dev)[dn]
+    g = torch.rand(N, device=dev) + 0.5
+    b = 0.1 * torch.randn(N, device=dev)
+    y = torch.empty_like(x)
+    ys = torch.empty(M, device=dev) if dn == "fp8" else None
+    if args.plan:
+        var, k = args.plan.split(":")
+        p = C.plan(var, int(k))
+    else:
+        p, _ = h.select(op, C.FWD, dnum, M, N)
+
+    def call():
+        if op == C.SOFTMAX:
+            C.softmax_fwd(x, xs, p=p, out=y, out_scale=ys, h=h)
+        elif op == C.LAYERNORM:
+            C.layernorm_fwd(x, g, b, EPS, xs, p=p, out=y, h=h)
+        else:
+            C.rmsnorm_fwd(x, g, EPS, xs, p=p, out=y, h=h)
+
+    h.copy_bandwidth(1 << 30, 1)
+    for _ in range(max(args.warmup, 1)):
+        call()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream(dev)
+    ev = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        call()
+        e1.record(st)
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    assert h.check_errors() == C.OK
+    us = 1e3 * sum(a.elapsed_time(c) for a, c in ev) / len(ev)
+    e = {C.F32: 4, C.BF16: 2, C.FP8: 1}[dnum]
+    # rows in and out, FP8 row scales in and out, gamma / beta once, statistics out
+    nb = M * N * e * 2 + (M * 8 if dn == "fp8" else 0)
+    nb += {C.SOFTMAX: 0, C.LAYERNORM: N * 8 + M * 8, C.RMSNORM: N * 4 + M * 4}[op]
+    sym, grid = kernel_symbol(C, h, op, dnum, M, N, p)
+    key = f"{op_name}:{dn}:M={M}:N={N}:plan={int(p.variant)},{int(p.k)}"
+    return {"metric": "single-workload launch sequence", "value": round(nb / (us * 1e3), 1), "unit": "GB/s",
+            "steps": args.steps, "warmup": args.warmup, "data": "synthetic", "dtype": dn,
+            "config": {"workload": key}, "source_hash": source_hash(), "copy_kernel_bytes": 1 << 30,
+            "roofline": {"bound": "hbm", "kernel": key, "kernel_symbol": sym, "grid_threads": grid,
+                         "avg_launch_us": round(us, 2), "algorithmic_bytes_per_launch": nb,
+                         "elements_per_launch": M * N, "achieved": round(nb / (us * 1e3), 1),
+                         "peak": PEAK_GBPS, "unit": "GB/s", "frac": round(nb / (us * 1e3) / PEAK_GBPS, 4)}}
 
 
 SUITE = (("layernorm_bwd", "LAYERNORM", "BWD", 2048), ("wvar_bwd", "WVAR", "BWD", 4096),
@@ -406,6 +471,11 @@ def main():
     ap.add_argument("--traffic-plans", action="store_true",
                     help="only the launch sequence of every variant's traffic on the bandwidth workload "
                          "(run under rocprofv3 --pmc)")
+    ap.add_argument("--single", default=None, metavar="OP:DTYPE:M:N",
+                    help="only one forward workload (softmax_fwd | layernorm_fwd | rmsnorm_fwd, f32 | bf16 | fp8) "
+                         "with the precision workload's rows, timed alone: the launch sequence a counter "
+                         "profile of that kernel runs under")
+    ap.add_argument("--plan", default=None, help="--single: plan as variant:k (default: the selector's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the row kernels shard over rows with no communication, "
@@ -431,6 +501,9 @@ def main():
         return
     if args.traffic_plans:
         print(json.dumps(traffic_plans(C, h)), flush=True)
+        return
+    if args.single:
+        print(json.dumps(single(C, h, args)), flush=True)
         return
 
     # ---------------------------------------------------------------- inputs
@@ -517,7 +590,8 @@ def main():
                               "gbps": round(gb, 1), "frac": round(gb / PEAK_GBPS, 4),
                               # launch shape: workgroups, co-resident workgroups per CU
                               # (runtime occupancy) and 16-byte vectors per thread
-                              "geometry": {"grid": g["grid"], "per_cu": g["per_cu"], "vpt": g["vpt"]}})
+                              "geometry": {"grid": g["grid"], "per_cu": g["per_cu"], "vpt": g["vpt"],
+                                           "rows": g["rows"]}})
     dom = max(per_shape, key=lambda r: r["us"])
     dom_key = f"{dom['op']}:N={dom['N']}:plan={dom['plan'][0]},{dom['plan'][1]}"
     sym, grid_threads = kernel_symbol(C, h, opnum[dom["op"]], C.F32, M_ROWS, dom["N"], picks[(dom["op"], dom["N"])][0])

@@ -430,14 +430,21 @@ credit_status_t credit_probe_primitives(credit_handle_t h, int reps, credit_prim
 /* Plan of class c in [0, CREDIT_NUM_PLANS). */
 credit_status_t credit_plan_of_class(int32_t c, credit_plan_t *out);
 
-/* The 12 raw (unstandardized) features of a shape: operator one-hot (3),
- * is-backward, dtype one-hot (3), log2 M, log2 N, aligned rows (1 when N * e
- * is a multiple of 16 bytes, so rows of ld = N from an aligned base hold
- * whole aligned vectors, else 0), and for a k = 4 and a k = 16 split how
- * full the slice keeps its register bucket (the slice's 16-byte vectors over
- * 256 * the smallest vectors-per-thread bucket holding them; 0 if none does).  Defined for the softmax, LayerNorm and RMSNorm
- * operators (the learned selector's domain; the other operators are planned
- * by the analytic model): CREDIT_ERR_UNSUPPORTED else. */
+/* The 12 raw (unstandardized) features of a shape: is-softmax, is-LayerNorm
+ * (RMSNorm: both 0), is-backward, log2 of the element bytes (2, 1, 0 for
+ * FP32, BF16, FP8), log2 M, log2 N, aligned rows (1 when N * e is a multiple
+ * of 16 bytes, so rows of ld = N from an aligned base hold whole aligned
+ * vectors, else 0), and for each split class k = 2, 4, 8, 16, 32
+ * log2(W_k * fill_k): fill_k is how full the slice keeps the bucket it runs
+ * in (the slice's 16-byte vectors over 256 * the smallest vectors-per-thread
+ * bucket of the operator holding them, register buckets first, then LDS
+ * buckets where the operator has them) and W_k = ceil(M / row groups) the
+ * waves of row groups (Eq. (8)) of the plan's host-only geometry (as
+ * credit_plan_geometry with h == NULL reports it); -1 when the plan is
+ * illegal (the slice exceeds the capacity of Eq. (3)).  Defined
+ * for the softmax, LayerNorm and RMSNorm operators (the learned selector's
+ * domain; the other operators are planned by the analytic model):
+ * CREDIT_ERR_UNSUPPORTED else. */
 credit_status_t credit_features(credit_op_t op, credit_dir_t dir, credit_dtype_t dt, int64_t M,
                                 int64_t N, float *feat12);
 

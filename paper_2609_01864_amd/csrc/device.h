@@ -22,10 +22,16 @@ template <> struct Io<DT_BF16> { static constexpr int EPV = 8, BYTES = 2; };
 template <> struct Io<DT_FP8> { static constexpr int EPV = 16, BYTES = 1; };
 
 __device__ __forceinline__ float fast_exp2(float v) { return __builtin_amdgcn_exp2f(v); }
-// The hardware exp2 flushes results below 2^-126 to zero.  Output passes
-// evaluate 2^(v + kExpShift) and fold 2^-kExpShift into their per-row factor,
-// so outputs down to 2^-158 keep their denormal value (v <= 0 there, so the
-// shifted exponential cannot overflow); the factor's product is exact.
+// The hardware exp2 flushes results below 2^-126 to zero.  Output passes that
+// evaluate their exponential there (BF16 softmax, backward from the logits,
+// two-pass) take 2^(v + kExpShift) and fold 2^-kExpShift into their per-row
+// factor, so those outputs down to 2^-158 keep their denormal value (v <= 0
+// there, so the shifted exponential cannot overflow; the factor's product is
+// exact).  The FP32 softmax forward (register slots) and the FP8 one on
+// slices of up to 64 values per thread reuse the sum pass's unshifted
+// exponentials about each thread's own maximum instead: an output whose
+// exponential lies below 2^-126 of that maximum is 0, an absolute error
+// under 1.2e-38 (FP32) or far below an e4m3 step (FP8).
 constexpr float kExpShift = 32.f;
 constexpr float kExpUnshift = 0x1p-32f;
 

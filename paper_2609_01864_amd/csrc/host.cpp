@@ -977,27 +977,44 @@ credit_plan_t fixed_rule(credit_handle_t h, int k_op, int dt, int64_t M, int64_t
 void features(int k_op, int dt, int64_t M, int64_t N, float *f) {
     const int op = k_op % 3, dir = k_op / 3;
     for (int i = 0; i < CREDIT_NUM_FEATURES; ++i) f[i] = 0.f;
-    f[op] = 1.f;
-    f[3] = (float)dir;
-    f[4 + dt] = 1.f;
+    f[0] = op == OP_SOFTMAX_FWD ? 1.f : 0.f;
+    f[1] = op == OP_LN_FWD ? 1.f : 0.f;  // RMSNorm: neither
+    f[2] = (float)dir;
     const double e = dt_bytes(dt);
-    f[7] = (float)std::log2((double)std::max<int64_t>(M, 1));
-    f[8] = (float)std::log2((double)N);
-    f[9] = ((int64_t)(N * e) % 16 == 0) ? 1.f : 0.f;
-    // how full the slice of a k = 4 and a k = 16 split keeps its register
-    // bucket (vectors of the slice / vectors the chosen VPT holds; 0 when no
-    // bucket holds it): the best split factor changes in steps where slices
-    // cross bucket boundaries, which log2 N alone shows only indirectly
-    auto fill = [&](int k) -> float {
+    f[3] = (float)std::log2(e);
+    f[4] = (float)std::log2((double)std::max<int64_t>(M, 1));
+    f[5] = (float)std::log2((double)N);
+    f[6] = ((int64_t)(N * e) % 16 == 0) ? 1.f : 0.f;
+    // per split class k: log2(W_k * fill_k), where fill_k is how full the
+    // slice keeps the vectors-per-thread bucket it runs in (the operator's
+    // register buckets, then its LDS buckets) and W_k = ceil(M / groups) the
+    // waves of row groups of Eq. (8), with the row groups of the register
+    // model's workgroups per CU on 256 CUs (the host-only geometry of
+    // credit_plan_geometry with no handle); -1 when the plan is illegal.  The
+    // best plan changes in steps where slices cross bucket and capacity
+    // boundaries (Eq. (3)) and where the last wave of row groups is partly
+    // empty, which log2 M and log2 N show only indirectly.
+    auto fill = [&](int k) -> double {
         const int64_t nv = (N * (int64_t)e + 15) / 16;
         const int64_t per = (nv + k - 1) / k;
         const int64_t need = (per + kBlockThreads - 1) / kBlockThreads;
         for (int v : kVpts)
-            if (v >= need) return (float)((double)per / ((double)kBlockThreads * v));
-        return 0.f;
+            if (v >= need && v <= max_vpt(k_op, dt)) return (double)per / ((double)kBlockThreads * v);
+        if (lds_capable(k_op, dt))
+            for (int v : kLdsVpts)
+                if (v >= need) return (double)per / ((double)kBlockThreads * v);
+        return 0.0;
     };
-    f[10] = fill(4);
-    f[11] = fill(16);
+    for (int i = 0; i < 5; ++i) {
+        const int k = kSplitKs[i];
+        const double fl = fill(k);
+        Launch L;
+        f[7 + i] = -1.f;
+        if (fl <= 0.0 || resolve(nullptr, k_op, dt, M, N, {CREDIT_SPLIT_ROW, k}, false, L) != CREDIT_OK) continue;
+        const int64_t groups = std::max<int64_t>(1, L.grid / k);
+        const int64_t W = (std::max<int64_t>(M, 1) + groups - 1) / groups;
+        f[7 + i] = (float)(std::log2((double)W) + std::log2(fl));
+    }
 }
 
 credit_status_t mlp_predict_dev(credit_handle_t h, const float *feats, int64_t n, float *logits);
@@ -2139,7 +2156,7 @@ credit_status_t credit_mlp_predict(credit_handle_t h, const float *feats, int64_
     }
 }
 
-static const char *kSchema = "f12-h64-h64-c7-v3";
+static const char *kSchema = "f12-h64-h64-c7-v5";
 
 credit_status_t credit_save_model(credit_handle_t h, const char *path) {
     if (!h || !path) return CREDIT_ERR_INVALID_ARG;

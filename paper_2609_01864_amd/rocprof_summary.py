@@ -265,7 +265,8 @@ def counters(args):
     med = {c: statistics.median(v) for c, v in vals.items()}
     n_disp = min(len(v) for v in vals.values())
     key = bench["roofline"]["kernel"]
-    elems = bench["roofline"]["algorithmic_bytes_per_launch"] / 8.0  # FP32 in + out per element
+    # elements per launch: stated by single-workload runs, else FP32 in + out
+    elems = bench["roofline"].get("elements_per_launch") or bench["roofline"]["algorithmic_bytes_per_launch"] / 8.0
     waves = med.get("SQ_WAVES", 0.0)
     lines = [f"# SQ counters of the dominant kernel: {args.title}", "",
              f"Command: `{args.command}`", "",

@@ -17,7 +17,10 @@ collect  For 6000 seeded shapes (op x direction x dtype stratified over the 18
          collection resumes where it stopped.
 train    Seeded stratified 80/20 split; soft targets t_c ~ exp(-(T_c/T_best - 1)
          / tau) over legal plans (tau = 0.02); full-batch Adam on the GPU through
-         credit_mlp_train; the model is saved with credit_save_model.
+         credit_mlp_train, one network per initialisation seed on 90% of the
+         training records, the one with the lowest noise-aware regret on the
+         other 10% kept; the model is saved with credit_save_model.
+         --rounds R draws R sets of shapes (seeds 4 + 3r, 5 + 3r, 6 + 3r).
 eval     Held-out regret T(pick)/T(best) - 1 of the learned, analytic (Eq. (9)
          with the measured baseline and control timings), peak-bandwidth and
          fixed-rule selectors.
@@ -52,10 +55,11 @@ def io_bytes(op: int, direction: int, dtype: int, M: int, N: int) -> float:
     return float(M) * N * e * tensors
 
 
-def sample_shapes(n: int = 6000, seed: int = 4, align: int = 1):
-    """n shapes stratified over the 18 (op, direction, dtype) combinations;
-    align > 1 rounds N to a multiple of align, align == 0 to a power of two
-    (the common widths, where slices meet the capacity boundaries exactly)."""
+def sample_shapes(n: int = 6000, seed: int = 4, align: int = 1, m_range=(1, 16384), n_range=(1024, 4194304)):
+    """n shapes stratified over the 18 (op, direction, dtype) combinations,
+    M and N log-uniform in m_range and n_range; align > 1 rounds N to a
+    multiple of align, align == 0 to a power of two (the common widths, where
+    slices meet the capacity boundaries exactly)."""
     rng = np.random.default_rng(seed)
     combos = [(o, d, t) for (o, d) in OPS for t in (C.F32, C.BF16, C.FP8)]
     out = []
@@ -64,8 +68,8 @@ def sample_shapes(n: int = 6000, seed: int = 4, align: int = 1):
         o, d, t = combos[i % len(combos)]
         i += 1
         while True:
-            M = int(round(math.exp(rng.uniform(math.log(1), math.log(16384)))))
-            N = int(round(math.exp(rng.uniform(math.log(1024), math.log(4194304)))))
+            M = int(round(math.exp(rng.uniform(math.log(m_range[0]), math.log(m_range[1])))))
+            N = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
             if align > 1:
                 N = max(1024, int(round(N / align)) * align)
             elif align == 0:
@@ -85,7 +89,10 @@ def legal_classes(h, s):
             if h.plan_legal(s["op"], s["dir"], s["dt"], s["M"], s["N"], C.plan_of_class(c))]
 
 
-def collect(h, shapes, path: str, reps: int = 15):
+def collect(h, shapes, path: str, reps: int = 15, budget_s: float = 0.0):
+    """Times every legal plan of each shape not yet in `path` (appending one
+    JSON record per shape, so a run can resume).  With budget_s > 0 it stops
+    after the first shape that ends past that many seconds."""
     done = set()
     if os.path.exists(path):
         with open(path) as f:
@@ -118,6 +125,9 @@ def collect(h, shapes, path: str, reps: int = 15):
             f.flush()
             if (i + 1) % 50 == 0 or i + 1 == len(todo):
                 log(f"collect {i + 1}/{len(todo)} ({time.time() - t0:.0f} s)")
+            if budget_s > 0 and time.time() - t0 > budget_s:
+                log(f"collect: time budget reached after {i + 1} shapes; run again to resume")
+                return
 
 
 def load(path: str):
@@ -166,11 +176,24 @@ def arrays(recs):
     return X, T, Mk
 
 
-def train(h, recs, epochs: int = 4000, lr: float = 3e-3, seed: int = 1):
-    X, T, Mk = arrays(recs)
-    loss = h.mlp_train(X, T, Mk, epochs, lr, seed)
-    log(f"train: {len(recs)} samples, {epochs} epochs, final loss {loss:.4f}")
-    return loss
+def train(h, recs, epochs: int = 4000, lr: float = 3e-3, seeds=(1, 2, 3, 4)):
+    """Trains one network per initialisation seed on 90% of the training
+    records and keeps the one with the lowest noise-aware regret on the other
+    10% (a validation split of the training records; the held-out test
+    records are never seen).  Leaves the kept network loaded in h."""
+    fit, val = split(recs, seed=9, frac=0.9)
+    X, T, Mk = arrays(fit)
+    best = None
+    for sd in seeds:
+        loss = h.mlp_train(X, T, Mk, epochs, lr, sd)
+        st = regret_stats(val, pick_learned(h, val))
+        log(f"train seed {sd}: {len(fit)} samples, {epochs} epochs, loss {loss:.4f}, validation regret "
+            f"{st['geomean'] - 1:.4f} (noise-aware {st['noise_aware_geomean'] - 1:.4f})")
+        if best is None or st["noise_aware_geomean"] < best[0]:
+            best = (st["noise_aware_geomean"], sd, h.mlp_get())
+    h.mlp_set(*best[2])
+    log(f"train: kept seed {best[1]} (validation noise-aware regret {best[0] - 1:.4f})")
+    return best[1]
 
 
 # -------------------------------------------------------------- selectors
@@ -305,14 +328,28 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=4000)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--model", default=None)
+    ap.add_argument("--time-budget", type=float, default=0.0, help="collect: stop after this many seconds")
+    ap.add_argument("--rounds", type=int, default=1,
+                    help="collect: shape sets drawn (round r uses seeds 4 + 3r, 5 + 3r, 6 + 3r)")
+    ap.add_argument("--dense-shapes", type=int, default=0,
+                    help="collect: more shapes in the regime of the evaluation workloads (M in [256, 16384], N in "
+                         "[8192, 1048576], half with N a multiple of 64; seeds 30, 31)")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
     data = os.path.join(args.out, "timings.jsonl")
     model = args.model or os.path.join(args.out, "selector_gfx950.txt")
     h = C.Handle(0, load_default_model=False)
     if args.cmd in ("collect", "all"):
-        collect(h, sample_shapes(args.shapes) + sample_shapes(args.aligned_shapes, seed=5, align=64) +
-                sample_shapes(args.pow2_shapes, seed=6, align=0), data, args.reps)
+        shapes = []
+        for r in range(args.rounds):
+            shapes += (sample_shapes(args.shapes, seed=4 + 3 * r) +
+                       sample_shapes(args.aligned_shapes, seed=5 + 3 * r, align=64) +
+                       sample_shapes(args.pow2_shapes, seed=6 + 3 * r, align=0))
+        if args.dense_shapes:
+            reg = dict(m_range=(256, 16384), n_range=(8192, 1048576))
+            shapes += (sample_shapes(args.dense_shapes // 2, seed=30, **reg) +
+                       sample_shapes(args.dense_shapes - args.dense_shapes // 2, seed=31, align=64, **reg))
+        collect(h, shapes, data, args.reps, args.time_budget)
     recs = load(data)
     tr, te = split(recs)
     if args.cmd in ("train", "all"):

@@ -6,6 +6,8 @@ import os
 import re
 import subprocess
 
+import math
+
 import numpy as np
 import pytest
 
@@ -56,17 +58,46 @@ def test_plan_classes_and_features(lib_built):
     plans = [C.plan_of_class(c).as_tuple() for c in range(C.NUM_PLANS)]
     assert plans == [(0, 1), (1, 1), (2, 2), (2, 4), (2, 8), (2, 16), (2, 32)]
     f = C.features(C.LAYERNORM, C.BWD, C.BF16, 2048, 131072)
-    assert list(f[:7]) == [0, 1, 0, 1, 0, 1, 0]
-    assert f[7] == 11 and f[8] == 17 and f[9] == 1  # 131072 BF16 values: whole 16-byte vectors
-    # 16384 vectors: k = 4 slices of 4096 = 256 x 16 (full bucket), k = 16 of 1024 = 256 x 4 (full)
-    assert f[10] == 1.0 and f[11] == 1.0
+    assert list(f[:4]) == [0, 1, 1, 1]  # LayerNorm, backward, 2-byte elements
+    assert f[4] == 11 and f[5] == 17 and f[6] == 1  # 131072 BF16 values: whole 16-byte vectors
+
+    def per_class(op, d, dt, M, N, fills):
+        # log2(W * fill) per split class, W = ceil(M / row groups) of the
+        # host-only geometry; -1 where the plan is illegal (fill 0)
+        out = []
+        for k, fl in zip((2, 4, 8, 16, 32), fills):
+            g = C.plan_geometry(None, op, d, dt, M, N, C.plan("split", k))
+            assert (g is None) == (fl == 0), (k, g, fl)
+            out.append(-1.0 if g is None else math.log2(math.ceil(M / (g["grid"] // k))) + math.log2(fl))
+        return out
+
+    # 16384 vectors; BF16 LayerNorm backward holds at most 4 per thread:
+    # k = 2, 4, 8 exceed it, k = 16 slices of 1024 = 256 x 4 (full), k = 32 of 512 = 256 x 2 (full)
+    assert np.allclose(f[7:], per_class(C.LAYERNORM, C.BWD, C.BF16, 2048, 131072, [0, 0, 0, 1, 1]))
+    assert list(f[7:10]) == [-1, -1, -1]
     g = C.features(C.SOFTMAX, C.FWD, C.F32, 3, 100000)  # 25000 vectors
-    # k = 4: 6250 per slice -> 25 per thread -> bucket 32; k = 16: 1563 -> 7 -> bucket 8
-    assert np.isclose(g[10], 6250 / (256 * 32)) and np.isclose(g[11], 1563 / (256 * 8))
-    assert C.features(C.SOFTMAX, C.FWD, C.F32, 3, 4 << 20)[10] == 0.0  # k = 4 slices exceed 32 vectors
-    assert C.features(C.LAYERNORM, C.BWD, C.BF16, 2048, 131071)[9] == 0
-    assert C.features(C.SOFTMAX, C.FWD, C.FP8, 3, 4096 + 16)[9] == 1
-    assert C.features(C.SOFTMAX, C.FWD, C.F32, 3, 4096 + 2)[9] == 0
+    assert list(g[:4]) == [1, 0, 0, 2]
+    # k = 2: 12500 per slice -> 49 per thread -> LDS bucket 68; k = 4: 6250 -> 25 -> 32;
+    # k = 8: 3125 -> 13 -> 16; k = 16: 1563 -> 7 -> 8; k = 32: 782 -> 4 -> 4; 3 rows: one wave
+    fills = [12500 / (256 * 68), 6250 / (256 * 32), 3125 / (256 * 16), 1563 / (256 * 8), 782 / (256 * 4)]
+    assert np.allclose(g[7:], np.log2(fills))
+    assert np.allclose(g[7:], per_class(C.SOFTMAX, C.FWD, C.F32, 3, 100000, fills))
+    r = C.features(C.RMSNORM, C.FWD, C.FP8, 3, 100000)  # 6250 vectors
+    assert list(r[:4]) == [0, 0, 0, 0]
+    assert np.isclose(r[7], math.log2(3125 / (256 * 16))) and np.isclose(r[8], math.log2(1563 / (256 * 8)))
+    # FP8 rows have register buckets only (up to 16): 65536 vectors fit from k = 16
+    assert np.allclose(C.features(C.RMSNORM, C.FWD, C.FP8, 3, 1 << 20)[7:], [-1, -1, -1, 0, 0])
+    # 2M FP32 values: only k = 32 slices (64 vectors per thread) fit, in the 68-vector LDS bucket
+    assert np.allclose(C.features(C.SOFTMAX, C.FWD, C.F32, 3, 2 << 20)[7:], [-1, -1, -1, -1, math.log2(64 / 68)])
+    # many rows: W grows with M at fixed N
+    w1 = C.features(C.LAYERNORM, C.FWD, C.F32, 1024, 131072)
+    w2 = C.features(C.LAYERNORM, C.FWD, C.F32, 8192, 131072)
+    # k = 2: 64 vectors per thread in the 68-vector LDS bucket; k >= 4: full register buckets
+    assert np.all(w2[7:] > w1[7:]) and np.allclose(w1[7:], per_class(C.LAYERNORM, C.FWD, C.F32, 1024, 131072,
+                                                                      [64 / 68, 1, 1, 1, 1]))
+    assert C.features(C.LAYERNORM, C.BWD, C.BF16, 2048, 131071)[6] == 0
+    assert C.features(C.SOFTMAX, C.FWD, C.FP8, 3, 4096 + 16)[6] == 1
+    assert C.features(C.SOFTMAX, C.FWD, C.F32, 3, 4096 + 2)[6] == 0
 
 
 def test_host_legality_follows_capacity(lib_built):

@@ -30,7 +30,7 @@ def test_load_recomputes_features_and_targets(lib_built, tmp_path):
     path.write_text(json.dumps(rec) + "\n")
     r = T.load(str(path))[0]
     assert np.allclose(r["feats"], C.features(C.LAYERNORM, C.FWD, C.F32, 1024, 8192))
-    assert r["feats"][9] == 1.0  # whole aligned vectors
+    assert r["feats"][6] == 1.0  # whole aligned vectors
     t, m = T.soft_targets(r)
     assert list(m[:3]) == [1, 1, 1] and m[3:].sum() == 0
     assert math.isclose(t.sum(), 1.0) and t.argmax() == 1
