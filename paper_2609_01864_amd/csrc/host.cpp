@@ -1109,9 +1109,16 @@ credit_status_t exhaustive_pick(credit_handle_t h, int k_op, int dt, int64_t M, 
     return CREDIT_OK;
 }
 
-// The network's best legal plan, or with `timed` its two best legal plans,
-// each timed (cold cache, median of 7), keeping the faster: the model as a
-// screen that narrows the search, the final choice by measurement.
+// Logit margin within which the untimed pick counts two plans as tied.  The
+// network is trained on soft targets exp(-(T_c / T_best - 1) / tau) with
+// tau = 0.02, so a logit gap of 0.5 is a predicted 1% time difference: the
+// judge's noise floor, inside which it takes the plan moving fewer bytes.
+constexpr float kTieLogit = 0.5f;
+// The network's best legal plan -- among the legal plans whose logits lie
+// within kTieLogit of the best, the one moving the fewest bytes -- or with
+// `timed` its two best legal plans, each timed (cold cache, median of 7),
+// keeping the faster: the model as a screen that narrows the search, the
+// final choice by measurement.
 credit_status_t learned_pick(credit_handle_t h, int k_op, int dt, int64_t M, int64_t N, bool timed,
                              credit_plan_t *out, float *pred) {
     float f[CREDIT_NUM_FEATURES], logits[CREDIT_NUM_PLANS];
@@ -1129,8 +1136,17 @@ credit_status_t learned_pick(credit_handle_t h, int k_op, int dt, int64_t M, int
         }
     }
     if (best < 0) return CREDIT_ERR_UNSUPPORTED;
+    if (!timed) {
+        int pick = best;
+        for (int c = 0; c < CREDIT_NUM_PLANS; ++c)
+            if (logits[best] - logits[c] <= kTieLogit && bytes_rank(c) < bytes_rank(pick) &&
+                plan_ok(h, k_op, dt, M, N, class_plan(c)))
+                pick = c;
+        *out = class_plan(pick);
+        return CREDIT_OK;
+    }
     *out = class_plan(best);
-    if (!timed || second < 0) return CREDIT_OK;
+    if (second < 0) return CREDIT_OK;
     float t1 = 0.f, t2 = 0.f;
     st = time_plan(h, k_op, dt, M, N, class_plan(best), 7, 1, &t1);
     if (st != CREDIT_OK) return st;

@@ -1,5 +1,6 @@
 // Kernel instantiations for OP_RMS_FWD: the register-resident / split-row kernel
-// for every (dtype, vectors-per-thread) within the register budget, and the
+// for every (dtype, vectors-per-thread) within the register budget (FP8 rows in
+// inst_rms_fwd_fp8.hip, built with the default instruction schedule), and the
 // two-pass kernel for 256- and 1024-thread workgroups (FP8 at 1024 threads
 // keeps 2 vectors in flight per thread: its decoded values then fit the 128
 // registers a 1024-thread workgroup allows, without spilling).
@@ -18,10 +19,12 @@ namespace credit {
 #define CREDIT_RL(DT, V) \
     if (dt == DT && vpt == V) return (const void *)&k_resident<OP_RMS_FWD, DT, kRegVptMax, V - kRegVptMax>;
 
+const void *resident_kernel_rms_fwd_fp8(int vpt);  // inst_rms_fwd_fp8.hip (default schedule)
+
 const void *resident_kernel_rms_fwd(int dt, int vpt) {
     CREDIT_RV(DT_F32)
     CREDIT_RV(DT_BF16)
-    CREDIT_RV(DT_FP8)
+    if (dt == DT_FP8) return resident_kernel_rms_fwd_fp8(vpt);
     CREDIT_RL(DT_F32, 48) CREDIT_RL(DT_F32, 68)
     CREDIT_RL(DT_BF16, 48) CREDIT_RL(DT_BF16, 68)
     return nullptr;

@@ -39,6 +39,9 @@ import statistics
 import sys
 
 
+CLOCK_HZ = 2.4e9  # MI355X peak engine clock (the launch's cycles for the coverage figure)
+
+
 def _find(d: str, suffix: str) -> str:
     hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
     if not hits:
@@ -280,6 +283,25 @@ def counters(args):
                       f"{med.get('SQ_LDS_BANK_CONFLICT', 0.0) / med['SQ_ACTIVE_INST_LDS']:.4f}"]
     if waves:
         lines += ["", f"Waves per dispatch {waves:.0f} (grid / 64 = {grid / 64:.0f})."]
+    gui = med.get("GRBM_GUI_ACTIVE")
+    avg_us = bench["roofline"].get("avg_launch_us")
+    if gui and avg_us:
+        # GRBM_GUI_ACTIVE counts the busy cycles of every XCD the collection
+        # covers: over the launch's duration it tells how many XCDs the SQ sums
+        # (which are summed over the same units) include
+        xcds = gui / (avg_us * 1e-6 * CLOCK_HZ)
+        lines += ["", f"Coverage: GRBM_GUI_ACTIVE is {xcds:.2f}x the launch's cycles ({avg_us:.1f} us at "
+                      f"{CLOCK_HZ / 1e9:.1f} GHz), i.e. the counters sum over about {round(xcds)} of the 8 XCDs; "
+                      f"SQ_BUSY_CYCLES / GRBM_GUI_ACTIVE = {med.get('SQ_BUSY_CYCLES', 0.0) / gui:.2f} "
+                      f"(the SQ units per XCD counted).  Full-chip figures per element, scaled by "
+                      f"8 / {xcds:.2f}:", ""]
+        lines += ["| counter | per element, full chip |", "|---|---:|"]
+        for c in ("SQ_INSTS_VALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_LDS"):
+            if c in med:
+                lines.append(f"| {c} | {med[c] / elems * 8.0 / xcds:.4g} |")
+        if med.get("SQ_WAVE_CYCLES") and med.get("SQ_BUSY_CYCLES"):
+            lines += ["", f"SQ_WAVE_CYCLES / SQ_BUSY_CYCLES = {med['SQ_WAVE_CYCLES'] / med['SQ_BUSY_CYCLES']:.2f} "
+                          f"(resident waves per counted SQ unit, in the counter's units)."]
     out = {"kernel": key, "kernel_symbol": sym, "grid_threads": grid, "dispatches": n_disp,
            "median_per_dispatch": med, "source_hash": bench.get("source_hash")}
     json.dump(out, open(args.json, "w"), indent=1)

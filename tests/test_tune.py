@@ -63,3 +63,16 @@ def test_noise_aware_regret_and_judge_tie_break():
     assert T.regret_stats([bare], [3])["noise_aware_geomean"] == 1.03
     # ranking by bytes: resident, split by increasing k, two-pass last
     assert sorted(range(C.NUM_PLANS), key=T.bytes_rank) == [1, 2, 3, 4, 5, 6, 0]
+
+
+def test_learned_pick_breaks_near_ties_by_bytes():
+    # the untimed pick: the largest logit among legal plans, or within 0.5 of
+    # it (a predicted 1% under tau = 0.02) the plan moving the fewest bytes
+    class Net:
+        def mlp_predict(self, X):
+            return np.tile(np.array([[2.0, 1.0, 1.3, 1.6, 0.0, 0.0, 0.0]], np.float32), (len(X), 1))
+
+    recs = [{"feats": [0.0] * 12, "times": {"0": 1.0, "1": 1.0, "2": 1.0, "3": 1.0}},  # 0 best, 3 within
+            {"feats": [0.0] * 12, "times": {"1": 1.0, "2": 1.0, "3": 1.0}},  # 3 best; 2 within, 1 not
+            {"feats": [0.0] * 12, "times": {"1": 1.0, "3": 1.0}}]  # 3 best; 1 is 0.6 below
+    assert T.pick_learned(Net(), recs) == [3, 2, 3]
