@@ -53,3 +53,28 @@ def test_learned_pick_beats_the_analytic_model(gpu_handle):
         assert learned["share_within_5pct"] > analytic["share_within_5pct"]
     finally:
         h.close()
+
+
+def test_library_untimed_pick_matches_the_tuning_mirror(lib_built):
+    # the handle's untimed learned pick (host features, device network, tie
+    # rule) and tune.pick_learned (the same features from the binding, the
+    # same network through credit_mlp_predict, the same rule) agree shape by
+    # shape, so the regret the tuning tools report is the library's
+    h = C.Handle(0)
+    try:
+        assert h.model_loaded
+        h.set_selector(C.SEL_LEARNED)
+        shapes = T.sample_shapes(180, seed=13) + T.sample_shapes(72, seed=14, align=0)
+        recs, lib_picks = [], []
+        for s in shapes:
+            o, d, dt, M, N = s["op"], s["dir"], s["dt"], s["M"], s["N"]
+            legal = T.legal_classes(h, s)
+            recs.append(dict(s, times={str(c): 1.0 for c in legal},
+                             feats=[float(v) for v in C.features(o, d, dt, M, N)]))
+            p, _ = h.select(o, d, dt, M, N)
+            lib_picks.append([C.plan_of_class(c).as_tuple() for c in range(C.NUM_PLANS)].index(p.as_tuple()))
+        mirror = T.pick_learned(h, recs)
+        print(f"[selector mirror] {len(recs)} shapes", flush=True)
+        assert lib_picks == mirror
+    finally:
+        h.close()
