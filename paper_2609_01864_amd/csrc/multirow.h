@@ -250,11 +250,7 @@ __device__ __forceinline__ void rows_loop(const RowArgs &a, int c, int grp, cons
         for (int i = 0; i < R; ++i) oinv[i] = 1.f;
         auto pass = [&](bool store, float (&amax)[R]) {
             fresh();
-            // parameter bases made opaque per pass, so the second pass loads
-            // gamma / beta again instead of the compiler keeping the first
-            // pass's loads live across the amax stage
             const float *gp = a.gamma, *bp = a.beta;
-            asm volatile("" : "+s"(gp), "+s"(bp));
 #pragma unroll
             for (int j = 0; j < VPT; ++j) {
                 __builtin_amdgcn_sched_barrier(0);
@@ -269,8 +265,6 @@ __device__ __forceinline__ void rows_loop(const RowArgs &a, int c, int grp, cons
                 const bool ok = ok_of(j);
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    // one row at a time: the decoded values of only one row are live
-                    __builtin_amdgcn_sched_barrier(0);
                     float q[EPV], y[EPV];
                     decode<DT>(d[i][j], q, 1.f);
                     h(i, q, g, LN ? bb : g, y);
