@@ -160,3 +160,53 @@ def test_rows_option_is_validated(handles):
         assert h2.geometry(op, d, C.F32, 64, 8192, C.plan("resident"))["rows"] == 1
     assert h2.geometry(C.LAYERNORM, C.FWD, C.F32, 64, 8192, C.plan("resident"))["rows"] == 4
     assert h2.geometry(C.LAYERNORM, C.FWD, C.F32, 1, 8192, C.plan("resident"))["rows"] == 1
+
+
+def test_multirow_graph_replay_with_new_inputs(lib_built):
+    # two-row split launches recorded into a HIP graph: every replay takes a
+    # new device-side epoch, so no row block accepts a previous replay's slots
+    import torch
+
+    import oracle
+    from paper_2609_01864_amd import inputs as I
+
+    h = C.Handle(0, load_default_model=False)
+    h.set_option(C.OPT_ROWS, 2)
+    M, N, eps = 37, 30000, 1e-5
+    g32, b32 = I.norm_params(N, seed=61)
+    gamma, beta = torch.from_numpy(g32).cuda(), torch.from_numpy(b32).cuda()
+    sx = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    side = torch.cuda.Stream()
+    p = C.plan("split", 4)
+    try:
+        for o in (C.LAYERNORM, C.RMSNORM):
+            assert h.geometry(o, C.FWD, C.F32, M, N, p)["rows"] == 2
+        sx.copy_(torch.from_numpy(I.norm_rows(M, N, seed=60).astype(np.float32)))
+        with torch.cuda.stream(side):
+            C.layernorm_fwd(sx, gamma, beta, eps, p=p, h=h)
+            C.rmsnorm_fwd(sx, gamma, eps, p=p, h=h)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            yl, _, _, _ = C.layernorm_fwd(sx, gamma, beta, eps, p=p, h=h)
+            yr, _, _ = C.rmsnorm_fwd(sx, gamma, eps, p=p, h=h)
+        for rep in range(3):
+            x32 = I.norm_rows(M, N, seed=400 + rep).astype(np.float32)
+            sx.copy_(torch.from_numpy(x32))
+            print(f"[multirow graph] replay {rep}", flush=True)
+            graph.replay()
+            torch.cuda.synchronize()
+            xr = x32.astype(np.float64)
+            ref, _, _ = oracle.layernorm_fwd(xr, g32.astype(np.float64), b32.astype(np.float64), eps)
+            assert np.max(np.abs(yl.double().cpu().numpy() - ref)) <= 1e-5
+            ref2, _ = oracle.rmsnorm_fwd(xr, g32.astype(np.float64), eps)
+            assert np.max(np.abs(yr.double().cpu().numpy() - ref2)) <= 1e-5
+            # eager two-row work on the same handle between replays
+            z = torch.randn(9, 30000, device="cuda") + 3.0
+            zz, _, _ = C.rmsnorm_fwd(z, gamma, eps, p=p, h=h)
+            torch.cuda.synchronize()
+            zr, _ = oracle.rmsnorm_fwd(z.double().cpu().numpy(), g32.astype(np.float64), eps)
+            assert np.max(np.abs(zz.double().cpu().numpy() - zr)) <= 1e-5
+        assert h.check_errors() == C.OK
+    finally:
+        h.close()
