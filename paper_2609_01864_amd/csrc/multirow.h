@@ -9,9 +9,9 @@
 // statistics of all R rows (Eq. (5) with q = R x the per-row statistics).
 // The row arithmetic is the one of resident.h: LayerNorm moments about a
 // per-thread shift, merged with Chan's update on means taken relative to the
-// row's first element; RMSNorm sums of squares; FP8 output with a per-row amax
-// stage and the output kept in nothing but the packed input (it is recomputed
-// from x, gamma and beta in the quantising pass).
+// row's first element; RMSNorm sums of squares; FP8 output through a per-row
+// amax stage, after which the quantising pass recomputes y from the resident
+// x, gamma and beta (no y is kept across the stage).
 #pragma once
 #include "resident.h"
 

@@ -69,6 +69,27 @@ def test_noalloc_layernorm_matches_the_workspace_entry_point(gpu_handle):
     assert h.check_errors() == C.OK
 
 
+def test_noalloc_two_row_workgroups(gpu_handle):
+    # shapes where the library holds two rows per workgroup: a row-resident
+    # plan with more than twice as many rows as row-group slots, and a split
+    # plan at k = 16 with two rows per workgroup forced
+    h = gpu_handle
+    cases = [(8192, 1024, C.plan("resident"), 0), (300, 65536, C.plan("split", 16), 2)]
+    try:
+        for M, N, plan, rows in cases:
+            h.set_option(C.OPT_ROWS, rows)
+            assert h.geometry(C.LAYERNORM, C.FWD, C.F32, M, N, plan)["rows"] == 2
+            print(f"[noalloc] two rows M={M} N={N} {plan}", flush=True)
+            (ws_out, na_out), (ref, mu, rs) = _ln_both(h, M, N, plan, seed=M + 7)
+            for a, b in zip(ws_out, na_out):
+                assert np.array_equal(a, b)
+            assert np.max(np.abs(na_out[0].astype(np.float64) - ref)) <= 1e-5
+            assert np.max(np.abs(na_out[2] - rs)) <= 1e-6 * np.max(rs)
+    finally:
+        h.set_option(C.OPT_ROWS, 0)
+    assert h.check_errors() == C.OK
+
+
 def test_noalloc_refuses_plans_beyond_its_scratch(gpu_handle):
     h = gpu_handle
     M, N = 12000, 4096  # split k = 32 needs M * 3 * 32 * 2 * 8 + 256 bytes > 16 MiB
