@@ -476,6 +476,9 @@ def main():
                          "with the precision workload's rows, timed alone: the launch sequence a counter "
                          "profile of that kernel runs under")
     ap.add_argument("--plan", default=None, help="--single: plan as variant:k (default: the selector's)")
+    ap.add_argument("--dominant", default=None, metavar="OP:N",
+                    help="report the roofline for this shape (e.g. layernorm_fwd:524288) instead of the longest "
+                         "launch, so that counter runs of two launches of nearly equal length name the same kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the row kernels shard over rows with no communication, "
@@ -593,6 +596,9 @@ def main():
                               "geometry": {"grid": g["grid"], "per_cu": g["per_cu"], "vpt": g["vpt"],
                                            "rows": g["rows"]}})
     dom = max(per_shape, key=lambda r: r["us"])
+    if args.dominant:
+        dop, dn = args.dominant.split(":")
+        dom = next(r for r in per_shape if r["op"] == dop and r["N"] == int(dn))
     dom_key = f"{dom['op']}:N={dom['N']}:plan={dom['plan'][0]},{dom['plan'][1]}"
     sym, grid_threads = kernel_symbol(C, h, opnum[dom["op"]], C.F32, M_ROWS, dom["N"], picks[(dom["op"], dom["N"])][0])
     roofline = {"bound": "hbm", "achieved": dom["gbps"], "peak": PEAK_GBPS, "unit": "GB/s",

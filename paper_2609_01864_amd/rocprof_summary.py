@@ -258,13 +258,27 @@ def counters(args):
     bench = json.loads(open(args.bench).read().strip().splitlines()[-1])
     sym, grid = kernel_name(bench)
     rows = _rows(_find(args.pmc, "counter_collection.csv"))
-    vals = {}
+    # one row per (dispatch, counter); other shapes can launch the same kernel
+    # instance with the same grid (the row-resident plan of a narrower row),
+    # so a dispatch counts only when its duration lies within 1/1.5..1.5x of
+    # the benchmark's own average for the dominant launch (both timed under
+    # the same counter collection)
+    avg = float(bench["roofline"]["avg_launch_us"])
+    disp, excluded = {}, set()
     for r in rows:
         if not (r.get("Kernel_Name") or "").startswith(sym) or _grid(r) != grid:
             continue
-        vals.setdefault(r.get("Counter_Name"), []).append(float(r.get("Counter_Value") or 0.0))
+        did = r.get("Dispatch_Id") or r.get("dispatch_id")
+        if not avg / 1.5 <= _dur_us(r) <= avg * 1.5:
+            excluded.add(did)
+            continue
+        disp.setdefault(did, {})[r.get("Counter_Name")] = float(r.get("Counter_Value") or 0.0)
+    vals = {}
+    for d in disp.values():
+        for c, v in d.items():
+            vals.setdefault(c, []).append(v)
     if not vals:
-        raise SystemExit(f"no dispatch of {sym} with grid {grid}")
+        raise SystemExit(f"no dispatch of {sym} with grid {grid} near {avg:.1f} us")
     med = {c: statistics.median(v) for c, v in vals.items()}
     n_disp = min(len(v) for v in vals.values())
     key = bench["roofline"]["kernel"]
@@ -273,7 +287,9 @@ def counters(args):
     waves = med.get("SQ_WAVES", 0.0)
     lines = [f"# SQ counters of the dominant kernel: {args.title}", "",
              f"Command: `{args.command}`", "",
-             f"Kernel `{sym}`, grid {grid} work-items ({key}); median over {n_disp} dispatches", "",
+             f"Kernel `{sym}`, grid {grid} work-items ({key}); median over {n_disp} dispatches "
+             f"({len(excluded)} dispatches of the same kernel and grid outside 1/1.5..1.5x of the benchmark's "
+             f"{avg:.1f} us excluded: other shapes)", "",
              "| counter | per dispatch | per wave | per element |", "|---|---:|---:|---:|"]
     for c in sorted(med):
         pw = med[c] / waves if waves else float("nan")
