@@ -174,8 +174,8 @@ def traffic(args):
     print("\n".join(lines))
 
 
-_OP_KERNEL = re.compile(r"credit::k_(twopass|resident|colreduce1|colreduce|colstats)\b")
-_MAIN_KERNEL = re.compile(r"credit::k_(twopass|resident)\b")
+_OP_KERNEL = re.compile(r"credit::k_(twopass|resident|multirow|colreduce1|colreduce|colstats)\b")
+_MAIN_KERNEL = re.compile(r"credit::k_(twopass|resident|multirow)\b")
 
 
 def _counter_seq(d: str, counter: str):

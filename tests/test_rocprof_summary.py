@@ -173,21 +173,28 @@ def test_dominant_traffic_rejects_runs_with_different_launches(tmp_path):
 
 def test_counters_median_and_ratios(tmp_path):
     bench = {"roofline": {"kernel": "layernorm_fwd:N=8:plan=2,2", "kernel_symbol": "void credit::k_resident<1, 0, 1>",
-                          "grid_threads": 128, "algorithmic_bytes_per_launch": 8.0 * 1000}, "source_hash": "h"}
+                          "grid_threads": 128, "algorithmic_bytes_per_launch": 8.0 * 1000, "avg_launch_us": 10.0},
+             "source_hash": "h"}
     bp = tmp_path / "b.json"
     bp.write_text(json.dumps(bench) + "\n")
     d = tmp_path / "sq"
     d.mkdir()
     with open(d / "x_counter_collection.csv", "w", newline="") as f:
         w = csv.writer(f)
-        w.writerow(HDR)
+        w.writerow(HDR + ["Start_Timestamp", "End_Timestamp"])
         k = "void credit::k_resident<1, 0, 1>(credit::RowArgs)"
-        rows = [(k, 128, "SQ_WAVES", 2), (k, 128, "SQ_INSTS_VALU", 100), (k, 128, "SQ_INSTS_VALU", 300),
-                (k, 128, "SQ_INSTS_VALU", 200), (k, 128, "SQ_WAVES", 2), (k, 128, "SQ_WAVES", 2),
-                (k, 64, "SQ_INSTS_VALU", 9999),  # another grid: ignored
-                (k, 128, "SQ_ACTIVE_INST_LDS", 50), (k, 128, "SQ_LDS_BANK_CONFLICT", 5)]
-        for i, (n, g, c, v) in enumerate(rows):
-            w.writerow([i + 1, g, n, c, v])
+        # (dispatch, grid, duration us, {counter: value})
+        disp = [(1, 128, 10.0, {"SQ_WAVES": 2, "SQ_INSTS_VALU": 100, "SQ_ACTIVE_INST_LDS": 50,
+                                "SQ_LDS_BANK_CONFLICT": 5}),
+                (2, 128, 11.0, {"SQ_WAVES": 2, "SQ_INSTS_VALU": 300}),
+                (3, 128, 9.0, {"SQ_WAVES": 2, "SQ_INSTS_VALU": 200}),
+                (4, 64, 10.0, {"SQ_INSTS_VALU": 9999}),  # another grid: ignored
+                (5, 128, 1.0, {"SQ_WAVES": 2, "SQ_INSTS_VALU": 7})]  # same kernel and grid, another shape
+        t = 1000
+        for did, g, us, cs in disp:
+            for c, v in cs.items():
+                w.writerow([did, g, k, c, v, t, t + int(us * 1000)])
+            t += 100000
     out = tmp_path / "c.json"
     R.main(["counters", "--pmc", str(d), "--bench", str(bp), "--json", str(out), "--out", str(tmp_path / "c.md")])
     res = json.load(open(out))
@@ -195,4 +202,5 @@ def test_counters_median_and_ratios(tmp_path):
     assert res["median_per_dispatch"]["SQ_WAVES"] == 2.0
     md = (tmp_path / "c.md").read_text()
     assert "| SQ_INSTS_VALU | 200 | 100 | 0.2 |" in md
+    assert "1 dispatches of the same kernel and grid" in md
     assert "0.1000" in md  # 5 conflict cycles per 50 active LDS cycles
