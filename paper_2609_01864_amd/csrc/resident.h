@@ -349,14 +349,17 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
         if constexpr (L > 0) {
             // the LDS slots: direct global -> LDS loads (16 bytes per lane, the
             // wave's 64 lanes land in its own row of the slot), in flight with
-            // the register loads; the same masked-slot addressing
+            // the register loads; the same masked-slot addressing.  Like the
+            // register slots they carry the non-temporal hint (cache policy 2):
+            // x is read once, and a cached stream would evict the parameter
+            // vectors that every row rereads from L2
             if (FULLS || sl.nfv > 0) {
                 const int wave = tid >> 6;
 #pragma unroll
                 for (int l = 0; l < L; ++l)
                     __builtin_amdgcn_global_load_lds((const void *)(b0 + doff(VPT + l)),
                                                      (__attribute__((address_space(3))) void *)(lds + l * kBlock + wave * 64),
-                                                     16, 0, 0);
+                                                     16, 0, 2);
             }
         }
         // LDS slot l (slot VPT + l of the slice), zero where masked; valid
