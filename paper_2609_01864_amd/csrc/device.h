@@ -400,13 +400,17 @@ struct MergeSoftmax {
         a[1] = sa + sb;
     }
 };
-// Chan et al. pairwise combination of (count, mean, M2).
+// Chan et al. pairwise combination of (count, mean, M2).  The weight
+// nb / (n + nb) goes through the hardware reciprocal (1 ulp) rather than a
+// correctly rounded division: its scale / fixup sequence ran on every merge
+// of every row (the wave and workgroup levels plus the k members of a split
+// row), and a 1-ulp weight moves the mean by 1 ulp of the means' difference.
 __device__ __forceinline__ void chan_merge(float &n, float &mean, float &m2, float nb, float meanb, float m2b) {
     float nn = n + nb;
     if (nb == 0.f) return;
     if (n == 0.f) { n = nb; mean = meanb; m2 = m2b; return; }
     float d = meanb - mean;
-    float wb = nb / nn;
+    float wb = nb * __builtin_amdgcn_rcpf(nn);
     mean = mean + d * wb;
     m2 = m2 + m2b + d * d * n * wb;
     n = nn;
@@ -439,7 +443,7 @@ __device__ __forceinline__ void co_merge(float (&a)[6], float nb, float mxb, flo
         return;
     }
     const float n = a[0] + nb, dx = mxb - a[1], dy = myb - a[2];
-    const float wb = nb / n, f = a[0] * wb;
+    const float wb = nb * __builtin_amdgcn_rcpf(n), f = a[0] * wb;  // as in chan_merge
     a[1] = a[1] + dx * wb;
     a[2] = a[2] + dy * wb;
     a[3] = a[3] + cxxb + dx * dx * f;
