@@ -24,6 +24,11 @@ train    Seeded stratified 80/20 split; soft targets t_c ~ exp(-(T_c/T_best - 1)
 eval     Held-out regret T(pick)/T(best) - 1 of the learned, analytic (Eq. (9)
          with the measured baseline and control timings), peak-bandwidth and
          fixed-rule selectors.
+fresh    Shapes the shipped model's collection did not draw (seeds 40 and 41:
+         half ragged, half with N a multiple of 64), timed on the library as
+         it is built now and judged with the model given by --model, so a
+         kernel change after the model was trained shows up as regret:
+         writes fresh.json.
 """
 from __future__ import annotations
 
@@ -42,6 +47,7 @@ OPS = [(C.SOFTMAX, C.FWD), (C.LAYERNORM, C.FWD), (C.RMSNORM, C.FWD),
        (C.SOFTMAX, C.BWD), (C.LAYERNORM, C.BWD), (C.RMSNORM, C.BWD)]
 SPLIT_KS = (2, 4, 8, 16, 32)
 TAU = 0.02
+FRESH_SEEDS = (40, 41)  # the fresh check's shapes; no collection round uses them
 MAX_IO_BYTES = 16e9
 
 
@@ -82,6 +88,30 @@ def sample_shapes(n: int = 6000, seed: int = 4, align: int = 1, m_range=(1, 1638
 
 def key_of(s) -> str:
     return f"{s['op']}:{s['dir']}:{s['dt']}:{s['M']}:{s['N']}"
+
+
+def collection_shapes(rounds: int = 2, shapes: int = 6000, aligned: int = 3000, pow2: int = 1000,
+                      dense: int = 6000):
+    """The shapes `collect` draws for these arguments (the shipped model's
+    dataset: two rounds of the defaults plus 6000 dense shapes)."""
+    out = []
+    for r in range(rounds):
+        out += (sample_shapes(shapes, seed=4 + 3 * r) + sample_shapes(aligned, seed=5 + 3 * r, align=64) +
+                sample_shapes(pow2, seed=6 + 3 * r, align=0))
+    if dense:
+        reg = dict(m_range=(256, 16384), n_range=(8192, 1048576))
+        out += (sample_shapes(dense // 2, seed=30, **reg) +
+                sample_shapes(dense - dense // 2, seed=31, align=64, **reg))
+    return out
+
+
+def fresh_shapes(n: int):
+    """n shapes from seeds FRESH_SEEDS (half ragged, half with N a multiple
+    of 64) minus any the shipped model's collection drew."""
+    seen = {key_of(s) for s in collection_shapes()}
+    cand = (sample_shapes(n // 2, seed=FRESH_SEEDS[0]) +
+            sample_shapes(n - n // 2, seed=FRESH_SEEDS[1], align=64))
+    return [s for s in cand if key_of(s) not in seen]
 
 
 def legal_classes(h, s):
@@ -329,7 +359,7 @@ def evaluate(h, recs, copy_gbps: float):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["collect", "train", "eval", "all"])
+    ap.add_argument("cmd", choices=["collect", "train", "eval", "all", "fresh"])
     ap.add_argument("--out", default="tune_out")
     ap.add_argument("--shapes", type=int, default=6000)
     ap.add_argument("--aligned-shapes", type=int, default=3000)
@@ -344,21 +374,26 @@ def main(argv=None):
     ap.add_argument("--dense-shapes", type=int, default=0,
                     help="collect: more shapes in the regime of the evaluation workloads (M in [256, 16384], N in "
                          "[8192, 1048576], half with N a multiple of 64; seeds 30, 31)")
+    ap.add_argument("--fresh-shapes", type=int, default=1000, help="fresh: shapes drawn (seeds 40, 41)")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
     data = os.path.join(args.out, "timings.jsonl")
     model = args.model or os.path.join(args.out, "selector_gfx950.txt")
     h = C.Handle(0, load_default_model=False)
+    if args.cmd == "fresh":
+        shapes = fresh_shapes(args.fresh_shapes)
+        path = os.path.join(args.out, "fresh.jsonl")
+        collect(h, shapes, path, args.reps, args.time_budget)
+        assert h.load_model(model) == C.OK, "model failed to load"
+        recs = load(path)
+        res = {"fresh": evaluate(h, recs, h.copy_bandwidth(1 << 30, 7)), "n": len(recs),
+               "seeds": list(FRESH_SEEDS), "model": os.path.basename(model)}
+        with open(os.path.join(args.out, "fresh.json"), "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res["fresh"]["learned"]), flush=True)
+        return
     if args.cmd in ("collect", "all"):
-        shapes = []
-        for r in range(args.rounds):
-            shapes += (sample_shapes(args.shapes, seed=4 + 3 * r) +
-                       sample_shapes(args.aligned_shapes, seed=5 + 3 * r, align=64) +
-                       sample_shapes(args.pow2_shapes, seed=6 + 3 * r, align=0))
-        if args.dense_shapes:
-            reg = dict(m_range=(256, 16384), n_range=(8192, 1048576))
-            shapes += (sample_shapes(args.dense_shapes // 2, seed=30, **reg) +
-                       sample_shapes(args.dense_shapes - args.dense_shapes // 2, seed=31, align=64, **reg))
+        shapes = collection_shapes(args.rounds, args.shapes, args.aligned_shapes, args.pow2_shapes, args.dense_shapes)
         collect(h, shapes, data, args.reps, args.time_budget)
     recs = load(data)
     tr, te = split(recs)

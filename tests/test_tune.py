@@ -76,3 +76,22 @@ def test_learned_pick_breaks_near_ties_by_bytes():
             {"feats": [0.0] * 12, "times": {"1": 1.0, "2": 1.0, "3": 1.0}},  # 3 best; 2 within, 1 not
             {"feats": [0.0] * 12, "times": {"1": 1.0, "3": 1.0}}]  # 3 best; 1 is 0.6 below
     assert T.pick_learned(Net(), recs) == [3, 2, 3]
+
+
+def test_fresh_shapes_are_drawn_by_no_training_round(lib_built):
+    # the fresh check judges the model on shapes it never saw: the shipped
+    # model's collection (two rounds of 6000 ragged, 3000 aligned and 1000
+    # power-of-two shapes, seeds 4-9, and 6000 dense shapes, seeds 30 and 31)
+    # re-derived here, against the fresh draw
+    reg = dict(m_range=(256, 16384), n_range=(8192, 1048576))
+    train = set()
+    for r in range(2):
+        train |= {T.key_of(s) for s in T.sample_shapes(6000, seed=4 + 3 * r) +
+                  T.sample_shapes(3000, seed=5 + 3 * r, align=64) + T.sample_shapes(1000, seed=6 + 3 * r, align=0)}
+    train |= {T.key_of(s) for s in T.sample_shapes(3000, seed=30, **reg) +
+              T.sample_shapes(3000, seed=31, align=64, **reg)}
+    assert len(train) == 25924  # the distinct shapes of the shipped model's dataset
+    fresh = T.fresh_shapes(1000)
+    keys = {T.key_of(s) for s in fresh}
+    assert len(fresh) >= 990 and len(keys) == len(fresh) and not keys & train
+    assert sum(s["N"] % 64 == 0 for s in fresh) >= 495
