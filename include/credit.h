@@ -78,7 +78,17 @@
 extern "C" {
 #endif
 
-typedef enum {
+/* The enumerations are int-sized in both languages.  Compiled as C++ they
+ * take int as their fixed underlying type, so any int a caller passes (ctypes
+ * passes plain ints) is a value of the type, and an out-of-range one is
+ * rejected with CREDIT_ERR_INVALID_ARG rather than being undefined. */
+#ifdef __cplusplus
+#define CREDIT_ENUM enum : int
+#else
+#define CREDIT_ENUM enum
+#endif
+
+typedef CREDIT_ENUM {
     CREDIT_OK = 0,
     CREDIT_ERR_INVALID_ARG = 1,
     CREDIT_ERR_UNSUPPORTED = 2, /* plan illegal for this shape / dtype        */
@@ -88,14 +98,14 @@ typedef enum {
     CREDIT_ERR_MODEL = 6        /* selector model missing, corrupt or foreign  */
 } credit_status_t;
 
-typedef enum { CREDIT_F32 = 0, CREDIT_BF16 = 1, CREDIT_FP8_E4M3 = 2 } credit_dtype_t;
+typedef CREDIT_ENUM { CREDIT_F32 = 0, CREDIT_BF16 = 1, CREDIT_FP8_E4M3 = 2 } credit_dtype_t;
 /* Operators.  The first three exist in both directions; the others are the
  * remaining reduction-reuse workloads of the paper's evaluation suite
  * (Sec. IV-A) and exist in one direction each: SOFTMAX_LOGITS, PEARSON and
  * WVAR backward only, the two QUANT operators and LAYERNORM_FP8_OUT forward
  * only.  Where a call
  * names an (operator, direction) pair, any other pair is CREDIT_ERR_INVALID_ARG. */
-typedef enum {
+typedef CREDIT_ENUM {
     CREDIT_SOFTMAX = 0,
     CREDIT_LAYERNORM = 1,
     CREDIT_RMSNORM = 2,
@@ -106,9 +116,9 @@ typedef enum {
     CREDIT_WVAR = 7,           /* weighted variance of a row                                     */
     CREDIT_LAYERNORM_FP8_OUT = 8 /* LayerNorm forward fused with row-wise e4m3 quantisation      */
 } credit_op_t;
-typedef enum { CREDIT_FWD = 0, CREDIT_BWD = 1 } credit_dir_t;
-typedef enum { CREDIT_TWO_PASS = 0, CREDIT_ROW_RESIDENT = 1, CREDIT_SPLIT_ROW = 2 } credit_variant_t;
-typedef enum {
+typedef CREDIT_ENUM { CREDIT_FWD = 0, CREDIT_BWD = 1 } credit_dir_t;
+typedef CREDIT_ENUM { CREDIT_TWO_PASS = 0, CREDIT_ROW_RESIDENT = 1, CREDIT_SPLIT_ROW = 2 } credit_variant_t;
+typedef CREDIT_ENUM {
     CREDIT_SEL_LEARNED = 0,    /* MLP over shape features; falls back to ANALYTIC   */
     CREDIT_SEL_ANALYTIC = 1,   /* Eq. (9) with one timing of the baseline (Eq. (7)) */
     CREDIT_SEL_EXHAUSTIVE = 2, /* time every legal plan, keep the fastest           */
@@ -140,7 +150,12 @@ const char *credit_version(void);
  * fixed | peak) sets the selector; CREDIT_FORCE_PLAN (two_pass | resident |
  * split:<k>) is used by calls with plan == NULL wherever it is legal for the
  * shape (elsewhere the selector decides); CREDIT_SPIN_LIMIT sets the split-row
- * wait bound.  Unrecognised values are ignored. */
+ * wait bound; CREDIT_CHECKED=1 makes every operator call wait for its launches
+ * and return CREDIT_ERR_TIMEOUT itself when an exchange wait expired (calls on
+ * a capturing stream are not waited on); CREDIT_LOG (stderr or a file path,
+ * appended) writes one JSON line per operator call: operator, dtype, M, N,
+ * plan, whether the caller gave it, the selector, launch geometry and status.
+ * Unrecognised values are ignored. */
 credit_status_t credit_create(int device, credit_handle_t *h);
 credit_status_t credit_destroy(credit_handle_t h);
 
@@ -484,7 +499,7 @@ credit_status_t credit_load_model(credit_handle_t h, const char *path);
 /* ------------------------------------------------------------- diagnostics */
 
 /* Handle options. */
-typedef enum {
+typedef CREDIT_ENUM {
     CREDIT_OPT_SPIN_LIMIT = 0,  /* poll iterations before an exchange wait gives up */
     CREDIT_OPT_TEST_DROP_PUBLISH = 1, /* test only: member 1 of each row group skips
                                          publishing its partials (forces the timeout

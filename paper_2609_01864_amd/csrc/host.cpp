@@ -254,6 +254,11 @@ struct credit_handle_s {
     } cal;
     int64_t max_groups = 0;
     int rows_opt = 0;  // rows per workgroup of norm-forward plans (0: the library's rule)
+    // CREDIT_CHECKED: every operator call waits for its launches and reports
+    // an expired exchange wait itself; CREDIT_LOG: one JSON line per call
+    bool checked = false;
+    FILE *log = nullptr;
+    bool log_owned = false;
     // private memory (bytes per lane) of the row-resident / split-row
     // instances, and for those that use it the workgroups per CU verified
     // co-resident at handle creation (0: none)
@@ -613,6 +618,45 @@ credit_status_t issue(credit_handle_t h, const OpCall &c, const Launch &L, void 
 
 // `host_pick`: with plan == NULL and no cached plan, take the fixed rule
 // (host arithmetic) instead of running the network on the device.
+// Checked mode: wait for the call's launches and read the error flag, so an
+// expired exchange wait is the call's own status.  A capturing stream cannot
+// be waited on; its launches are checked when the graph is replayed, through
+// credit_check_errors.
+credit_status_t checked_wait(credit_handle_t h, hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return CREDIT_ERR_HIP;
+    if (cs != hipStreamCaptureStatusNone) return CREDIT_OK;
+    if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return CREDIT_ERR_HIP;
+    unsigned flag = 0;
+    if (hipMemcpy(&flag, h->errflag, 4, hipMemcpyDeviceToHost) != hipSuccess) return CREDIT_ERR_HIP;
+    if (flag == 0) return CREDIT_OK;
+    if (hipMemset(h->errflag, 0, 4) != hipSuccess) return CREDIT_ERR_HIP;
+    return CREDIT_ERR_TIMEOUT;
+}
+
+// One JSON line per operator call: the operator, the shape, the plan, whether
+// the caller gave it (else the handle's selector, or CREDIT_FORCE_PLAN, chose
+// it), the launch geometry and the call's status.
+void log_call(credit_handle_t h, const OpCall &c, credit_plan_t p, bool given, const Launch &L,
+              credit_status_t st) {
+    static const char *ops[] = {"softmax_fwd", "layernorm_fwd", "rmsnorm_fwd", "softmax_bwd", "layernorm_bwd",
+                                "rmsnorm_bwd", "softmax_logits_bwd", "quant_int8", "quant_fp8", "pearson_bwd",
+                                "wvar_bwd", "layernorm_fwd_fp8_out"};
+    static const char *dts[] = {"f32", "bf16", "fp8"};
+    static const char *sels[] = {"learned", "analytic", "exhaustive", "fixed", "peak", "learned_timed"};
+    const credit_selector_t sel =
+        h->selector_set ? h->selector : (h->has_model ? CREDIT_SEL_LEARNED : CREDIT_SEL_FIXED);
+    const bool forced = !given && h->force_set && p.variant == h->force_plan.variant && p.k == h->force_plan.k;
+    std::fprintf(h->log,
+                 "{\"op\": \"%s\", \"dtype\": \"%s\", \"M\": %lld, \"N\": %lld, \"plan\": [%d, %d], "
+                 "\"plan_given\": %s, \"forced\": %s, \"selector\": \"%s\", \"grid\": %d, \"per_cu\": %d, "
+                 "\"vpt\": %d, \"rows\": %d, \"checked\": %s, \"status\": \"%s\"}\n",
+                 ops[c.k_op], dts[c.dt], (long long)c.M, (long long)c.N, (int)p.variant, (int)p.k,
+                 given ? "true" : "false", forced ? "true" : "false", sels[(int)sel], L.grid, L.per_cu, L.vpt, L.rows,
+                 h->checked ? "true" : "false", credit_status_string(st));
+    std::fflush(h->log);
+}
+
 credit_status_t run_op(credit_handle_t h, const OpCall &c, const credit_plan_t *plan, void *ws, size_t ws_bytes,
                        void *stream, bool recompute, bool host_pick = false) {
     if (!h) return CREDIT_ERR_INVALID_ARG;
@@ -652,9 +696,11 @@ credit_status_t run_op(credit_handle_t h, const OpCall &c, const credit_plan_t *
     Launch L;
     std::lock_guard<std::recursive_mutex> g(h->lock);
     credit_status_t st = resolve(h, c.k_op, c.dt, c.M, c.N, p, recompute, L);
-    if (st != CREDIT_OK) return st;
-    if (!ws || ws_bytes < L.ws_bytes) return CREDIT_ERR_WORKSPACE;
-    return issue(h, c, L, ws, (hipStream_t)stream, recompute);
+    if (st == CREDIT_OK && (!ws || ws_bytes < L.ws_bytes)) st = CREDIT_ERR_WORKSPACE;
+    if (st == CREDIT_OK) st = issue(h, c, L, ws, (hipStream_t)stream, recompute);
+    if (st == CREDIT_OK && h->checked) st = checked_wait(h, (hipStream_t)stream);
+    if (h->log) log_call(h, c, p, plan != nullptr, L, st);
+    return st;
 }
 
 // ------------------------------------------------------------ static analysis
@@ -1446,6 +1492,10 @@ const char *credit_version(void) { return "credit-mi355x 0.1.0 (gfx950)"; }
 //   CREDIT_FORCE_PLAN  two_pass | resident | split:<k>   (calls with plan == NULL
 //                      use it where it is legal for the shape)
 //   CREDIT_SPIN_LIMIT  polls before a split-row wait gives up
+//   CREDIT_CHECKED     1: operator calls wait for their launches and return
+//                      CREDIT_ERR_TIMEOUT themselves
+//   CREDIT_LOG         stderr | <path>: one JSON line per operator call
+//                      (appended; a path that cannot be opened is ignored)
 // Unrecognised values are ignored.
 static void read_env(credit_handle_t h) {
     if (const char *v = std::getenv("CREDIT_SELECTOR")) {
@@ -1477,6 +1527,16 @@ static void read_env(credit_handle_t h) {
     if (const char *v = std::getenv("CREDIT_SPIN_LIMIT")) {
         const long long n = std::atoll(v);
         if (n > 0) h->spin_limit = n;
+    }
+    if (const char *v = std::getenv("CREDIT_CHECKED")) h->checked = std::string(v) == "1";
+    if (const char *v = std::getenv("CREDIT_LOG")) {
+        const std::string s(v);
+        if (s == "stderr") {
+            h->log = stderr;
+        } else if (!s.empty()) {
+            h->log = std::fopen(v, "a");
+            h->log_owned = h->log != nullptr;
+        }
     }
 }
 
@@ -1550,6 +1610,7 @@ credit_status_t credit_destroy(credit_handle_t h) {
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     if (h->stream) (void)hipStreamDestroy(h->stream);
+    if (h->log_owned) std::fclose(h->log);
     delete h;
     return CREDIT_OK;
 }

@@ -1,5 +1,8 @@
 """Environment configuration read when a handle is created:
-CREDIT_FORCE_PLAN, CREDIT_SELECTOR, CREDIT_SPIN_LIMIT."""
+CREDIT_FORCE_PLAN, CREDIT_SELECTOR, CREDIT_SPIN_LIMIT, CREDIT_CHECKED and
+CREDIT_LOG."""
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -66,6 +69,56 @@ def test_spin_limit_from_environment(lib_built, monkeypatch):
         assert h.check_errors() == C.OK
     finally:
         h.close()
+
+
+def test_checked_mode_reports_the_timeout_from_the_call(lib_built, monkeypatch):
+    # CREDIT_CHECKED=1: the call itself waits and returns CREDIT_ERR_TIMEOUT
+    # (raised by the binding) when an exchange wait expired; the flag is then
+    # clear, and a normal call afterwards succeeds
+    monkeypatch.setenv("CREDIT_CHECKED", "1")
+    h = C.Handle(0, load_default_model=False)
+    try:
+        x = torch.randn(8, 4096, device="cuda")
+        C.softmax_fwd(x, p=C.plan("split", 2), h=h)
+        h.set_option(C.OPT_SPIN_LIMIT, 64)
+        h.set_option(C.OPT_TEST_DROP_PUBLISH, 1)
+        print("[config] forced timeout in checked mode", flush=True)
+        with pytest.raises(C.CreditError) as e:
+            C.softmax_fwd(x, p=C.plan("split", 2), h=h)
+        assert e.value.status == C.ERR_TIMEOUT
+        assert h.check_errors() == C.OK
+        h.set_option(C.OPT_TEST_DROP_PUBLISH, 0)
+        h.set_option(C.OPT_SPIN_LIMIT, 1 << 22)
+        y, _ = C.softmax_fwd(x, p=C.plan("split", 2), h=h)
+        ref = torch.softmax(x.double().cpu(), dim=1)
+        assert torch.max(torch.abs(y.double().cpu() - ref)).item() < 1e-6
+    finally:
+        h.close()
+
+
+def test_call_log_has_one_record_per_call(lib_built, monkeypatch, tmp_path):
+    path = tmp_path / "calls.jsonl"
+    monkeypatch.setenv("CREDIT_LOG", str(path))
+    monkeypatch.setenv("CREDIT_SELECTOR", "fixed")
+    h = C.Handle(0, load_default_model=False)
+    try:
+        x = torch.randn(64, 20000, device="cuda")
+        g = torch.rand(20000, device="cuda") + 0.5
+        C.rmsnorm_fwd(x, g, 1e-5, p=C.plan("split", 4), h=h)
+        C.rmsnorm_fwd(x, g, 1e-5, h=h)
+        fixed, _ = h.select(C.RMSNORM, C.FWD, C.F32, 64, 20000)
+        torch.cuda.synchronize()
+    finally:
+        h.close()
+    recs = [json.loads(line) for line in path.read_text().splitlines()]
+    assert len(recs) == 2  # operator calls only (not select)
+    a, b = recs
+    assert (a["op"], a["dtype"], a["M"], a["N"]) == ("rmsnorm_fwd", "f32", 64, 20000)
+    assert a["plan"] == [C.SPLIT_ROW, 4] and a["plan_given"] and not a["forced"]
+    assert a["status"] == "CREDIT_OK" and a["checked"] is False
+    assert a["grid"] > 0 and a["grid"] % 4 == 0 and a["vpt"] >= 1 and a["per_cu"] >= 1
+    assert not b["plan_given"] and b["selector"] == "fixed" and b["status"] == "CREDIT_OK"
+    assert b["plan"] == list(fixed.as_tuple())
 
 
 def test_register_model_is_a_lower_bound_of_runtime_occupancy(lib_built):
