@@ -96,6 +96,32 @@ def test_checked_mode_reports_the_timeout_from_the_call(lib_built, monkeypatch):
         h.close()
 
 
+def test_checked_mode_records_into_a_graph(lib_built, monkeypatch):
+    # a capturing stream is not waited on: the call records normally, and
+    # every replay is checked through credit_check_errors
+    monkeypatch.setenv("CREDIT_CHECKED", "1")
+    h = C.Handle(0, load_default_model=False)
+    side = torch.cuda.Stream()
+    try:
+        x = torch.randn(24, 30000, device="cuda")
+        with torch.cuda.stream(side):
+            C.softmax_fwd(x, p=C.plan("split", 4), h=h)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            y, _ = C.softmax_fwd(x, p=C.plan("split", 4), h=h)
+        for rep in range(3):
+            x.copy_(torch.randn(24, 30000, device="cuda") * (1 + rep))
+            print(f"[config] checked-mode replay {rep}", flush=True)
+            graph.replay()
+            torch.cuda.synchronize()
+            assert h.check_errors() == C.OK
+            ref = torch.softmax(x.double().cpu(), dim=1)
+            assert torch.max(torch.abs(y.double().cpu() - ref)).item() < 1e-6
+    finally:
+        h.close()
+
+
 def test_call_log_has_one_record_per_call(lib_built, monkeypatch, tmp_path):
     path = tmp_path / "calls.jsonl"
     monkeypatch.setenv("CREDIT_LOG", str(path))
