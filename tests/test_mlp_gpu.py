@@ -89,8 +89,12 @@ def test_model_file_round_trip_and_rejection(gpu_handle, tmp_path):
 
 
 def test_timed_learned_selector_keeps_the_faster_of_the_two_best(gpu_handle):
-    # the shipped model's two highest-scoring legal plans are timed once; the
-    # pick is one of them, and the faster one by the library's own timing
+    # the untimed pick is the tie rule's (among legal plans within 0.5 of the
+    # best logit, the one moving the fewest bytes); the timed selector times
+    # the shipped model's two highest-scoring legal plans once and keeps one
+    # of them, the faster by the library's own timing
+    from paper_2609_01864_amd import tune as T
+
     h = C.Handle(0)
     try:
         assert h.model_loaded
@@ -100,8 +104,10 @@ def test_timed_learned_selector_keeps_the_faster_of_the_two_best(gpu_handle):
         lg = h.mlp_predict(f[None, :])[0]
         legal = [c for c in range(NC) if h.plan_legal(op, C.FWD, C.F32, M, N, C.plan_of_class(c))]
         top2 = sorted(legal, key=lambda c: -lg[c])[:2]
+        best = max(lg[c] for c in legal)
+        untimed = min((c for c in legal if best - lg[c] <= T.TIE_LOGIT), key=T.bytes_rank)
         h.set_selector(C.SEL_LEARNED)
-        assert h.select(op, C.FWD, C.F32, M, N)[0].as_tuple() == C.plan_of_class(top2[0]).as_tuple()
+        assert h.select(op, C.FWD, C.F32, M, N)[0].as_tuple() == C.plan_of_class(untimed).as_tuple()
         h.set_selector(C.SEL_LEARNED_TIMED)
         p, pred = h.select(op, C.FWD, C.F32, M, N)
         assert p.as_tuple() in [C.plan_of_class(c).as_tuple() for c in top2]
