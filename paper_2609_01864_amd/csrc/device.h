@@ -14,6 +14,7 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kFp8Max = 448.0f;
+constexpr float kLog2Fp8Max = 8.807354922057604f;  // log2(448)
 constexpr int kBlock = kBlockThreads;  // one wave per SIMD
 
 template <int DT> struct Io;

@@ -493,13 +493,18 @@ __device__ __forceinline__ void row_loop(const RowArgs &a, int c, int grp, const
                     ST(j, encode<DT>(y, 1.f));
                 }
             } else {
+                // FP8: 448 * 2^(q K - c) is taken as one exponential, 2^(q K + log2 448 - c),
+                // saving a multiply per element (outputs below 2^-126 of the largest
+                // are 0 either way, far below the smallest e4m3 code)
+                const float cs8 = kLog2Fp8Max - cmax;
                 fresh();
 #pragma unroll
                 for (int j = 0; j < VPT; ++j) {
                     float q[EPV], y[EPV];
                     decode<DT>(d0[j], q, 1.f);
 #pragma unroll
-                    for (int i = 0; i < EPV; ++i) y[i] = fast_exp2(fmaf(q[i], K, csh)) * omuls;
+                    for (int i = 0; i < EPV; ++i)
+                        y[i] = FP8 ? fast_exp2(fmaf(q[i], K, cs8)) : fast_exp2(fmaf(q[i], K, csh)) * omuls;
                     ST(j, encode<DT>(y, 1.f));
                 }
             }
