@@ -38,11 +38,14 @@ def log(msg):
 
 
 def source_hash() -> str:
+    """Hash of the kernel sources and of the build script (its compiler flags
+    and per-file schedules shape the kernels as much as the sources do)."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2609_01864_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+    pkg = os.path.join(ROOT, "paper_2609_01864_amd")
+    csrc = os.path.join(pkg, "csrc")
+    for path in [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))] + [os.path.join(pkg, "build.py")]:
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode() + fh.read())
     return h.hexdigest()[:16]
 
 

@@ -33,15 +33,20 @@ FLAGS = [
 
 SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
-# Instruction scheduling of the FP32 / BF16 forward row kernels: the
-# scheduler's ILP-maximising strategy, measured on MI355X (cold cache, median
-# of 15): LayerNorm FP32 N = 524288 823 -> 771 us, N = 131072 201 -> 194 us,
-# softmax FP32 4096 x 65536 376 -> 365 us, FP8 softmax 478 -> 466 us; the
-# other forward shapes within +-1%.  The backward kernels and the FP8
-# LayerNorm / RMSNorm forward (+1% / +2.4% with it, and two FP8 RMSNorm slices
-# spill) keep the default schedule.
-FILE_FLAGS = {src: ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
-              for src in ("inst_softmax_fwd.hip", "inst_ln_fwd.hip", "inst_rms_fwd.hip")}
+# Instruction scheduling of the forward row kernels, measured on MI355X (cold
+# cache, median of 15).  The scheduler's ILP-maximising strategy against the
+# default: LayerNorm FP32 N = 524288 823 -> 771 us, N = 131072 201 -> 194 us,
+# softmax FP32 4096 x 65536 376 -> 365 us, FP8 softmax 478 -> 466 us.  Its
+# iterative ILP strategy, later, against the ILP-maximising one: LayerNorm
+# FP32 N = 524288 759 -> 745 us, the other LayerNorm shapes within +-1%, so
+# the FP32 / BF16 LayerNorm instances take it; for the softmax it spilled
+# the LDS-slice instances (up to 2.3 KiB per lane) and slowed FP8 rows by
+# 3.5%, and RMSNorm gained nothing, so those keep the ILP-maximising one.
+# The backward kernels and the FP8 LayerNorm / RMSNorm forward (+1% / +2.4%
+# with max-ilp, and two FP8 RMSNorm slices spill) keep the default schedule.
+_MAX_ILP = ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
+_ITER_ILP = ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]
+FILE_FLAGS = {"inst_ln_fwd.hip": _ITER_ILP, "inst_softmax_fwd.hip": _MAX_ILP, "inst_rms_fwd.hip": _MAX_ILP}
 
 
 _REMARK = re.compile(r"remark:\s+(Function Name|VGPRs|AGPRs|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]"

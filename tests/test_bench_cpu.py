@@ -32,6 +32,8 @@ def test_traffic_used_only_for_the_sources_it_was_taken_from(bench, tmp_path, mo
     csrc = tmp_path / "paper_2609_01864_amd" / "csrc"
     csrc.mkdir(parents=True)
     (csrc / "a.hip").write_text("kernel one\n")
+    build_py = tmp_path / "paper_2609_01864_amd" / "build.py"
+    build_py.write_text("FLAGS = ['-O3']\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     key = "layernorm_fwd:N=524288:plan=2,16"
     assert bench.traffic_for(key) is None  # no profile
@@ -41,6 +43,10 @@ def test_traffic_used_only_for_the_sources_it_was_taken_from(bench, tmp_path, mo
     assert bench.traffic_for(key) == 123
     assert bench.traffic_for("rmsnorm_fwd:N=8192:plan=1,1") is None  # no entry for that launch
     (csrc / "a.hip").write_text("kernel two\n")  # the kernel changed since the counters were taken
+    assert bench.traffic_for(key) is None
+    (csrc / "a.hip").write_text("kernel one\n")
+    assert bench.traffic_for(key) == 123
+    build_py.write_text("FLAGS = ['-O2']\n")  # so did its compiler flags
     assert bench.traffic_for(key) is None
     prof.write_text("{not json")
     assert bench.traffic_for(key) is None

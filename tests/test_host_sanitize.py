@@ -6,7 +6,6 @@ arguments: byte accounting, shape features, plan classes and geometry of
 every (operator, direction, dtype, plan) on a grid of shapes, the register
 model of every instance, the Eq. (9) model, status strings, argument checks
 and handle creation.  No out-of-bounds access, no undefined operation."""
-import glob
 import os
 import subprocess
 
@@ -21,8 +20,8 @@ SAN = "-Xarch_host -fsanitize=address,undefined -Xarch_host -fno-sanitize-recove
 
 @pytest.mark.skipif(not os.path.exists(CLANG), reason="ROCm clang not available")
 def test_host_code_under_asan_and_ubsan(lib_built, tmp_path):
-    objs = [o for o in sorted(glob.glob(os.path.join(B.OUT_DIR, "*.o"))) if os.path.basename(o) != "host.o"]
-    assert len(objs) == len(B.SOURCES) - 1, "the regular build's objects are needed"
+    objs = [os.path.join(B.OUT_DIR, os.path.splitext(src)[0] + ".o") for src in B.SOURCES if src != "host.cpp"]
+    assert all(os.path.exists(o) for o in objs), "the regular build's objects are needed"
     host = tmp_path / "host_san.o"
     cmd = [B.HIPCC, "-x", "hip", *B.FLAGS, *SAN, "-Xarch_host", "-fno-omit-frame-pointer", "-I", B.CSRC, "-c",
            os.path.join(B.CSRC, "host.cpp"), "-o", str(host)]
