@@ -481,7 +481,10 @@ credit_status_t credit_mlp_grad(credit_handle_t h, const float *feats, const flo
 /* Full-batch Adam training on the GPU (beta1 0.9, beta2 0.999, eps 1e-8) for
  * `epochs` steps from a seeded He initialisation (seed != 0) or from the
  * current parameters (seed == 0).  The standardization is computed from the
- * given features when seed != 0. */
+ * given features when seed != 0.  The handle keeps the Adam moments and step
+ * count: seed == 0 continues from them (they are zero after a seeded start,
+ * credit_mlp_set, or loading a model saved without them), so training split
+ * over calls, or resumed from a saved model, takes the same steps as one call. */
 credit_status_t credit_mlp_train(credit_handle_t h, const float *feats, const float *targets,
                                  const uint8_t *mask, int64_t n, int epochs, float lr,
                                  uint64_t seed, float *final_loss);
@@ -490,9 +493,13 @@ credit_status_t credit_mlp_train(credit_handle_t h, const float *feats, const fl
 credit_status_t credit_mlp_predict(credit_handle_t h, const float *feats, int64_t n,
                                    float *logits);
 
-/* Saves / loads the network with a header (format, arch, CU count, feature
- * schema); a foreign or corrupt file returns CREDIT_ERR_MODEL and leaves the
- * handle without a model. */
+/* Saves / loads the network with a header (format version, arch, CU count,
+ * feature schema, the library that wrote it, the plan classes in order), the
+ * standardization, the parameters and the Adam moments and step count (the
+ * training checkpoint; files of format 1, without them, load with zero
+ * moments); a foreign or corrupt file returns CREDIT_ERR_MODEL and leaves the
+ * handle without a model.  Values are written with 9 significant digits, so a
+ * saved and reloaded network is bit-identical. */
 credit_status_t credit_save_model(credit_handle_t h, const char *path);
 credit_status_t credit_load_model(credit_handle_t h, const char *path);
 

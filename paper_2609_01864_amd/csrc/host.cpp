@@ -282,6 +282,12 @@ struct credit_handle_s {
     std::vector<float> params = std::vector<float>(kMlpParams, 0.f);
     float mu[CREDIT_NUM_FEATURES] = {0};
     float sd[CREDIT_NUM_FEATURES] = {0};
+    // Adam state of the training that produced `params`: first and second
+    // moments and the steps taken (0: none, the moments are zero), kept so
+    // that training resumes, also from a saved model
+    std::vector<float> adam_m = std::vector<float>(kMlpParams, 0.f);
+    std::vector<float> adam_v = std::vector<float>(kMlpParams, 0.f);
+    int64_t adam_t = 0;
 };
 
 namespace {
@@ -2123,6 +2129,12 @@ credit_status_t credit_features(credit_op_t op, credit_dir_t dir, credit_dtype_t
 
 int64_t credit_mlp_num_params(void) { return kMlpParams; }
 
+static void reset_adam(credit_handle_t h) {
+    std::fill(h->adam_m.begin(), h->adam_m.end(), 0.f);
+    std::fill(h->adam_v.begin(), h->adam_v.end(), 0.f);
+    h->adam_t = 0;
+}
+
 credit_status_t credit_mlp_set(credit_handle_t h, const float *params, const float *mu, const float *sd) {
     if (!h || !params || !mu || !sd) return CREDIT_ERR_INVALID_ARG;
     std::lock_guard<std::recursive_mutex> g(h->lock);
@@ -2131,6 +2143,7 @@ credit_status_t credit_mlp_set(credit_handle_t h, const float *params, const flo
     std::memcpy(h->params.data(), params, kMlpParams * 4);
     std::memcpy(h->mu, mu, kF * 4);
     std::memcpy(h->sd, sd, kF * 4);
+    reset_adam(h);
     if (upload_infer(h) != CREDIT_OK) return CREDIT_ERR_HIP;
     h->has_model = true;
     h->plan_cache.clear();
@@ -2189,14 +2202,22 @@ credit_status_t credit_mlp_train(credit_handle_t h, const float *feats, const fl
             he(oW1, kH, kF);
             he(oW2, kH, kH);
             he(oW3, kC, kH);
+            reset_adam(h);
         }
         MlpDev d;
         if (!d.init(n) || !mlp_upload(h, d, feats, targets, mask)) return CREDIT_ERR_HIP;
-        if (hipMemset(d.m, 0, kMlpParams * 4) != hipSuccess || hipMemset(d.v, 0, kMlpParams * 4) != hipSuccess)
+        // Adam continues from the handle's moments and step count (zero after
+        // a seeded initialisation, credit_mlp_set or a model without them)
+        if (hipMemcpy(d.m, h->adam_m.data(), kMlpParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d.v, h->adam_v.data(), kMlpParams * 4, hipMemcpyHostToDevice) != hipSuccess)
             return CREDIT_ERR_HIP;
         const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
         int64_t np = kMlpParams;
-        double p1 = 1.0, p2 = 1.0;
+        double p1 = 1.0, p2 = 1.0;  // b1^t, b2^t by the same running products as the steps take
+        for (int64_t t = 0; t < h->adam_t; ++t) {
+            p1 *= b1;
+            p2 *= b2;
+        }
         for (int t = 1; t <= epochs; ++t) {
             if (mlp_forward(d, h->stream) != hipSuccess || mlp_backward(d, h->stream) != hipSuccess)
                 return CREDIT_ERR_HIP;
@@ -2210,8 +2231,11 @@ credit_status_t credit_mlp_train(credit_handle_t h, const float *feats, const fl
         // loss at the final parameters
         if (mlp_forward(d, h->stream) != hipSuccess || mlp_backward(d, h->stream) != hipSuccess) return CREDIT_ERR_HIP;
         if (hipStreamSynchronize(h->stream) != hipSuccess) return CREDIT_ERR_HIP;
-        if (hipMemcpy(h->params.data(), d.p, kMlpParams * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        if (hipMemcpy(h->params.data(), d.p, kMlpParams * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(h->adam_m.data(), d.m, kMlpParams * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(h->adam_v.data(), d.v, kMlpParams * 4, hipMemcpyDeviceToHost) != hipSuccess)
             return CREDIT_ERR_HIP;
+        h->adam_t += epochs;
         if (final_loss && hipMemcpy(final_loss, d.lmean, 4, hipMemcpyDeviceToHost) != hipSuccess)
             return CREDIT_ERR_HIP;
         if (upload_infer(h) != CREDIT_OK) return CREDIT_ERR_HIP;
@@ -2234,6 +2258,7 @@ credit_status_t credit_mlp_predict(credit_handle_t h, const float *feats, int64_
 }
 
 static const char *kSchema = "f12-h64-h64-c7-v5";
+static const char *kLibraryTag = "credit-mi355x-0.1.0";  // written into saved models (provenance)
 
 credit_status_t credit_save_model(credit_handle_t h, const char *path) {
     if (!h || !path) return CREDIT_ERR_INVALID_ARG;
@@ -2242,12 +2267,21 @@ credit_status_t credit_save_model(credit_handle_t h, const char *path) {
     FILE *f = std::fopen(path, "w");
     if (!f) return CREDIT_ERR_INVALID_ARG;
     std::string arch = h->arch.substr(0, h->arch.find(':'));
-    std::fprintf(f, "CREDIT-MLP 1\narch %s\ncus %d\nschema %s\nmu", arch.c_str(), h->cus, kSchema);
+    std::fprintf(f, "CREDIT-MLP 2\narch %s\ncus %d\nschema %s\nlibrary %s\nclasses", arch.c_str(), h->cus, kSchema,
+                 kLibraryTag);
+    for (int c = 0; c < kC; ++c) {
+        const credit_plan_t p = class_plan(c);
+        std::fprintf(f, " %d:%d", (int)p.variant, (int)p.k);
+    }
+    std::fprintf(f, "\nmu");
     for (int i = 0; i < kF; ++i) std::fprintf(f, " %.9g", h->mu[i]);
     std::fprintf(f, "\nsd");
     for (int i = 0; i < kF; ++i) std::fprintf(f, " %.9g", h->sd[i]);
     std::fprintf(f, "\nparams %d\n", kMlpParams);
     for (int i = 0; i < kMlpParams; ++i) std::fprintf(f, "%.9g\n", h->params[i]);
+    // Adam moments and step count, so that training resumes from the file
+    std::fprintf(f, "adam %lld %d\n", (long long)h->adam_t, kMlpParams);
+    for (int i = 0; i < kMlpParams; ++i) std::fprintf(f, "%.9g %.9g\n", h->adam_m[i], h->adam_v[i]);
     std::fprintf(f, "end\n");
     return std::fclose(f) == 0 ? CREDIT_OK : CREDIT_ERR_INVALID_ARG;
 }
@@ -2259,11 +2293,22 @@ credit_status_t credit_load_model(credit_handle_t h, const char *path) {
     h->plan_cache.clear();
     FILE *f = std::fopen(path, "r");
     if (!f) return CREDIT_ERR_MODEL;
-    char arch[64] = {0}, schema[64] = {0}, tag[16] = {0};
+    char arch[64] = {0}, schema[64] = {0}, tag[16] = {0}, library[64] = {0};
     int ver = 0, cus = 0, np = 0;
-    bool ok = std::fscanf(f, "CREDIT-MLP %d arch %63s cus %d schema %63s mu", &ver, arch, &cus, schema) == 4;
+    bool ok = std::fscanf(f, "CREDIT-MLP %d arch %63s cus %d schema %63s", &ver, arch, &cus, schema) == 4;
     std::string want = h->arch.substr(0, h->arch.find(':'));
-    ok = ok && ver == 1 && want == arch && cus == h->cus && std::strcmp(schema, kSchema) == 0;
+    ok = ok && (ver == 1 || ver == 2) && want == arch && cus == h->cus && std::strcmp(schema, kSchema) == 0;
+    if (ok && ver == 2) {
+        // the library that wrote it (provenance only) and the plan classes,
+        // which must be this library's
+        ok = std::fscanf(f, " library %63s classes", library) == 1;
+        for (int c = 0; ok && c < kC; ++c) {
+            int v = -1, k = -1;
+            const credit_plan_t p = class_plan(c);
+            ok = std::fscanf(f, " %d:%d", &v, &k) == 2 && v == (int)p.variant && k == (int)p.k;
+        }
+    }
+    ok = ok && std::fscanf(f, " mu") == 0;
     float mu[kF], sd[kF];
     for (int i = 0; ok && i < kF; ++i) ok = std::fscanf(f, "%f", &mu[i]) == 1;
     ok = ok && std::fscanf(f, " sd") == 0;
@@ -2271,12 +2316,24 @@ credit_status_t credit_load_model(credit_handle_t h, const char *path) {
     ok = ok && std::fscanf(f, " params %d", &np) == 1 && np == kMlpParams;
     std::vector<float> p(kMlpParams);
     for (int i = 0; ok && i < kMlpParams; ++i) ok = std::fscanf(f, "%f", &p[i]) == 1 && std::isfinite(p[i]);
+    std::vector<float> am(kMlpParams, 0.f), av(kMlpParams, 0.f);
+    long long at = 0;
+    if (ok && ver == 2) {
+        int na = -1;
+        ok = std::fscanf(f, " adam %lld %d", &at, &na) == 2 && at >= 0 && na == kMlpParams;
+        for (int i = 0; ok && i < kMlpParams; ++i)
+            ok = std::fscanf(f, "%f %f", &am[i], &av[i]) == 2 && std::isfinite(am[i]) && av[i] >= 0.f &&
+                 std::isfinite(av[i]);
+    }
     ok = ok && std::fscanf(f, "%15s", tag) == 1 && std::strcmp(tag, "end") == 0;
     std::fclose(f);
     if (!ok) return CREDIT_ERR_MODEL;
     std::memcpy(h->params.data(), p.data(), kMlpParams * 4);
     std::memcpy(h->mu, mu, sizeof(mu));
     std::memcpy(h->sd, sd, sizeof(sd));
+    h->adam_m = am;
+    h->adam_v = av;
+    h->adam_t = at;
     if (upload_infer(h) != CREDIT_OK) return CREDIT_ERR_HIP;
     h->has_model = true;
     return CREDIT_OK;

@@ -88,6 +88,40 @@ def test_model_file_round_trip_and_rejection(gpu_handle, tmp_path):
     # without a model the default selection falls back to the fixed rule
 
 
+def test_training_resumes_from_a_saved_checkpoint(lib_built, tmp_path):
+    # 24 epochs in one call, and 12 + save / load (parameters, standardization,
+    # Adam moments and step count in the file) + 12 on a fresh handle, take
+    # the same steps: bit-identical networks
+    _, _, _, feats, t, mask = _case(n=300, seed=5)
+    path = str(tmp_path / "ckpt.txt")
+    ha, hb, hc = (C.Handle(0, load_default_model=False) for _ in range(3))
+    try:
+        ha.mlp_train(feats, t, mask, epochs=24, lr=3e-3, seed=11)
+        hb.mlp_train(feats, t, mask, epochs=12, lr=3e-3, seed=11)
+        hb.save_model(path)
+        assert hc.load_model(path) == C.OK
+        hc.mlp_train(feats, t, mask, epochs=12, lr=3e-3, seed=0)
+        for a, c in zip(ha.mlp_get(), hc.mlp_get()):
+            assert np.array_equal(a, c)
+        # without the moments (a format-1 file) the continuation differs
+        txt = open(path).read()
+        head, _, _ = txt.partition("adam ")
+        v1 = head.replace("CREDIT-MLP 2", "CREDIT-MLP 1", 1)
+        v1 = v1[:v1.index("library ")] + v1[v1.index("mu "):] + "end\n"
+        open(path, "w").write(v1)
+        assert hc.load_model(path) == C.OK
+        hc.mlp_train(feats, t, mask, epochs=12, lr=3e-3, seed=0)
+        assert not np.array_equal(ha.mlp_get()[0], hc.mlp_get()[0])
+        # a file whose plan classes differ from the library's is refused
+        bad = txt.replace("classes 0:1 1:1 2:2", "classes 0:1 1:1 2:4", 1)
+        assert bad != txt
+        open(path, "w").write(bad)
+        assert hc.load_model(path) == C.ERR_MODEL
+    finally:
+        for h in (ha, hb, hc):
+            h.close()
+
+
 def test_timed_learned_selector_keeps_the_faster_of_the_two_best(gpu_handle):
     # the untimed pick is the tie rule's (among legal plans within 0.5 of the
     # best logit, the one moving the fewest bytes); the timed selector times
